@@ -1,0 +1,413 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Every test here checks the oracle against something other than itself: values
+printed in the paper (tests/golden/paper_values.json, each with its citation),
+closed forms, brute-force quadrature of the Galerkin definition (Lemma 3.1),
+independent derivations of the boundary rows, theorems on spectra and norms.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import assemble, fd, krylov, pc, precond, spectral
+from workloads import (config1, one_d_paper, small_2d, wedge_instance, point_source,
+                       sine_mode_fields, gaussian_source)
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+# ------------------------------------------------------------------ basis
+
+def test_basis_size_and_order():
+    for s, r in [(1, 5), (4, 3), (6, 3), (3, 8), (2, 4)]:
+        a = pc.multi_indices(s, r)
+        assert a.shape == (math.comb(s + r, s), s)          # eq. number_basis_polynomial
+        assert len({tuple(x) for x in a}) == a.shape[0]
+        deg = a.sum(1)
+        assert np.all(np.diff(deg) >= 0) and deg[0] == 0 and deg.max() == r
+    assert [tuple(x) for x in pc.multi_indices(2, 2)] == [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2)]
+
+
+def test_legendre_matches_numpy_legval():
+    x = np.linspace(-1, 1, 37)
+    phi = pc.orthonormal_legendre(9, x)
+    for n in range(10):
+        c = np.zeros(n + 1)
+        c[n] = 1.0
+        ref = np.polynomial.legendre.legval(x, c) * math.sqrt(2 * n + 1)
+        np.testing.assert_allclose(phi[n], ref, rtol=0, atol=1e-12)
+
+
+def _tensor_rule(s, npts):
+    x, w = np.polynomial.legendre.leggauss(npts)
+    w = w / 2
+    grids = np.meshgrid(*([x] * s), indexing="ij")
+    wg = np.meshgrid(*([w] * s), indexing="ij")
+    X = np.stack([g.ravel() for g in grids], 1)
+    W = np.prod(np.stack([g.ravel() for g in wg], 1), 1)
+    return X, W
+
+
+def _phi_multi(alpha, X, r):
+    out = np.ones((alpha.shape[0], X.shape[0]))
+    for l in range(alpha.shape[1]):
+        ph = pc.orthonormal_legendre(r, X[:, l])
+        out *= ph[alpha[:, l]]
+    return out
+
+
+def test_orthonormality_and_moments_bruteforce():
+    """E[ξ_a ξ_b φ_i φ_j] equals a direct s-dimensional tensor quadrature."""
+    s, r = 3, 3
+    alpha = pc.multi_indices(s, r)
+    E = pc.moment_tables(s, r)
+    X, W = _tensor_rule(s, r + 4)
+    Phi = _phi_multi(alpha, X, r)
+    np.testing.assert_allclose((Phi * W) @ Phi.T, np.eye(len(alpha)), atol=1e-13)
+    np.testing.assert_allclose(E[0, 0], np.eye(len(alpha)), atol=1e-15)      # G_0 = I
+    xi = np.concatenate([np.ones((X.shape[0], 1)), X], 1)
+    for a in range(s + 1):
+        for b in range(s + 1):
+            ref = (Phi * (W * xi[:, a] * xi[:, b])) @ Phi.T
+            np.testing.assert_allclose(E[a, b], ref, atol=1e-12)
+
+
+def test_jacobi_entry_closed_form():
+    """E[ξ φ_i φ_{i+1}] = (i+1)/sqrt((2i+1)(2i+3)) (three-term recurrence of orthonormal Legendre)."""
+    M = pc.univariate_moments(8, 2)
+    for i in range(8):
+        assert abs(M[1, i, i + 1] - (i + 1) / math.sqrt((2 * i + 1) * (2 * i + 3))) < 1e-14
+
+
+def test_lemma_A3_bandwidth():
+    """Lemma A.3: with k linear in one uniform ξ, B_ij = 0 for |i-j| > 1, C_ij = 0 for |i-j| > 2."""
+    inst = one_d_paper(20.0, 0.2, degree=6)
+    S = assemble.from_instance(inst)
+    P = S.P
+    for name, Mx, band in (("B", S.Bnd, 1), ("C", S.K, 2)):
+        Md = Mx.toarray()
+        for i in range(S.Q):
+            for j in range(S.Q):
+                blk = Md[i * P:(i + 1) * P, j * P:(j + 1) * P]
+                if abs(i - j) > band:
+                    assert not np.any(blk), (name, i, j)
+                elif abs(i - j) == band:
+                    assert np.any(blk), (name, i, j)
+
+
+# ------------------------------------------------------ FD building blocks
+
+def test_T_kernel_and_determinant_recursion():
+    """Theorem A.2: ker T = span{1}; det of leading blocks of h²T is 1 up to q+1 and 0 at q+2."""
+    n = 12
+    T = fd.T_absorbing(n, 1.0).toarray()
+    assert np.allclose(T @ np.ones(n), 0)
+    ev = np.linalg.eigvalsh(T)
+    assert abs(ev[0]) < 1e-12 and ev[1] > 1e-3
+    dets = [round(np.linalg.det(T[:j, :j])) for j in range(1, n + 1)]
+    assert dets == [1] * (n - 1) + [0]
+
+
+def test_1d_closed_form_second_order():
+    """Constant k, point source at 1/2: u = (i/2k) e^{ik|x-1/2|} solves -u''-k²u = δ with
+    u' ∓ iku = 0; the FD solution (Theorem A.2) converges with order two."""
+    k = 20.0
+    errs = []
+    for n in (201, 401, 801):
+        S = fd.deterministic_S(1, n, "absorbing", np.full(n, k))
+        _, w, _, _ = fd.laplacian(1, n, "absorbing")
+        U = spla.spsolve(S.tocsc(), w * point_source(n, 1))
+        x = np.linspace(0, 1, n)
+        u = 1j / (2 * k) * np.exp(1j * k * np.abs(x - 0.5))
+        errs.append(np.max(np.abs(U - u)) / np.max(np.abs(u)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.7 < r1 < 4.3 and 3.7 < r2 < 4.3, errs
+    assert errs[0] < 5e-3
+
+
+def test_2d_boundary_rows_by_ghost_points():
+    """Theorem A.4 rows equal the 5-point scheme with the ghost node eliminated by the
+    centred absorbing condition, weighted 1/2 on edges and 1/4 at corners."""
+    n = 9
+    h = 1.0 / (n - 1)
+    rng = np.random.default_rng(1)
+    k = 3.0 + rng.random(n * n)
+    u = rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)
+    S = fd.deterministic_S(2, n, "absorbing", k)
+    got = (S @ u).reshape(n, n)
+    U = u.reshape(n, n)
+    K = k.reshape(n, n)
+    ref = np.zeros((n, n), dtype=complex)
+    for j in range(n):
+        for i in range(n):
+            def val(ii, jj):
+                # ghost value from (u_{+1} - u_{-1})/(2h) = -ik u_0 along the outward normal
+                if ii < 0:
+                    return U[j, 1] + 2j * h * K[j, 0] * U[j, 0]
+                if ii > n - 1:
+                    return U[j, n - 2] + 2j * h * K[j, n - 1] * U[j, n - 1]
+                if jj < 0:
+                    return U[1, i] + 2j * h * K[0, i] * U[0, i]
+                if jj > n - 1:
+                    return U[n - 2, i] + 2j * h * K[n - 1, i] * U[n - 1, i]
+                return U[jj, ii]
+            pde = (4 * U[j, i] - val(i - 1, j) - val(i + 1, j) - val(i, j - 1) - val(i, j + 1)) / h ** 2 \
+                - K[j, i] ** 2 * U[j, i]
+            wx = 0.5 if i in (0, n - 1) else 1.0
+            wy = 0.5 if j in (0, n - 1) else 1.0
+            ref[j, i] = wx * wy * pde
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-9)
+
+
+# ----------------------------------------------------------- SG assembly
+
+def _galerkin_bruteforce(inst):
+    """Lemma 3.1 definition: A_ij = E[S(ξ) φ_i φ_j] by tensor quadrature over ξ."""
+    s, r = inst.s, inst.degree
+    alpha = pc.multi_indices(s, r)
+    X, W = _tensor_rule(s, r + 3)
+    Phi = _phi_multi(alpha, X, r)
+    A = None
+    for q in range(X.shape[0]):
+        kq = inst.k_fields[0] + X[q] @ inst.k_fields[1:]
+        Sq = fd.deterministic_S(inst.dim, inst.n, inst.bc, kq).toarray()
+        term = W[q] * np.kron(np.outer(Phi[:, q], Phi[:, q]), Sq)
+        A = term if A is None else A + term
+    return A
+
+
+@pytest.mark.parametrize("which", ["1d", "2d", "1d_dir"])
+def test_assembly_equals_galerkin_definition(which):
+    if which == "1d":
+        inst = one_d_paper(12.0, 0.3, degree=4)
+    elif which == "1d_dir":
+        inst = one_d_paper(12.0, 0.3, degree=3, bc="dirichlet")
+    else:
+        inst = small_2d(n=7, kbar=4.0, sigma=1.5, s=2, degree=3)
+    S = assemble.from_instance(inst)
+    ref = _galerkin_bruteforce(inst)
+    got = S.A.toarray()
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
+def test_complex_symmetric_not_hermitian():
+    """Lemma 3.1 / Theorem 3.3: A = A^T exactly (after exact-zero cleaning), A != A^H."""
+    for inst in (config1(), small_2d(n=17, s=3, degree=3)):
+        A = assemble.from_instance(inst).A
+        assert abs(A - A.T).max() == 0.0
+        assert abs(A - A.conj().T).max() > 0.0
+
+
+def test_sigma_zero_reduction():
+    """Corollary 3.2 / Remark 6.1: with σ=0, A = I⊗S(k̄): V_0 is the deterministic solution,
+    V_i = 0 for i >= 1, and A_0-preconditioned GMRES converges in one step."""
+    inst = small_2d(n=21, kbar=6.0, sigma=0.0, s=2, degree=2)
+    S = assemble.from_instance(inst)
+    x = precond.direct_solve(S)
+    Sd = fd.deterministic_S(2, inst.n, "absorbing", inst.k_fields[0])
+    u = spla.spsolve(Sd.tocsc(), S.b[: S.P])
+    np.testing.assert_allclose(x[: S.P], u, rtol=0, atol=1e-13 * np.abs(u).max())
+    assert np.max(np.abs(x[S.P:])) == 0.0
+    xg, info = krylov.gmres(lambda v: S.A @ v, S.b, precond.mean_value(S), restart=10, tol=1e-12)
+    assert info.iters == 1 and info.converged
+
+
+def test_nnz_table_construct_A():
+    g = GOLD["table_construct_A"]
+    for r, nb, size, nnz in zip(g["r"], g["n_basis"], g["size"], g["nnz"]):
+        S = assemble.from_instance(wedge_instance(r))
+        assert S.Q == nb and S.A.shape[0] == size and S.A.nnz == nnz, r
+
+
+# ------------------------------------------------------------- 1D numbers
+
+def _cond_set(kbar):
+    S = assemble.from_instance(one_d_paper(kbar))
+    A0 = sp.kron(sp.identity(S.Q), assemble.mean_block(S))
+    M0 = sp.kron(sp.identity(S.Q), assemble.mean_block(S, 1 + 0.5j))
+    M = S.csl(0.5)
+    return S, A0, M0, M
+
+
+def test_condition_numbers_k10():
+    g = GOLD["cond_1d"]
+    S, A0, M0, M = _cond_set(10.0)
+    assert abs(spectral.cond2_right_prec(S.A, M) - g["kappa_AMinv_k10"]) < 5e-5
+    assert abs(spectral.cond2_right_prec(S.A, A0) - g["kappa_AA0inv_k10"]) < 0.05
+
+
+def test_condition_numbers_k150_k200():
+    g = GOLD["cond_1d"]
+    S, A0, M0, M = _cond_set(150.0)
+    got = [spectral.cond2(X) for X in (S.A, A0, M, M0)]
+    ref = [g["k150"][k] for k in ("kappa_A", "kappa_A0", "kappa_M", "kappa_M0")]
+    assert [round(x) for x in got] == ref
+    S, A0, M0, M = _cond_set(200.0)
+    assert abs(spectral.cond2_right_prec(S.A, M) - g["kappa_AMinv_k200"]) < 5e-5
+    assert round(spectral.cond2_right_prec(S.A, A0)) == g["kappa_AA0inv_k200"]
+    assert spectral.cond2(M) <= g["kappa_M_max"]
+
+
+def test_norm_order_and_gmres_k50():
+    """Section 6.3: iteration counts, ||x - x'||_inf and the ∞-norm ordering at k̄ = 50."""
+    g = GOLD["gmres_1d_k50"]
+    S = assemble.from_instance(one_d_paper(50.0))
+    A = lambda v: S.A @ v
+    Ad = S.A
+    A0 = sp.kron(sp.identity(S.Q), assemble.mean_block(S))
+    M0 = sp.kron(sp.identity(S.Q), assemble.mean_block(S, 1 + 0.5j))
+    M = S.csl(0.5)
+    nrm = lambda X: abs(X).sum(1).max()
+    assert nrm(Ad - A0) < nrm(Ad - M) < nrm(Ad - M0)
+    xd = precond.direct_solve(S)
+    its = {}
+    for name, P in (("unpreconditioned", None), ("M", precond.full_csl(S, 0.5)),
+                    ("M0", precond.mean_csl(S, 0.5)), ("A0", precond.mean_value(S))):
+        x, info = krylov.gmres(A, S.b, P, restart=10 ** 6, tol=1e-12, maxit=5000)
+        assert info.converged
+        assert np.max(np.abs(x - xd)) <= g["solution_difference_max"]
+        its[name] = info.iters
+    # "about 250", "about 50", "about 25": within 10% (unpreconditioned within 15%)
+    assert abs(its["unpreconditioned"] - g["unpreconditioned"]) <= 0.15 * g["unpreconditioned"]
+    for k in ("M", "M0", "A0"):
+        assert abs(its[k] - g[k]) <= max(0.15 * g[k], 2), its
+    assert its["A0"] < its["M"] <= its["M0"] < its["unpreconditioned"]
+
+
+def test_iteration_ratios_k60_to_200():
+    """Section 6.3: percentages of unpreconditioned iterations for k̄ in [60, 200]; the paper's
+    sample points are not given and its percentages are rounded, so each ratio may exceed the
+    printed range by one percentage point."""
+    g = GOLD["gmres_iter_ratio_1d"]
+    for kbar in (60.0, 120.0, 200.0):
+        S = assemble.from_instance(one_d_paper(kbar))
+        A = lambda v: S.A @ v
+        n0 = krylov.gmres(A, S.b, None, restart=10 ** 6, tol=1e-12, maxit=5000)[1].iters
+        for name, P in (("M", precond.full_csl(S, 0.5)), ("M0", precond.mean_csl(S, 0.5)),
+                        ("A0", precond.mean_value(S))):
+            it = krylov.gmres(A, S.b, P, restart=10 ** 6, tol=1e-12, maxit=5000)[1].iters
+            lo, hi = g[name]
+            assert lo - 0.01 <= it / n0 <= hi + 0.01, (kbar, name, it, n0)
+
+
+# ------------------------------------------------------------- 2D numbers
+
+def _wedge_gmres(theta):
+    S = assemble.from_instance(wedge_instance(8, theta))
+    _, info = krylov.gmres(lambda v: S.A @ v, S.b, precond.mean_value(S), restart=200, tol=1e-8, maxit=200)
+    return info
+
+
+def test_wedge_r8_gmres_theta01():
+    info = _wedge_gmres(0.1)
+    assert info.converged and abs(info.iters - GOLD["gmres_2d_wedge_r8"]["theta_0.1"]) <= 1
+
+
+@pytest.mark.slow
+def test_wedge_r8_gmres_theta02():
+    info = _wedge_gmres(0.2)
+    assert info.converged and abs(info.iters - GOLD["gmres_2d_wedge_r8"]["theta_0.2"]) <= 3
+
+
+def test_stationary_iteration_wedge_r2():
+    """Section 7: the stationary iteration with B = A_0 converges at θ = 0.1, diverges at θ = 0.2."""
+    for theta, conv in ((0.1, True), (0.2, False)):
+        S = assemble.from_instance(wedge_instance(2, theta))
+        xd = precond.direct_solve(S)
+        _, errs = krylov.stationary(lambda v: S.A @ v, S.b, precond.mean_value(S), 40, xd)
+        if conv:
+            assert errs[-1] < 1e-8 and errs[-1] < errs[0]
+        else:
+            assert errs[-1] > errs[0]
+
+
+# ---------------------------------------------------------- theorems 4, 5
+
+def test_theorem_4_1_and_remark_4_2():
+    beta = 0.5
+    # absorbing: σ(AM^{-1}) in the closed disk |z-1/2| <= 1/2, outside |z-(1-iβ/2)| < β/2
+    for inst in (one_d_paper(15.0, 0.2, degree=3), small_2d(n=9, kbar=12.0, sigma=2.0, s=2, degree=2)):
+        S = assemble.from_instance(inst)
+        sig = spectral.eig_pencil(S.A, S.csl(beta))
+        assert spectral.disk_excess(sig) <= 1e-10
+        assert np.min(np.abs(sig - (1 - 0.5j * beta))) >= beta / 2 - 1e-10
+    # Dirichlet: on the circle |z-1/2| = 1/2
+    S = assemble.from_instance(one_d_paper(15.0, 0.2, degree=3, bc="dirichlet"))
+    sig = spectral.eig_pencil(S.A, S.csl(beta))
+    np.testing.assert_allclose(np.abs(sig - 0.5), 0.5, atol=1e-9)
+    assert np.max(np.abs(S.Bnd.toarray())) == 0.0
+
+
+def _deltaS_l2_frobenius(inst):
+    X, W = _tensor_rule(inst.s, inst.degree + 3)
+    S0 = fd.deterministic_S(inst.dim, inst.n, inst.bc, inst.k_fields[0]).toarray()
+    acc = 0.0
+    for q in range(X.shape[0]):
+        kq = inst.k_fields[0] + X[q] @ inst.k_fields[1:]
+        Sq = fd.deterministic_S(inst.dim, inst.n, inst.bc, kq).toarray()
+        acc += W[q] * np.linalg.norm(Sq - S0, "fro") ** 2
+    return math.sqrt(acc)
+
+
+def test_theorem_5_1_bound():
+    for inst in (one_d_paper(10.0, 0.1, degree=3), small_2d(n=7, kbar=5.0, sigma=0.5, s=2, degree=2)):
+        S = assemble.from_instance(inst)
+        lhs, rhs = spectral.frobenius_bound(S, assemble.mean_block(S), _deltaS_l2_frobenius(inst))
+        assert 0 < lhs <= rhs
+
+
+def test_theorem_5_3_order_theta():
+    """||A_0^{-1} A - I||_F = O(θ): the ratio to θ tends to a constant as θ → 0."""
+    ratios = []
+    for theta in (1e-2, 1e-3, 1e-4):
+        S = assemble.from_instance(one_d_paper(10.0, theta, degree=3))
+        A0i = np.kron(np.eye(S.Q), np.linalg.inv(assemble.mean_block(S).toarray()))
+        ratios.append(np.linalg.norm(A0i @ S.A.toarray() - np.eye(S.A.shape[0]), "fro") / theta)
+    assert abs(ratios[1] / ratios[2] - 1) < 1e-2 and abs(ratios[0] / ratios[1] - 1) < 0.1
+
+
+# --------------------------------------------------------------- Krylov
+
+def test_givens_rotation():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        a, b = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        c, s = krylov.givens(a, b)
+        G = np.array([[c, s], [-np.conj(s), c]])
+        out = G @ np.array([a, b])
+        assert abs(out[1]) < 1e-14 and np.allclose(G @ G.conj().T, np.eye(2))
+
+
+def test_full_gmres_equals_direct_and_arnoldi_relation():
+    inst = small_2d(n=9, s=2, degree=2)
+    S = assemble.from_instance(inst)
+    n = S.A.shape[0]
+    P = precond.mean_csl(S, 0.5)
+    x, info = krylov.gmres(lambda v: S.A @ v, S.b, P, restart=n, tol=1e-13, maxit=n, keep_basis=True)
+    xd = precond.direct_solve(S)
+    assert np.max(np.abs(x - xd)) < 1e-10 * np.max(np.abs(xd))
+    V, H = info.V, info.H
+    k = H.shape[1]
+    AZ = np.stack([S.A @ P(V[j]) for j in range(k)], 1)
+    assert np.linalg.norm(AZ - V[: k + 1].T @ H) < 1e-11 * np.linalg.norm(AZ)
+    # MGS keeps orthogonality to O(ε κ / relres): check the steps taken while relres > 1e-5
+    j = int(np.sum(np.array(info.hist) > 1e-5))
+    assert j >= 3
+    assert np.linalg.norm(V[:j].conj() @ V[:j].T - np.eye(j)) < 1e-8
+    assert np.all(np.diff(info.hist) <= 1e-15)   # residual estimate is monotone
+
+
+def test_restarted_and_flexible_variants_converge():
+    S = assemble.from_instance(config1())
+    A = lambda v: S.A @ v
+    xd = precond.direct_solve(S)
+    for P in (precond.mean_value(S), precond.mean_csl(S, 0.5)):
+        for flex in (False, True):
+            x, info = krylov.gmres(A, S.b, P, restart=30, tol=1e-10, maxit=2000, flexible=flex)
+            assert info.converged and info.relres_true <= 1e-10
+            assert np.max(np.abs(x - xd)) <= 1e-7 * np.max(np.abs(xd))
