@@ -1,0 +1,170 @@
+/*
+ * sg.h - C ABI of the MI355X stochastic-Galerkin Helmholtz solver.
+ *
+ * Problem (Section 3, eq. stochastic_helmholtz; absorbing BC eq. stochastic_bc_abs):
+ *     -Δu - k(x,ξ)² u = f  on (0,1)^d,  ∂_n u - i k u = 0 on the boundary,
+ *     k(x,ξ) = k_0(x) + Σ_{ℓ=1..s} ξ_ℓ k_ℓ(x),  ξ_ℓ ~ U[-1,1] independent (Section 2.2).
+ * Discretisation: finite differences (Theorems A.2 / A.4) and stochastic Galerkin
+ * projection on the orthonormal Legendre chaos of total degree <= r (Section 2.3,
+ * Section 3.1).  The result is the complex symmetric system
+ *     A V = b,   A = I_{m+1} ⊗ L - i[B_ij] - [C_ij]   (Theorem 3.3, Theorem A.4),
+ *     b = [w∘f; 0; ...; 0],
+ * with unknown V = [V_0; ...; V_m], m+1 = Q = (s+r)!/(s!r!) (eq. number_basis_polynomial).
+ *
+ * Vector layout: Q·n^d complex128 values, PC index slowest, then y, then x fastest
+ * (eq. LGS_from_FD_G; Theorem A.3 node ordering).  A complex value is two doubles
+ * (re, im), the layout of torch.complex128 and hipDoubleComplex.  All vector
+ * arguments are DEVICE pointers, 16-byte aligned, owned by the caller; the
+ * library never frees them.  Host pointers are marked "host".
+ *
+ * Errors: a negative return value is a hard failure (outputs undefined); a
+ * positive value means the result is valid but see the stats (not converged,
+ * fallback used).  No function aborts or throws; sg_last_error() returns a
+ * description of the last failure on the calling thread.
+ *
+ * Threading and streams: one handle serves one stream at a time.  Every call
+ * enqueues its work on the given stream; calls that return host results
+ * (sg_gmres, sg_fgmres, sg_cgs2, sg_norm) synchronise that stream.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } sg_c64;
+typedef struct sg_ctx* sg_handle;
+
+enum {
+    SG_OK = 0,
+    SG_ENOTCONV = 1,        /* maxit reached before tol: x is the last iterate   */
+    SG_FALLBACK_USED = 2,   /* learned correction was rejected, plain path used  */
+    SG_EINVAL = -1,         /* invalid argument                                   */
+    SG_ENOMEM = -2,         /* device or host allocation failed                   */
+    SG_EHIP = -3,           /* a HIP runtime call failed                          */
+    SG_EBREAKDOWN = -4,     /* Krylov breakdown with a non-solution               */
+    SG_ENONFINITE = -5,     /* NaN/Inf met in a residual or Hessenberg entry      */
+    SG_ESETUP = -6          /* setup validation failed (eigenfactors, pivots)     */
+};
+
+enum { SG_BC_ABSORBING = 0 };
+
+/* Preconditioners (Sections 4-5). */
+enum {
+    SG_PC_NONE = 0,         /* no preconditioner                                  */
+    SG_PC_MEAN = 1,         /* mean value A_0 = I ⊗ S(ξ̄)  (Section 5, eq. bar_A)   */
+    SG_PC_CSL_MEAN = 2,     /* mean CSL   M_0 = I ⊗ S_β(ξ̄), k̄² → (1+iβ)k̄² (eq. M) */
+    SG_PC_MEAN_NET = 3      /* A_0 followed by the learned correction (sg_net_*)  */
+};
+
+/* Arithmetic of the preconditioner's dense transforms; the outer operator,
+ * orthogonalisation, least squares and true residual are always FP64. */
+enum { SG_PREC_F64 = 0, SG_PREC_F32 = 1, SG_PREC_BF16X3 = 2 };
+
+typedef struct {
+    int dim;                  /* 1 or 2                                                     */
+    int n;                    /* nodes per side including the boundary (n = q+2 >= 3),
+                                 h = 1/(n-1)  (grids grid_1d / grid_2d)                     */
+    int bc;                   /* SG_BC_ABSORBING                                            */
+    int s;                    /* number of random variables, 1..8                          */
+    int degree;               /* total PC degree r, 0..8                                   */
+    const double* k_fields;   /* host, (s+1)·n^dim doubles: k_0, ..., k_s at the nodes,
+                                 x fastest (eq. random_wavenumber)                          */
+    double k_mean;            /* the mean wavenumber k̄: every entry of k_0 must equal it
+                                 (the preconditioners' block solve needs constant k̄)       */
+    double csl_beta;          /* β of the CSL shift (Section 4, eq. shifted_helmholtz)      */
+} sg_problem;
+
+typedef struct {
+    int restart;              /* m of GMRES(m), 1..512                                      */
+    int maxit;                /* cap on the total number of inner iterations                */
+    int precond;              /* SG_PC_*                                                    */
+    int precision;            /* SG_PREC_* for the preconditioner                           */
+    double tol;               /* target of the true relative residual ||b-Ax||_2/||b||_2   */
+    int x0_zero;              /* 1: start from x = 0; 0: x holds the initial guess          */
+    double* hist;             /* host, optional: residual estimate after each iteration     */
+    int hist_cap;             /* capacity of hist                                           */
+} sg_solve_opts;
+
+typedef struct {
+    int iters;                /* inner iterations performed                                 */
+    int restarts;             /* completed cycles                                           */
+    int converged;            /* 1 if the true relative residual <= tol                     */
+    int fallback;             /* 1 if the learned correction was switched off               */
+    double relres_true;       /* final ||b-Ax||_2/||b||_2 recomputed in FP64                */
+    double relres_est;        /* final Arnoldi estimate |g_{j+1}|/||b||                     */
+    double t_setup, t_precond, t_matvec, t_orth, t_total;   /* milliseconds              */
+} sg_solve_stats;
+
+/* Build the operator for one problem: basis, triple-product tables, coefficient
+ * fields, eigenfactors of the 1D mean operator and pivoted tridiagonal factors
+ * (host FP64, validated), then upload to the current device.  *out owns all of it. */
+int  sg_setup(const sg_problem* prob, hipStream_t stream, sg_handle* out);
+void sg_destroy(sg_handle h);
+
+/* Q (number of PC coefficients) and the multi-index table: multi_index may be NULL,
+ * else host, Q·s ints, row i = exponents of φ_i (graded order, Section 2.3). */
+int  sg_basis(sg_handle h, int* Q, int* multi_index);
+/* Unknown count Q·n^dim. */
+long long sg_size(sg_handle h);
+
+/* b = [w∘f; 0; ...; 0] with the boundary weights of Theorems A.2 / A.4;
+ * f_host: host, n^dim doubles; b_dev: device, Q·n^dim complex. */
+int  sg_rhs(sg_handle h, const double* f_host, sg_c64* b_dev, hipStream_t stream);
+
+/* y = A x (Theorem 3.3), FP64, matrix-free; x and y must not overlap. */
+int  sg_apply(sg_handle h, const sg_c64* x, sg_c64* y, hipStream_t stream);
+
+/* z = P^{-1} r for P = A_0 or M_0 (pc = SG_PC_MEAN / SG_PC_CSL_MEAN) by fast
+ * diagonalisation of the mean block (Section 5; Section 6.3 block reuse), in the given
+ * precision; SG_PC_NONE copies.  r and z may alias. */
+int  sg_precond(sg_handle h, int pc, int precision, const sg_c64* r, sg_c64* z, hipStream_t stream);
+
+/* Right-preconditioned restarted GMRES(m) (eq. CSL_preconditioned, eq. preconditioned_2d):
+ * CGS2 Arnoldi, Givens least squares, true FP64 residual at each cycle end. */
+int  sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
+              sg_solve_stats* stats, hipStream_t stream);
+
+/* Flexible GMRES(m): the preconditioner may change between iterations.  cb == NULL
+ * uses the built-in opts->precond / opts->precision; otherwise cb(user, r, z, stream)
+ * must write z ≈ P^{-1} r (device vectors of sg_size()) and return 0. */
+typedef int (*sg_precond_cb)(void* user, const sg_c64* r, sg_c64* z, hipStream_t stream);
+int  sg_fgmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
+               sg_precond_cb cb, void* user, sg_solve_stats* stats, hipStream_t stream);
+
+/* One CGS2 step: orthogonalise w (n complex) against the nv orthonormal columns of
+ * V (nv·n complex, vector-major) twice, normalise it in place, and return the nv+1
+ * Arnoldi coefficients h_host[0..nv-1] = V^H w (both passes summed), h_host[nv] = ||w||. */
+int  sg_cgs2(long long n, int nv, const sg_c64* V, sg_c64* w, sg_c64* h_host, hipStream_t stream);
+
+/* ||x||_2 in FP64 (deterministic two-stage reduction). */
+int  sg_norm(long long n, const sg_c64* x, double* out_host, hipStream_t stream);
+
+/* Per-kernel-class timing with HIP events recorded on the launch stream around every
+ * kernel the handle issues (off by default).  Classes: */
+enum {
+    SG_K_APPLY = 0,     /* SG operator                 (algorithmic bytes)            */
+    SG_K_GEMM = 1,      /* preconditioner transforms   (algorithmic flops)            */
+    SG_K_TRI = 2,       /* tridiagonal sweeps          (algorithmic bytes)            */
+    SG_K_DOT = 3,       /* CGS2 multi-dot              (algorithmic bytes)            */
+    SG_K_AXPY = 4,      /* CGS2 multi-axpy / updates   (algorithmic bytes)            */
+    SG_K_NORM = 5,      /* norms and second-stage reductions (algorithmic bytes)      */
+    SG_K_NKINDS = 8
+};
+/* on != 0 enables recording and clears the counters. */
+int  sg_set_profiling(sg_handle h, int on);
+/* Synchronises the pending events and returns, per class k < nkinds (host arrays of
+ * nkinds entries, any may be NULL): total milliseconds, launch count, and the summed
+ * algorithmic work (bytes or flops as listed above). */
+int  sg_kernel_times(sg_handle h, int nkinds, double* ms, long long* count, double* work);
+
+const char* sg_strerror(int status);
+const char* sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SG_H */

@@ -91,3 +91,29 @@ def mean_block(sys_: SGSystem, shift: complex = 1.0) -> sp.csr_matrix:
     """S(ξ̄) at the mean ξ̄ = E[ξ] = 0, i.e. the deterministic operator with k = k_0
     (Section 5, eq. bar_A); shift = 1+iβ gives the mean CSL block of M_0 (Section 6)."""
     return fd.deterministic_S(sys_.dim, sys_.n, sys_.bc, sys_.k_fields[0], shift)
+
+
+def apply_at_points(inst, x: np.ndarray, points) -> np.ndarray:
+    """(A x) at the rows of the given grid points, for every block i, evaluated point by
+    point from Theorem A.4 / A.2 and eqs. b_ij, c_ij without assembling A:
+
+        (A x)_i(p) = (L x_i)(p) - w_p Σ_j c_ij(p) x_j(p) - i (e_p/h) Σ_j b_ij(p) x_j(p).
+
+    Returns an array of shape (Q, len(points)).  Used for sampled checks at sizes where the
+    assembled matrix would not fit.
+    """
+    points = np.asarray(points, dtype=np.int64)
+    Lap1, w, e, h = fd.laplacian(inst.dim, inst.n, inst.bc)
+    E = pc.moment_tables(inst.s, inst.degree)
+    Q = E.shape[2]
+    P = Lap1.shape[0]
+    X = np.asarray(x, dtype=np.complex128).reshape(Q, P)
+    LX = np.asarray((Lap1.tocsr()[points] @ X.T).T)
+    kf = np.asarray(inst.k_fields, dtype=np.float64)
+    out = np.empty((Q, points.size), dtype=np.complex128)
+    for t, p in enumerate(points):
+        kp = kf[:, p]
+        Cp = np.einsum("a,b,abij->ij", kp, kp, E)
+        Bp = np.einsum("a,aij->ij", kp, E[:, 0])
+        out[:, t] = LX[:, t] - w[p] * (Cp @ X[:, p]) - 1j * (e[p] / h) * (Bp @ X[:, p])
+    return out

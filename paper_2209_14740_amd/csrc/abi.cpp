@@ -1,0 +1,234 @@
+// extern "C" entry points of include/sg.h.  Every function converts C++ exceptions
+// into status codes; none aborts.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "sg_internal.h"
+
+using sgi::Ctx;
+using sgi::fail;
+
+static Ctx* ctx(sg_handle h) { return reinterpret_cast<Ctx*>(h); }
+
+static int guard_device(Ctx* c) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SG_EHIP, "hipGetDevice failed");
+    if (dev != c->device) return fail(SG_EINVAL, "handle was created on another device");
+    return SG_OK;
+}
+
+// Makes the handle's profiler the current one for the duration of an entry point.
+struct ProfBind {
+    sgi::Prof* prev;
+    explicit ProfBind(Ctx* c) : prev(sgi::g_prof) { sgi::g_prof = &c->prof; }
+    ~ProfBind() { sgi::g_prof = prev; }
+};
+
+#define SG_TRY(...)                                                        \
+    try {                                                                  \
+        __VA_ARGS__                                                        \
+    } catch (const std::bad_alloc&) {                                      \
+        return fail(SG_ENOMEM, "host allocation failed");                  \
+    } catch (...) {                                                        \
+        return fail(SG_EINVAL, "unexpected exception");                    \
+    }
+
+extern "C" {
+
+int sg_setup(const sg_problem* prob, hipStream_t stream, sg_handle* out) {
+    SG_TRY({
+        if (!out) return fail(SG_EINVAL, "out is null");
+        *out = nullptr;
+        Ctx* c = nullptr;
+        int rc = sgi::build_ctx(prob, stream, &c);
+        if (rc != SG_OK) return rc;
+        *out = reinterpret_cast<sg_handle>(c);
+        return SG_OK;
+    })
+}
+
+void sg_destroy(sg_handle h) {
+    try {
+        delete ctx(h);
+    } catch (...) {
+    }
+}
+
+int sg_basis(sg_handle h, int* Q, int* multi_index) {
+    SG_TRY({
+        if (!h || !Q) return fail(SG_EINVAL, "null argument");
+        Ctx* c = ctx(h);
+        *Q = c->Q;
+        if (multi_index)
+            for (size_t i = 0; i < c->alpha.size(); ++i) multi_index[i] = c->alpha[i];
+        return SG_OK;
+    })
+}
+
+long long sg_size(sg_handle h) { return h ? ctx(h)->nvec : 0; }
+
+int sg_rhs(sg_handle h, const double* f_host, sg_c64* b_dev, hipStream_t stream) {
+    SG_TRY({
+        if (!h || !f_host || !b_dev) return fail(SG_EINVAL, "null argument");
+        Ctx* c = ctx(h);
+        if (int rc = guard_device(c)) return rc;
+        std::vector<double> w(c->P);
+        if (hipMemcpy(w.data(), c->d_w, c->P * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(SG_EHIP, "weight download failed");
+        std::vector<double2> b0(c->P);
+        for (long long i = 0; i < c->P; ++i) b0[i] = make_double2(w[i] * f_host[i], 0.0);
+        SG_HIP(hipMemsetAsync(b_dev, 0, (size_t)c->nvec * sizeof(double2), stream));
+        SG_HIP(hipMemcpyAsync(b_dev, b0.data(), (size_t)c->P * sizeof(double2), hipMemcpyHostToDevice, stream));
+        SG_HIP(hipStreamSynchronize(stream));
+        return SG_OK;
+    })
+}
+
+int sg_apply(sg_handle h, const sg_c64* x, sg_c64* y, hipStream_t stream) {
+    SG_TRY({
+        if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
+        Ctx* c = ctx(h);
+        if (int rc = guard_device(c)) return rc;
+        ProfBind pb(c);
+        return sgi::launch_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), stream);
+    })
+}
+
+int sg_precond(sg_handle h, int pc, int precision, const sg_c64* r, sg_c64* z, hipStream_t stream) {
+    SG_TRY({
+        if (!h || !r || !z) return fail(SG_EINVAL, "null argument");
+        Ctx* c = ctx(h);
+        if (int rc = guard_device(c)) return rc;
+        ProfBind pb(c);
+        return sgi::launch_precond(c, pc, precision, reinterpret_cast<const double2*>(r),
+                                   reinterpret_cast<double2*>(z), stream);
+    })
+}
+
+int sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts, sg_solve_stats* stats,
+             hipStream_t stream) {
+    SG_TRY({
+        if (!h) return fail(SG_EINVAL, "null handle");
+        Ctx* c = ctx(h);
+        if (int rc = guard_device(c)) return rc;
+        ProfBind pb(c);
+        return sgi::run_gmres(c, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), opts, nullptr,
+                              nullptr, false, stats, stream);
+    })
+}
+
+int sg_fgmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts, sg_precond_cb cb, void* user,
+              sg_solve_stats* stats, hipStream_t stream) {
+    SG_TRY({
+        if (!h) return fail(SG_EINVAL, "null handle");
+        Ctx* c = ctx(h);
+        if (int rc = guard_device(c)) return rc;
+        ProfBind pb(c);
+        return sgi::run_gmres(c, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), opts, cb, user,
+                              true, stats, stream);
+    })
+}
+
+int sg_cgs2(long long n, int nv, const sg_c64* V, sg_c64* w, sg_c64* h_host, hipStream_t stream) {
+    SG_TRY({
+        if (n < 1 || nv < 1 || nv > 512 || !V || !w || !h_host) return fail(SG_EINVAL, "invalid argument");
+        const int nb = sgi::reduction_blocks(n);
+        double2 *partial = nullptr, *coef = nullptr, *pin = nullptr;
+        int rc = SG_OK;
+        if (hipMalloc(&partial, (size_t)nb * (nv + 1) * sizeof(double2)) != hipSuccess ||
+            hipMalloc(&coef, (size_t)(2 * nv + 2) * sizeof(double2)) != hipSuccess ||
+            hipHostMalloc(&pin, (size_t)(2 * nv + 2) * sizeof(double2), hipHostMallocDefault) != hipSuccess) {
+            rc = fail(SG_ENOMEM, "sg_cgs2 scratch allocation failed");
+        } else {
+            rc = sgi::cgs2_step(n, nv, reinterpret_cast<const double2*>(V), n, nullptr, reinterpret_cast<double2*>(w),
+                                partial, nb, coef, pin, stream);
+            if (rc == SG_OK) {
+                const double nrm = pin[2 * nv].x;
+                for (int k = 0; k < nv; ++k)
+                    h_host[k] = sg_c64{pin[k].x + pin[nv + k].x, pin[k].y + pin[nv + k].y};
+                h_host[nv] = sg_c64{nrm, 0.0};
+                if (!std::isfinite(nrm)) rc = fail(SG_ENONFINITE, "non-finite norm");
+                else if (nrm > 0.0) {
+                    rc = sgi::launch_scale_copy(n, 1.0 / nrm, reinterpret_cast<double2*>(w),
+                                                reinterpret_cast<double2*>(w), stream);
+                    if (rc == SG_OK && hipStreamSynchronize(stream) != hipSuccess) rc = fail(SG_EHIP, "sync failed");
+                }
+            }
+        }
+        (void)hipFree(partial);
+        (void)hipFree(coef);
+        if (pin) (void)hipHostFree(pin);
+        return rc;
+    })
+}
+
+int sg_norm(long long n, const sg_c64* x, double* out_host, hipStream_t stream) {
+    SG_TRY({
+        if (n < 1 || !x || !out_host) return fail(SG_EINVAL, "invalid argument");
+        const int nb = sgi::reduction_blocks(n);
+        double2 *partial = nullptr, *coef = nullptr;
+        int rc = SG_OK;
+        if (hipMalloc(&partial, (size_t)nb * sizeof(double2)) != hipSuccess ||
+            hipMalloc(&coef, sizeof(double2)) != hipSuccess) {
+            rc = fail(SG_ENOMEM, "sg_norm scratch allocation failed");
+        } else {
+            rc = sgi::launch_norm2(n, reinterpret_cast<const double2*>(x), partial, nb, stream);
+            if (rc == SG_OK) rc = sgi::launch_reduce_norm(nb, partial, coef, stream);
+            double2 hv;
+            if (rc == SG_OK && (hipMemcpyAsync(&hv, coef, sizeof(double2), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                                hipStreamSynchronize(stream) != hipSuccess))
+                rc = fail(SG_EHIP, "sg_norm copy failed");
+            if (rc == SG_OK) *out_host = hv.x;
+        }
+        (void)hipFree(partial);
+        (void)hipFree(coef);
+        return rc;
+    })
+}
+
+int sg_set_profiling(sg_handle h, int on) {
+    SG_TRY({
+        if (!h) return fail(SG_EINVAL, "null handle");
+        Ctx* c = ctx(h);
+        c->prof.reset();
+        c->prof.on = on != 0;
+        return SG_OK;
+    })
+}
+
+int sg_kernel_times(sg_handle h, int nkinds, double* ms, long long* count, double* work) {
+    SG_TRY({
+        if (!h || nkinds < 0) return fail(SG_EINVAL, "invalid argument");
+        Ctx* c = ctx(h);
+        if (int rc = c->prof.resolve()) return rc;
+        for (int k = 0; k < nkinds; ++k) {
+            const bool in = k < SG_K_NKINDS;
+            if (ms) ms[k] = in ? c->prof.ms[k] : 0.0;
+            if (count) count[k] = in ? c->prof.cnt[k] : 0;
+            if (work) work[k] = in ? c->prof.work[k] : 0.0;
+        }
+        return SG_OK;
+    })
+}
+
+const char* sg_strerror(int status) {
+    switch (status) {
+        case SG_OK: return "ok";
+        case SG_ENOTCONV: return "not converged (maxit reached)";
+        case SG_FALLBACK_USED: return "learned correction rejected, plain path used";
+        case SG_EINVAL: return "invalid argument";
+        case SG_ENOMEM: return "out of memory";
+        case SG_EHIP: return "HIP runtime error";
+        case SG_EBREAKDOWN: return "Krylov breakdown";
+        case SG_ENONFINITE: return "non-finite value";
+        case SG_ESETUP: return "setup validation failed";
+        default: return "unknown status";
+    }
+}
+
+const char* sg_last_error(void) { return sgi::last_error(); }
+
+}  // extern "C"

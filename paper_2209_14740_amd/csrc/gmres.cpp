@@ -1,0 +1,278 @@
+// Restarted right-preconditioned GMRES(m) and flexible GMRES(m) drivers.
+//
+// Right preconditioning solves A P^{-1} y = b, x = P^{-1} y, so the residual that is
+// monitored is the one of the unpreconditioned system, ||b - Ax||/||b|| (eq.
+// CSL_preconditioned, eq. preconditioned_2d, Section 6.3).  Each Arnoldi step:
+//   z_j = P^{-1} v_j            (sg_precond or a user callback)
+//   w   = A z_j                 (sg_apply)
+//   CGS2: h = Vᴴw, w -= Vh, twice; h_{j+1,j} = ||w||    (classical Gram-Schmidt with
+//         one full re-orthogonalisation)
+//   complex Givens rotation of the new Hessenberg column, |g_{j+1}|/||b|| estimate.
+// A cycle ends at the estimate tolerance, at m steps or at breakdown; x is updated
+// (x += P^{-1} V y, or x += Z y for the flexible form) and the true FP64 residual
+// decides between stopping and restarting.  Basis vectors are stored unnormalised
+// with a per-vector scale (v_k = s_k V_k).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace sgi {
+
+int launch_reduce_norm(int nblocks, const double2* partial, double2* out, hipStream_t st);
+
+int ensure_workspace(Ctx* c, int m, bool flexible) {
+    Workspace& w = c->ws;
+    if (w.V && w.m >= m && (!flexible || w.Z)) return SG_OK;
+    (void)hipFree(w.V);
+    (void)hipFree(w.Z);
+    (void)hipFree(w.tmp);
+    (void)hipFree(w.scale);
+    (void)hipFree(w.coef);
+    (void)hipFree(w.partial);
+    if (w.host_pinned) (void)hipHostFree(w.host_pinned);
+    w = Workspace{};
+    const size_t nv = (size_t)c->nvec;
+    w.m = m;
+    w.flexible = flexible;
+    w.npartial_blocks = reduction_blocks(c->nvec);
+    if (hipMalloc(&w.V, (size_t)(m + 1) * nv * sizeof(double2)) != hipSuccess) return fail(SG_ENOMEM, "Krylov basis allocation failed");
+    if (flexible && hipMalloc(&w.Z, (size_t)m * nv * sizeof(double2)) != hipSuccess)
+        return fail(SG_ENOMEM, "flexible basis allocation failed");
+    if (hipMalloc(&w.tmp, 2 * nv * sizeof(double2)) != hipSuccess) return fail(SG_ENOMEM, "scratch allocation failed");
+    SG_HIP(hipMalloc(&w.scale, (size_t)(m + 2) * sizeof(double)));
+    SG_HIP(hipMalloc(&w.coef, (size_t)3 * (m + 2) * sizeof(double2)));
+    SG_HIP(hipMalloc(&w.partial, (size_t)w.npartial_blocks * (m + 2) * sizeof(double2)));
+    SG_HIP(hipHostMalloc(&w.host_pinned, (size_t)3 * (m + 2) * sizeof(double2), hipHostMallocDefault));
+    return SG_OK;
+}
+
+// Two passes of classical Gram-Schmidt of w against v_k = s_k V_k (k < nv), then ||w||.
+// On return h_pinned[0..nv) = pass-1 coefficients, [nv..2nv) = pass-2 coefficients,
+// h_pinned[2nv].x = ||w|| after both passes; the stream is synchronised.
+int cgs2_step(long long n, int nv, const double2* V, long long ldv, const double* d_scale, double2* w,
+              double2* partial, int nblocks, double2* d_coef, double2* h_pinned, hipStream_t st) {
+    int rc;
+    for (int pass = 0; pass < 2; ++pass) {
+        if ((rc = launch_multidot(n, nv, V, ldv, d_scale, w, partial, nblocks, st))) return rc;
+        if ((rc = launch_reduce(nblocks, nv, partial, d_scale, d_coef + pass * nv, st))) return rc;
+        if ((rc = launch_axpy_dot(n, nv, V, ldv, d_scale, d_coef + pass * nv, w, nullptr, 0, false, st))) return rc;
+    }
+    if ((rc = launch_norm2(n, w, partial, nblocks, st))) return rc;
+    if ((rc = launch_reduce_norm(nblocks, partial, d_coef + 2 * nv, st))) return rc;
+    SG_HIP(hipMemcpyAsync(h_pinned, d_coef, (size_t)(2 * nv + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));
+    return SG_OK;
+}
+
+static int norm_sync(Ctx* c, const double2* x, double* out, hipStream_t st) {
+    Workspace& w = c->ws;
+    int rc = launch_norm2(c->nvec, x, w.partial, w.npartial_blocks, st);
+    if (rc) return rc;
+    if ((rc = launch_reduce_norm(w.npartial_blocks, w.partial, w.coef, st))) return rc;
+    SG_HIP(hipMemcpyAsync(w.host_pinned, w.coef, sizeof(double2), hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));
+    *out = w.host_pinned[0].x;
+    return SG_OK;
+}
+
+namespace {
+struct Timer {
+    hipEvent_t e[4];
+    bool ok = false;
+    Timer() { ok = hipEventCreate(&e[0]) == hipSuccess && hipEventCreate(&e[1]) == hipSuccess &&
+                   hipEventCreate(&e[2]) == hipSuccess && hipEventCreate(&e[3]) == hipSuccess; }
+    ~Timer() { for (auto& x : e) (void)hipEventDestroy(x); }
+    float between(int a, int b) {
+        float ms = 0;
+        if (ok && hipEventElapsedTime(&ms, e[a], e[b]) == hipSuccess) return ms;
+        return 0.f;
+    }
+};
+}  // namespace
+
+int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_precond_cb cb, void* user,
+              bool flexible, sg_solve_stats* st, hipStream_t stream) {
+    using cd = std::complex<double>;
+    auto t_start = std::chrono::steady_clock::now();
+    if (!o || !b || !x) return fail(SG_EINVAL, "null argument");
+    if (o->restart < 1 || o->restart > 512) return fail(SG_EINVAL, "restart must be in [1, 512]");
+    if (o->maxit < 1) return fail(SG_EINVAL, "maxit must be >= 1");
+    if (!(o->tol > 0)) return fail(SG_EINVAL, "tol must be positive");
+    if (!cb && (o->precond < SG_PC_NONE || o->precond > SG_PC_CSL_MEAN))
+        return fail(SG_EINVAL, "unsupported built-in preconditioner");
+    const int m = o->restart;
+    int rc = ensure_workspace(c, m, flexible);
+    if (rc) return rc;
+    Workspace& W = c->ws;
+    const long long n = c->nvec;
+    const long long ldv = n;
+    sg_solve_stats s{};
+    Timer tm;
+
+    auto precond = [&](const double2* in, double2* out) -> int {
+        if (cb) {
+            int r = cb(user, reinterpret_cast<const sg_c64*>(in), reinterpret_cast<sg_c64*>(out), stream);
+            return r == 0 ? SG_OK : fail(SG_EINVAL, "preconditioner callback returned " + std::to_string(r));
+        }
+        return launch_precond(c, o->precond, o->precision, in, out, stream);
+    };
+
+    double bnorm = 0;
+    if ((rc = norm_sync(c, b, &bnorm, stream))) return rc;
+    if (!std::isfinite(bnorm)) return fail(SG_ENONFINITE, "non-finite right-hand side");
+    if (o->x0_zero) SG_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double2), stream));
+    if (bnorm == 0.0) {
+        SG_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double2), stream));
+        SG_HIP(hipStreamSynchronize(stream));
+        s.converged = 1;
+        if (st) *st = s;
+        return SG_OK;
+    }
+    double2* Vb = W.V;
+    double2* zt = W.tmp;            // z_j (non-flexible) / update scratch
+    double2* ut = W.tmp + n;
+    std::vector<double> hscale(m + 2, 1.0), zscale(m + 1, 1.0);
+    std::vector<cd> H((size_t)(m + 1) * m), R((size_t)(m + 1) * m), g(m + 1), sn(m);
+    std::vector<double> cs(m);
+    bool first = true;
+    int result = SG_ENOTCONV;
+
+    while (true) {
+        // r = b - A x, stored as V_0
+        if (first && o->x0_zero) {
+            SG_HIP(hipMemcpyAsync(Vb, b, (size_t)n * sizeof(double2), hipMemcpyDeviceToDevice, stream));
+        } else {
+            SG_HIP(hipEventRecord(tm.e[0], stream));
+            if ((rc = launch_apply(c, x, ut, stream))) return rc;
+            SG_HIP(hipEventRecord(tm.e[1], stream));
+            if ((rc = launch_axpby(n, make_double2(1, 0), b, make_double2(-1, 0), ut, Vb, stream))) return rc;
+        }
+        double beta = 0;
+        if ((rc = norm_sync(c, Vb, &beta, stream))) return rc;
+        if (!(first && o->x0_zero)) s.t_matvec += tm.between(0, 1);
+        first = false;
+        if (!std::isfinite(beta)) return fail(SG_ENONFINITE, "non-finite residual");
+        s.relres_true = beta / bnorm;
+        if (s.relres_true <= o->tol) { result = SG_OK; s.converged = 1; break; }
+        if (s.iters >= o->maxit) break;
+        hscale[0] = 1.0 / beta;
+        SG_HIP(hipMemcpyAsync(W.scale, hscale.data(), sizeof(double), hipMemcpyHostToDevice, stream));
+        std::fill(g.begin(), g.end(), cd(0));
+        g[0] = beta;
+        int k = 0;
+        bool breakdown = false;
+        for (int j = 0; j < m; ++j) {
+            const double2* vj = Vb + (long long)j * ldv;
+            double2* zj = flexible ? W.Z + (long long)j * ldv : zt;
+            double2* wv = Vb + (long long)(j + 1) * ldv;
+            SG_HIP(hipEventRecord(tm.e[0], stream));
+            if ((rc = precond(vj, zj))) return rc;
+            SG_HIP(hipEventRecord(tm.e[1], stream));
+            if ((rc = launch_apply(c, zj, wv, stream))) return rc;        // w = A P^{-1} V_j (unscaled)
+            SG_HIP(hipEventRecord(tm.e[2], stream));
+            zscale[j] = hscale[j];
+            if ((rc = cgs2_step(n, j + 1, Vb, ldv, W.scale, wv, W.partial, W.npartial_blocks, W.coef,
+                                W.host_pinned, stream)))
+                return rc;
+            SG_HIP(hipEventRecord(tm.e[3], stream));
+            SG_HIP(hipEventSynchronize(tm.e[3]));
+            s.t_precond += tm.between(0, 1);
+            s.t_matvec += tm.between(1, 2);
+            s.t_orth += tm.between(2, 3);
+            const double sj = hscale[j];
+            double colnorm = 0;
+            for (int i = 0; i <= j; ++i) {
+                const double2 a1 = W.host_pinned[i], a2 = W.host_pinned[j + 1 + i];
+                const cd hv = sj * cd(a1.x + a2.x, a1.y + a2.y);
+                if (!std::isfinite(hv.real()) || !std::isfinite(hv.imag()))
+                    return fail(SG_ENONFINITE, "non-finite Hessenberg entry");
+                H[(size_t)i * m + j] = hv;
+                colnorm += std::norm(hv);
+            }
+            const double nrm = W.host_pinned[2 * (j + 1)].x;
+            if (!std::isfinite(nrm)) return fail(SG_ENONFINITE, "non-finite Arnoldi norm");
+            const double hnext = sj * nrm;
+            H[(size_t)(j + 1) * m + j] = hnext;
+            colnorm = std::sqrt(colnorm + hnext * hnext);
+            // apply previous rotations to column j, then a new one
+            std::vector<cd> col(j + 2);
+            for (int i = 0; i <= j + 1; ++i) col[i] = H[(size_t)i * m + j];
+            for (int i = 0; i < j; ++i) {
+                const cd t = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -std::conj(sn[i]) * col[i] + cs[i] * col[i + 1];
+                col[i] = t;
+            }
+            const cd a = col[j], bb = col[j + 1];
+            double cj;
+            cd sjr;
+            if (std::abs(bb) == 0.0) { cj = 1.0; sjr = 0.0; }
+            else if (std::abs(a) == 0.0) { cj = 0.0; sjr = std::conj(bb) / std::abs(bb); }
+            else {
+                const double t = std::hypot(std::abs(a), std::abs(bb));
+                cj = std::abs(a) / t;
+                sjr = (a / std::abs(a)) * std::conj(bb) / t;
+            }
+            cs[j] = cj;
+            sn[j] = sjr;
+            col[j] = cj * a + sjr * bb;
+            col[j + 1] = 0.0;
+            for (int i = 0; i <= j + 1; ++i) R[(size_t)i * m + j] = col[i];
+            g[j + 1] = -std::conj(sjr) * g[j];
+            g[j] = cj * g[j];
+            ++s.iters;
+            k = j + 1;
+            s.relres_est = std::abs(g[j + 1]) / bnorm;
+            if (o->hist && s.iters - 1 < o->hist_cap) o->hist[s.iters - 1] = s.relres_est;
+            if (!(nrm > 1e-14 * colnorm / (sj > 0 ? sj : 1.0)) || hnext <= 1e-14 * colnorm) { breakdown = true; break; }
+            hscale[j + 1] = 1.0 / nrm;
+            SG_HIP(hipMemcpyAsync(W.scale + j + 1, &hscale[j + 1], sizeof(double), hipMemcpyHostToDevice, stream));
+            if (s.relres_est <= o->tol || s.iters >= o->maxit) break;
+        }
+        // y = R^{-1} g (upper triangular k×k)
+        std::vector<cd> y(k);
+        for (int i = k - 1; i >= 0; --i) {
+            cd acc = g[i];
+            for (int l = i + 1; l < k; ++l) acc -= R[(size_t)i * m + l] * y[l];
+            y[i] = acc / R[(size_t)i * m + i];
+            if (!std::isfinite(y[i].real()) || !std::isfinite(y[i].imag()))
+                return fail(SG_ENONFINITE, "non-finite least-squares solution");
+        }
+        for (int i = 0; i < k; ++i) W.host_pinned[i] = make_double2(y[i].real(), y[i].imag());
+        SG_HIP(hipMemcpyAsync(W.coef, W.host_pinned, (size_t)k * sizeof(double2), hipMemcpyHostToDevice, stream));
+        if (flexible) {
+            SG_HIP(hipMemcpyAsync(W.scale, zscale.data(), (size_t)k * sizeof(double), hipMemcpyHostToDevice, stream));
+            if ((rc = launch_lincomb(n, k, W.Z, ldv, W.scale, W.coef, x, stream))) return rc;
+        } else {
+            SG_HIP(hipMemsetAsync(ut, 0, (size_t)n * sizeof(double2), stream));
+            if ((rc = launch_lincomb(n, k, Vb, ldv, W.scale, W.coef, ut, stream))) return rc;
+            if ((rc = precond(ut, zt))) return rc;
+            if ((rc = launch_axpby(n, make_double2(1, 0), x, make_double2(1, 0), zt, x, stream))) return rc;
+        }
+        SG_HIP(hipStreamSynchronize(stream));   // host vectors above must outlive the copies
+        ++s.restarts;
+        if (breakdown) {
+            // the Krylov space is invariant: the update is the solution of this space
+            SG_HIP(hipEventRecord(tm.e[0], stream));
+            if ((rc = launch_apply(c, x, ut, stream))) return rc;
+            if ((rc = launch_axpby(n, make_double2(1, 0), b, make_double2(-1, 0), ut, ut, stream))) return rc;
+            double rn = 0;
+            if ((rc = norm_sync(c, ut, &rn, stream))) return rc;
+            s.relres_true = rn / bnorm;
+            if (s.relres_true <= o->tol) { result = SG_OK; s.converged = 1; }
+            else result = SG_EBREAKDOWN;
+            break;
+        }
+    }
+    s.t_setup = c->t_setup_ms;
+    s.t_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (st) *st = s;
+    if (result == SG_EBREAKDOWN) return fail(SG_EBREAKDOWN, "breakdown before reaching the tolerance");
+    return result;
+}
+
+}  // namespace sgi

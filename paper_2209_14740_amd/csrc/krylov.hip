@@ -1,0 +1,237 @@
+// Vector kernels of the Krylov drivers (HBM-bound, FP64 complex).
+//
+//  multidot   partial[b][k] = Σ_{i in block b} conj(V_k[i]) · w[i]        (first stage)
+//  reduce     out[k] = scale[k] · Σ_b partial[b][k]                        (second stage)
+//  axpy       w[i] -= Σ_k V_k[i] · scale[k] · coef[k]
+//  norm2      partial[b] = Σ_{i in block b} |x[i]|²
+//  lincomb    x[i] += Σ_k V_k[i] · scale[k] · coef[k]
+//
+// The basis vectors are kept unnormalised: v_k = scale[k] · V_k, so a new Arnoldi
+// vector never needs a separate normalisation pass.  Reductions are two-stage with a
+// fixed order (no atomics), so results are bitwise repeatable.
+#include <hip/hip_runtime.h>
+
+#include "sg_internal.h"
+
+namespace sgi {
+
+namespace {
+
+constexpr int RB = 256;      // threads per block
+constexpr int KG = 16;       // basis vectors per register group
+constexpr int MAXBLK = 2048; // first-stage blocks
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-reduce KG complex values; thread 0 of the block ends up with the totals in red[].
+__device__ __forceinline__ void block_reduce(double2 (&acc)[KG], double2* red /* [4][KG] */) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+        acc[k].x = wave_sum(acc[k].x);
+        acc[k].y = wave_sum(acc[k].y);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < KG; ++k) red[wv * KG + k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < KG) {
+        double2 s = red[threadIdx.x];
+        for (int w = 1; w < RB / 64; ++w) {
+            s.x += red[w * KG + threadIdx.x].x;
+            s.y += red[w * KG + threadIdx.x].y;
+        }
+        red[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(RB) void k_multidot(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                                 const double2* __restrict__ w, double2* __restrict__ partial) {
+    __shared__ double2 red[(RB / 64) * KG];
+    const long long stride = (long long)gridDim.x * RB;
+    for (int kg = 0; kg < nv; kg += KG) {
+        double2 acc[KG];
+#pragma unroll
+        for (int k = 0; k < KG; ++k) acc[k] = make_double2(0.0, 0.0);
+        for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += stride) {
+            const double2 wi = w[i];
+#pragma unroll
+            for (int k = 0; k < KG; ++k) {
+                if (kg + k < nv) {
+                    const double2 v = V[(long long)(kg + k) * ldv + i];
+                    acc[k].x += v.x * wi.x + v.y * wi.y;   // conj(v) * w
+                    acc[k].y += v.x * wi.y - v.y * wi.x;
+                }
+            }
+        }
+        block_reduce(acc, red);
+        if (threadIdx.x < KG && kg + threadIdx.x < nv)
+            partial[(long long)blockIdx.x * nv + kg + threadIdx.x] = red[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(RB) void k_norm2(long long n, const double2* __restrict__ x, double2* __restrict__ partial) {
+    __shared__ double red[RB / 64];
+    double s = 0.0;
+    for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
+        const double2 v = x[i];
+        s += v.x * v.x + v.y * v.y;
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < RB / 64; ++w) t += red[w];
+        partial[blockIdx.x] = make_double2(t, 0.0);
+    }
+}
+
+// One block per output coefficient k; mode 0: scaled complex sum, mode 1: sqrt of real sum.
+__global__ __launch_bounds__(RB) void k_reduce(int nblocks, int nv, const double2* __restrict__ partial,
+                                               const double* __restrict__ scale, double2* __restrict__ out, int mode) {
+    __shared__ double2 red[RB / 64];
+    const int k = blockIdx.x;
+    double sx = 0.0, sy = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += RB) {
+        const double2 p = partial[(long long)b * nv + k];
+        sx += p.x;
+        sy += p.y;
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double2(sx, sy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tx = 0.0, ty = 0.0;
+        for (int w = 0; w < RB / 64; ++w) {
+            tx += red[w].x;
+            ty += red[w].y;
+        }
+        if (mode == 1) {
+            out[k] = make_double2(sqrt(tx), 0.0);
+        } else {
+            const double s = scale ? scale[k] : 1.0;
+            out[k] = make_double2(s * tx, s * ty);
+        }
+    }
+}
+
+// w[i] = w[i] + sign · Σ_k V_k[i] · scale[k] · coef[k]
+__global__ __launch_bounds__(RB) void k_axpy(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                             const double* __restrict__ scale, const double2* __restrict__ coef,
+                                             double2* __restrict__ w, double sign) {
+    __shared__ double2 c[512];
+    for (int k = threadIdx.x; k < nv; k += RB) {
+        const double s = (scale ? scale[k] : 1.0) * sign;
+        c[k] = make_double2(coef[k].x * s, coef[k].y * s);
+    }
+    __syncthreads();
+    for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
+        double2 acc = w[i];
+        for (int k = 0; k < nv; ++k) {
+            const double2 v = V[(long long)k * ldv + i];
+            const double2 ck = c[k];
+            acc.x += v.x * ck.x - v.y * ck.y;
+            acc.y += v.x * ck.y + v.y * ck.x;
+        }
+        w[i] = acc;
+    }
+}
+
+__global__ __launch_bounds__(RB) void k_axpby(long long n, double2 a, const double2* __restrict__ x, double2 b,
+                                              const double2* __restrict__ y, double2* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
+        const double2 xv = x[i];
+        double2 r = make_double2(a.x * xv.x - a.y * xv.y, a.x * xv.y + a.y * xv.x);
+        if (y) {
+            const double2 yv = y[i];
+            r.x += b.x * yv.x - b.y * yv.y;
+            r.y += b.x * yv.y + b.y * yv.x;
+        }
+        out[i] = r;
+    }
+}
+
+}  // namespace
+
+int reduction_blocks(long long n) {
+    long long b = (n + RB * 4 - 1) / (RB * 4);
+    if (b < 1) b = 1;
+    if (b > MAXBLK) b = MAXBLK;
+    return (int)b;
+}
+
+static unsigned grid_for(long long n) {
+    long long b = (n + RB - 1) / RB;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+int launch_multidot(long long n, int nv, const double2* V, long long ldv, const double*, const double2* w,
+                    double2* partial, int nblocks, hipStream_t st) {
+    KScope ks(SG_K_DOT, 16.0 * (nv + 1) * (double)n, st);
+    hipLaunchKernelGGL(k_multidot, dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, w, partial);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_reduce(int nblocks, int nv, const double2* partial, const double* scale, double2* out, hipStream_t st) {
+    KScope ks(SG_K_NORM, 16.0 * nblocks * (double)nv, st);
+    hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(RB), 0, st, nblocks, nv, partial, scale, out, 0);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_reduce_norm(int nblocks, const double2* partial, double2* out, hipStream_t st) {
+    KScope ks(SG_K_NORM, 16.0 * nblocks, st);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RB), 0, st, nblocks, 1, partial, (const double*)nullptr, out, 1);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_axpy_dot(long long n, int nv, const double2* V, long long ldv, const double* scale, const double2* coef,
+                    double2* w, double2*, int, bool, hipStream_t st) {
+    if (nv > 512) return fail(SG_EINVAL, "too many basis vectors");
+    KScope ks(SG_K_AXPY, 16.0 * (nv + 2) * (double)n, st);
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, w, -1.0);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_lincomb(long long n, int nv, const double2* V, long long ldv, const double* scale, const double2* coef,
+                   double2* x, hipStream_t st) {
+    if (nv > 512) return fail(SG_EINVAL, "too many basis vectors");
+    KScope ks(SG_K_AXPY, 16.0 * (nv + 2) * (double)n, st);
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, x, 1.0);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_norm2(long long n, const double2* x, double2* partial, int nblocks, hipStream_t st) {
+    KScope ks(SG_K_NORM, 16.0 * (double)n, st);
+    hipLaunchKernelGGL(k_norm2, dim3(nblocks), dim3(RB), 0, st, n, x, partial);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_axpby(long long n, double2 a, const double2* x, double2 b, const double2* y, double2* out, hipStream_t st) {
+    KScope ks(SG_K_AXPY, (y ? 48.0 : 32.0) * (double)n, st);
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(RB), 0, st, n, a, x, b, y, out);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_scale_copy(long long n, double a, const double2* x, double2* out, hipStream_t st) {
+    return launch_axpby(n, make_double2(a, 0.0), x, make_double2(0.0, 0.0), nullptr, out, st);
+}
+
+}  // namespace sgi

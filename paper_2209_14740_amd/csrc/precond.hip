@@ -1,0 +1,473 @@
+// Mean-value (A_0) and mean-CSL (M_0) preconditioner solves (Section 5, eq. bar_A;
+// eq. M with the shift on the k² term; Section 6.3 reuse of one block factorisation for
+// all m+1 blocks).
+//
+// 2D: z = (I_Q ⊗ S(ξ̄))^{-1} r with S(ξ̄) = D⊗S_1 + S_1⊗D is solved per block by
+//   (1) R' = R Ṽ             dense transform along x (complex GEMM, all Q·N rows at once),
+//   (2) for every column a:  (T - i(k̄/h)E_1 + (μ_a - c) D) w_a = r'_a   along y,
+//       pivoted tridiagonal LU factors precomputed in FP64 at setup,
+//   (3) Z = W Ṽᵀ             inverse transform along x.
+// 1D: S(ξ̄) is itself tridiagonal: step (2) alone, one system per block.
+//
+// The complex GEMM C = A·B with complex-interleaved rows is done as the real GEMM
+// C[M×2N] = A[M×2K] · Bexp[2K×2N], Bexp[2k+c][2n+d] = [[Re, Im], [-Im, Re]](B[k][n]),
+// so the interleaved complex128 buffers are used as they are.  Bexp is stored
+// n-major (Bt[2n+d][2k+c]) in the compute precision.  Three arithmetic modes:
+//   F64     v_mfma_f64_16x16x4f64, FP64 throughout;
+//   F32     A rounded to FP32 on load, v_mfma_f32_16x16x4f32, FP32 accumulation;
+//   BF16X3  A and B split into bf16 hi + lo, C += Ahi·Bhi + Ahi·Blo + Alo·Bhi with
+//           v_mfma_f32_16x16x32_bf16, FP32 accumulation.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace sgi {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16X3 = 2 };
+
+constexpr int BM = 128, BN = 128, BK = 32;
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+template <int MODE>
+struct Lds;
+template <>
+struct Lds<MODE_F64> {
+    static constexpr int PAD = BK + 1;
+    double a[BM * PAD];
+    double b[BN * PAD];
+};
+template <>
+struct Lds<MODE_F32> {
+    static constexpr int PAD = BK + 1;
+    float a[BM * PAD];
+    float b[BN * PAD];
+};
+template <>
+struct Lds<MODE_BF16X3> {
+    static constexpr int PAD = BK + 8;
+    uint16_t ahi[BM * PAD], alo[BM * PAD];
+    uint16_t bhi[BN * PAD], blo[BN * PAD];
+};
+
+// C[M][Nc] = A[M][Kc] · B where Bt[Nc][Kc] (n-major).  A is FP64; C is FP64.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, long long lda,
+                                              const void* __restrict__ Bt0, const void* __restrict__ Bt1,
+                                              long long ldb, double* __restrict__ C, long long ldc,
+                                              int M, int Nc, int Kc, int tiles_m, int tiles_n) {
+    __shared__ Lds<MODE> sm;
+    constexpr int PAD = Lds<MODE>::PAD;
+    const int ntiles = tiles_m * tiles_n;
+    const int per = gridDim.x / 8;
+    const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-contiguous bands
+    if (tile >= ntiles) return;
+    const int tm = tile / tiles_n, tn = tile % tiles_n;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv >> 1, wn = wv & 1;
+    const int l16 = lane & 15, lq = lane >> 4;
+
+    using acc_t = typename std::conditional<MODE == MODE_F64, d4, f4>::type;
+    acc_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    // global → register staging: A tile 128×32 doubles = 2048 double2, 8 per thread
+    double2 ra[8];
+    // B staging per mode
+    double2 rb64[8];
+    float4 rb32[4];
+    uint4 rbh[2], rbl[2];
+
+    auto load_tiles = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int idx = p * 256 + tid, row = idx >> 4, k = (idx & 15) * 2;
+            const int gm = m0 + row, gk = k0 + k;
+            ra[p] = (gm < M && gk < Kc) ? *reinterpret_cast<const double2*>(A + (long long)gm * lda + gk)
+                                        : make_double2(0.0, 0.0);
+        }
+        if constexpr (MODE == MODE_F64) {
+            const double* B = reinterpret_cast<const double*>(Bt0);
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+                const int idx = p * 256 + tid, row = idx >> 4, k = (idx & 15) * 2;
+                const int gn = n0 + row, gk = k0 + k;
+                rb64[p] = (gn < Nc && gk < Kc) ? *reinterpret_cast<const double2*>(B + (long long)gn * ldb + gk)
+                                               : make_double2(0.0, 0.0);
+            }
+        } else if constexpr (MODE == MODE_F32) {
+            const float* B = reinterpret_cast<const float*>(Bt0);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int idx = p * 256 + tid, row = idx >> 3, k = (idx & 7) * 4;
+                const int gn = n0 + row, gk = k0 + k;
+                // Kc is even and ldb a multiple of 4: a float4 is either fully inside or
+                // straddles the end, in which case the tail lanes are read as zero below.
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gn < Nc && gk + 3 < Kc) v = *reinterpret_cast<const float4*>(B + (long long)gn * ldb + gk);
+                else if (gn < Nc && gk < Kc) {
+                    v.x = B[(long long)gn * ldb + gk];
+                    v.y = B[(long long)gn * ldb + gk + 1];
+                }
+                rb32[p] = v;
+            }
+        } else {
+            const uint16_t* Bh = reinterpret_cast<const uint16_t*>(Bt0);
+            const uint16_t* Bl = reinterpret_cast<const uint16_t*>(Bt1);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int idx = p * 256 + tid, row = idx >> 2, k = (idx & 3) * 8;
+                const int gn = n0 + row, gk = k0 + k;
+                uint4 vh = make_uint4(0, 0, 0, 0), vl = make_uint4(0, 0, 0, 0);
+                if (gn < Nc && gk < Kc) {   // ldb is padded to a multiple of 8 with zeros
+                    vh = *reinterpret_cast<const uint4*>(Bh + (long long)gn * ldb + gk);
+                    vl = *reinterpret_cast<const uint4*>(Bl + (long long)gn * ldb + gk);
+                }
+                rbh[p] = vh;
+                rbl[p] = vl;
+            }
+        }
+    };
+
+    auto store_tiles = [&]() {
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int idx = p * 256 + tid, row = idx >> 4, k = (idx & 15) * 2;
+            if constexpr (MODE == MODE_F64) {
+                sm.a[row * PAD + k] = ra[p].x;
+                sm.a[row * PAD + k + 1] = ra[p].y;
+            } else if constexpr (MODE == MODE_F32) {
+                sm.a[row * PAD + k] = (float)ra[p].x;
+                sm.a[row * PAD + k + 1] = (float)ra[p].y;
+            } else {
+                const float x0 = (float)ra[p].x, x1 = (float)ra[p].y;
+                const uint16_t h0 = bf16_rne(x0), h1 = bf16_rne(x1);
+                sm.ahi[row * PAD + k] = h0;
+                sm.ahi[row * PAD + k + 1] = h1;
+                sm.alo[row * PAD + k] = bf16_rne((float)(ra[p].x - (double)bf16_to_f(h0)));
+                sm.alo[row * PAD + k + 1] = bf16_rne((float)(ra[p].y - (double)bf16_to_f(h1)));
+            }
+        }
+        if constexpr (MODE == MODE_F64) {
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+                const int idx = p * 256 + tid, row = idx >> 4, k = (idx & 15) * 2;
+                sm.b[row * PAD + k] = rb64[p].x;
+                sm.b[row * PAD + k + 1] = rb64[p].y;
+            }
+        } else if constexpr (MODE == MODE_F32) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int idx = p * 256 + tid, row = idx >> 3, k = (idx & 7) * 4;
+                sm.b[row * PAD + k] = rb32[p].x;
+                sm.b[row * PAD + k + 1] = rb32[p].y;
+                sm.b[row * PAD + k + 2] = rb32[p].z;
+                sm.b[row * PAD + k + 3] = rb32[p].w;
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int idx = p * 256 + tid, row = idx >> 2, k = (idx & 3) * 8;
+                *reinterpret_cast<uint4*>(&sm.bhi[row * PAD + k]) = rbh[p];
+                *reinterpret_cast<uint4*>(&sm.blo[row * PAD + k]) = rbl[p];
+            }
+        }
+    };
+
+    const int nk = (Kc + BK - 1) / BK;
+    load_tiles(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+        if constexpr (MODE == MODE_BF16X3) {
+            bf8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = wm * 64 + i * 16 + l16;
+                ah[i] = *reinterpret_cast<const bf8*>(&sm.ahi[r * PAD + lq * 8]);
+                al[i] = *reinterpret_cast<const bf8*>(&sm.alo[r * PAD + lq * 8]);
+                const int cN = wn * 64 + i * 16 + l16;
+                bh[i] = *reinterpret_cast<const bf8*>(&sm.bhi[cN * PAD + lq * 8]);
+                bl[i] = *reinterpret_cast<const bf8*>(&sm.blo[cN * PAD + lq * 8]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                using e_t = typename std::conditional<MODE == MODE_F64, double, float>::type;
+                e_t av[4], bv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    av[i] = sm.a[(wm * 64 + i * 16 + l16) * PAD + kk + lq];
+                    bv[i] = sm.b[(wn * 64 + i * 16 + l16) * PAD + kk + lq];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if constexpr (MODE == MODE_F64)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+                        else
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                    }
+            }
+        }
+    }
+    // epilogue: the f32-output MFMAs leave D[4*lq + v][l16] of each 16×16 block in lane
+    // (lq, l16); the f64 one leaves D[lq + 4*v][l16].
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + l16;
+            if (col >= Nc) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rl = (MODE == MODE_F64) ? (lq + 4 * v) : (lq * 4 + v);
+                const int row = m0 + wm * 64 + i * 16 + rl;
+                if (row < M) C[(long long)row * ldc + col] = (double)acc[i][j][v];
+            }
+        }
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+constexpr int CH = 8;
+
+// Pivoted tridiagonal solve, in place, one thread per system (q, a).
+//   element i of system (q,a):  X[q*sq + a*sa + i*se]
+//   factor row i of system a:   f.xxx[i*f.nsys + a*fa]
+__global__ __launch_bounds__(64) void k_tri(double2* __restrict__ X, TriFactors f, int len, int na, int nq,
+                                            long long se, long long sa, long long sq, int fa) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)na * nq) return;
+    const int a = (int)(t % na), q = (int)(t / na);
+    double2* x = X + (long long)q * sq + (long long)a * sa;
+    const int fs = f.nsys;
+    const int fo = a * fa;
+    // forward: L y = P b
+    double2 cur = x[0];
+    for (int i0 = 0; i0 < len - 1; i0 += CH) {
+        const int cnt = min(CH, len - 1 - i0);
+        double2 nb[CH], l[CH];
+        uint8_t pv[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (u < cnt) {
+                nb[u] = x[(long long)(i0 + u + 1) * se];
+                l[u] = f.dl[(long long)(i0 + u) * fs + fo];
+                pv[u] = f.piv[(long long)(i0 + u) * fs + fo];
+            }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (u < cnt) {
+                double2 out, nxt;
+                if (pv[u]) {
+                    out = nb[u];
+                    nxt = csub(cur, cmul(l[u], nb[u]));
+                } else {
+                    out = cur;
+                    nxt = csub(nb[u], cmul(l[u], cur));
+                }
+                x[(long long)(i0 + u) * se] = out;
+                cur = nxt;
+            }
+    }
+    // backward: U x = y
+    double2 x1 = cmul(cur, f.dinv[(long long)(len - 1) * fs + fo]);
+    x[(long long)(len - 1) * se] = x1;
+    if (len < 2) return;
+    double2 x0 = cmul(csub(x[(long long)(len - 2) * se], cmul(f.du1[(long long)(len - 2) * fs + fo], x1)),
+                      f.dinv[(long long)(len - 2) * fs + fo]);
+    x[(long long)(len - 2) * se] = x0;
+    // x0 = x[i+1], x1 = x[i+2]
+    for (int i0 = len - 3; i0 >= 0; i0 -= CH) {
+        const int cnt = min(CH, i0 + 1);
+        double2 bb[CH], u1[CH], u2[CH], di[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (u < cnt) {
+                const long long i = i0 - u;
+                bb[u] = x[i * se];
+                u1[u] = f.du1[i * fs + fo];
+                u2[u] = f.du2[i * fs + fo];
+                di[u] = f.dinv[i * fs + fo];
+            }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (u < cnt) {
+                const double2 r = csub(csub(bb[u], cmul(u1[u], x0)), cmul(u2[u], x1));
+                const double2 xv = cmul(r, di[u]);
+                x[(long long)(i0 - u) * se] = xv;
+                x1 = x0;
+                x0 = xv;
+            }
+    }
+}
+
+static inline uint16_t host_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+static inline float host_bf16_f(uint16_t b) {
+    uint32_t u = ((uint32_t)b) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+}  // namespace
+
+int bexp_ld(int n) { return ((2 * n + 7) / 8) * 8; }
+
+// Bt[2n+d][2k+c] = Bexp[2k+c][2n+d] for the complex matrix B[k][n] (k, n < N).
+static void expand_bt(int N, const std::vector<cplx>& B /* [k][n] */, std::vector<double>& out, int ld) {
+    out.assign((size_t)2 * N * ld, 0.0);
+    for (int k = 0; k < N; ++k)
+        for (int n = 0; n < N; ++n) {
+            const cplx b = B[(size_t)k * N + n];
+            out[(size_t)(2 * n) * ld + 2 * k] = b.real();
+            out[(size_t)(2 * n) * ld + 2 * k + 1] = -b.imag();
+            out[(size_t)(2 * n + 1) * ld + 2 * k] = b.imag();
+            out[(size_t)(2 * n + 1) * ld + 2 * k + 1] = b.real();
+        }
+}
+
+static int upload_one(DenseB& d, const std::vector<double>& e) {
+    const size_t cnt = e.size();
+    std::vector<float> f32(cnt);
+    std::vector<uint16_t> hi(cnt), lo(cnt);
+    for (size_t i = 0; i < cnt; ++i) {
+        f32[i] = (float)e[i];
+        hi[i] = host_bf16((float)e[i]);
+        lo[i] = host_bf16((float)(e[i] - (double)host_bf16_f(hi[i])));
+    }
+    SG_HIP(hipMalloc(&d.f64, cnt * sizeof(double)));
+    SG_HIP(hipMalloc(&d.f32, cnt * sizeof(float)));
+    SG_HIP(hipMalloc(&d.bf_hi, cnt * sizeof(uint16_t)));
+    SG_HIP(hipMalloc(&d.bf_lo, cnt * sizeof(uint16_t)));
+    SG_HIP(hipMemcpy(d.f64, e.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(d.f32, f32.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(d.bf_hi, hi.data(), cnt * sizeof(uint16_t), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(d.bf_lo, lo.data(), cnt * sizeof(uint16_t), hipMemcpyHostToDevice));
+    return SG_OK;
+}
+
+int upload_dense_b(Ctx* c, hipStream_t) {
+    const int N = c->n, ld = bexp_ld(N);
+    std::vector<cplx> Bf((size_t)N * N), Bi((size_t)N * N);
+    for (int x = 0; x < N; ++x)
+        for (int a = 0; a < N; ++a) {
+            Bf[(size_t)x * N + a] = c->Vt[(size_t)x * N + a];   // forward: B[k=x][n=a] = Ṽ[x][a]
+            Bi[(size_t)a * N + x] = c->Vt[(size_t)x * N + a];   // inverse: B[k=a][n=x] = Ṽ[x][a]
+        }
+    std::vector<double> e;
+    expand_bt(N, Bf, e, ld);
+    int rc = upload_one(c->fwd, e);
+    if (rc) return rc;
+    expand_bt(N, Bi, e, ld);
+    return upload_one(c->inv, e);
+}
+
+static int launch_gemm(int precision, const double* A, long long lda, const DenseB& B, int N, double* C,
+                       long long ldc, int M, hipStream_t st) {
+    const int Nc = 2 * N, Kc = 2 * N, ldb = bexp_ld(N);
+    const int tiles_m = (M + BM - 1) / BM, tiles_n = (Nc + BN - 1) / BN;
+    const int nt = tiles_m * tiles_n;
+    const int nblk = ((nt + 7) / 8) * 8;
+    KScope ks(SG_K_GEMM, 2.0 * M * (double)Nc * (double)Kc, st);
+    switch (precision) {
+        case SG_PREC_F64:
+            hipLaunchKernelGGL(k_gemm<MODE_F64>, dim3(nblk), dim3(256), 0, st, A, lda, (const void*)B.f64,
+                               (const void*)nullptr, (long long)ldb, C, ldc, M, Nc, Kc, tiles_m, tiles_n);
+            break;
+        case SG_PREC_F32:
+            hipLaunchKernelGGL(k_gemm<MODE_F32>, dim3(nblk), dim3(256), 0, st, A, lda, (const void*)B.f32,
+                               (const void*)nullptr, (long long)ldb, C, ldc, M, Nc, Kc, tiles_m, tiles_n);
+            break;
+        case SG_PREC_BF16X3:
+            hipLaunchKernelGGL(k_gemm<MODE_BF16X3>, dim3(nblk), dim3(256), 0, st, A, lda, (const void*)B.bf_hi,
+                               (const void*)B.bf_lo, (long long)ldb, C, ldc, M, Nc, Kc, tiles_m, tiles_n);
+            break;
+        default:
+            return fail(SG_EINVAL, "unknown precision");
+    }
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+static int launch_tri(const TriFactors& f, double2* X, int n, int Q, int dim, hipStream_t st) {
+    int na, nq, fa;
+    long long se, sa, sq;
+    if (dim == 2) {
+        na = n; nq = Q; se = n; sa = 1; sq = (long long)n * n; fa = 1;
+    } else {
+        na = 1; nq = Q; se = 1; sa = 0; sq = n; fa = 0;
+    }
+    const long long nth = (long long)na * nq;
+    const int blk = 64;
+    // algorithmic: every element read and written once, factors read once
+    KScope ks(SG_K_TRI, 32.0 * na * (double)nq * n + 65.0 * f.nsys * (double)n, st);
+    hipLaunchKernelGGL(k_tri, dim3((unsigned)((nth + blk - 1) / blk)), dim3(blk), 0, st, X, f, n, na, nq, se, sa,
+                       sq, fa);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, hipStream_t st) {
+    if (pc == SG_PC_NONE) {
+        if (r != z) SG_HIP(hipMemcpyAsync(z, r, (size_t)c->nvec * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        return SG_OK;
+    }
+    if (pc != SG_PC_MEAN && pc != SG_PC_CSL_MEAN) return fail(SG_EINVAL, "sg_precond: unknown preconditioner");
+    if (precision < SG_PREC_F64 || precision > SG_PREC_BF16X3) return fail(SG_EINVAL, "sg_precond: unknown precision");
+    const TriFactors& f = c->tri[pc == SG_PC_MEAN ? 0 : 1];
+    const int n = c->n;
+    if (c->dim == 1) {
+        if (r != z) SG_HIP(hipMemcpyAsync(z, r, (size_t)c->nvec * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        return launch_tri(f, z, n, c->Q, 1, st);
+    }
+    const int M = c->Q * n;
+    double2* t = c->d_tmp_pc;
+    int rc = launch_gemm(precision, reinterpret_cast<const double*>(r), 2LL * n, c->fwd, n,
+                         reinterpret_cast<double*>(t), 2LL * n, M, st);
+    if (rc) return rc;
+    rc = launch_tri(f, t, n, c->Q, 2, st);
+    if (rc) return rc;
+    return launch_gemm(precision, reinterpret_cast<const double*>(t), 2LL * n, c->inv, n,
+                       reinterpret_cast<double*>(z), 2LL * n, M, st);
+}
+
+}  // namespace sgi

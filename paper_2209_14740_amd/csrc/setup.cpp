@@ -1,0 +1,514 @@
+// Host-side setup of the SG Helmholtz operator (FP64, validated), then upload.
+//
+//  * Chaos basis: multi-indices of total degree <= r in s variables, graded and
+//    descending-lexicographic within a degree (Section 2.3).
+//  * Galerkin coupling: with k = k_0 + Σ k_ℓ ξ_ℓ (eq. random_wavenumber) and
+//    ξ = φ_1/√3, ξ² = 1/3 + 2φ_2/(3√5) for the orthonormal Legendre φ_n, the
+//    products k and k² are finite sums Σ_γ κ_γ(x) Ψ_γ(ξ) over the multi-indices γ
+//    of degree <= 1 and <= 2.  Hence (eqs. b_ij, c_ij)
+//        b_ij(x) = Σ_γ κ1_γ(x) E[Ψ_γ φ_i φ_j],   c_ij(x) = Σ_γ κ2_γ(x) E[Ψ_γ φ_i φ_j],
+//    and E[Ψ_γ φ_i φ_j] = Π_ℓ t(γ_ℓ, α_iℓ, α_jℓ) with the univariate triple product
+//    t(c,a,b) = E[φ_c φ_a φ_b] = sqrt((2a+1)(2b+1)(2c+1)) · (a b c; 0 0 0)², the squared
+//    Wigner 3j symbol (Adams-Neumann linearisation of Legendre products).  Exact zeros
+//    come from its parity and triangle rules.
+//  * Fields: D2_γ = w·κ2_γ (k² term with the boundary weights of Theorem A.4) and
+//    D1_γ = (e/h)·κ1_γ (absorbing-boundary term, Theorem A.2 / A.4).
+//  * Mean block: with k_0 = k̄ constant, S(ξ̄) = D⊗S_1 + S_1⊗D in 2D, where
+//    S_1 = T - i(k̄/h)E_1 - (c/2)D, E_1 = diag(1,0,...,0,1), c = k̄² (A_0) or (1+iβ)k̄²
+//    (M_0, eq. M); in 1D S(ξ̄) = T - i(k̄/h)E_1 - cD (Theorem A.2, Remark 6.1).
+//    The generalised eigenpairs (T - i(k̄/h)E_1) v_a = μ_a D v_a, normalised v_aᵀ D v_a = 1
+//    (complex symmetric, unconjugated), do not depend on c.  Writing the block vector
+//    as X[x,y], S(ξ̄)X = S_1 X D + D X S_1; substituting X = Ṽ W gives for every a the
+//    tridiagonal system along y (T - i(k̄/h)E_1 + (μ_a - c) D) w_a = (Ṽᵀ R)_a.  The
+//    preconditioner is thus one dense transform along x, Na pivoted tridiagonal solves
+//    along y, and the inverse transform (fast diagonalisation in one direction,
+//    after Lynch, Rice & Thomas 1964).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "sg_internal.h"
+
+namespace sgi {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+const char* last_error() { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------- basis
+
+static void enum_level(int s, int d, std::vector<int>& cur, std::vector<int>& out) {
+    // all tuples of length s with sum d, first component descending
+    int pos = (int)cur.size();
+    if (pos == s - 1) {
+        cur.push_back(d);
+        out.insert(out.end(), cur.begin(), cur.end());
+        cur.pop_back();
+        return;
+    }
+    for (int a = d; a >= 0; --a) {
+        cur.push_back(a);
+        enum_level(s, d - a, cur, out);
+        cur.pop_back();
+    }
+}
+
+static std::vector<int> make_basis(int s, int r) {
+    std::vector<int> out, cur;
+    for (int d = 0; d <= r; ++d) enum_level(s, d, cur, out);
+    return out;
+}
+
+static long double lfactorial(int n) {
+    long double f = 1.0L;
+    for (int i = 2; i <= n; ++i) f *= (long double)i;
+    return f;
+}
+
+// t(c,a,b) = E[φ_c φ_a φ_b] for orthonormal Legendre φ and ξ ~ U[-1,1].
+static double triple(int c, int a, int b) {
+    int tot = a + b + c;
+    if (tot & 1) return 0.0;
+    int g = tot / 2;
+    if (a > g || b > g || c > g) return 0.0;
+    long double w3 = lfactorial(2 * g - 2 * a) * lfactorial(2 * g - 2 * b) * lfactorial(2 * g - 2 * c) /
+                     lfactorial(2 * g + 1);
+    long double ratio = lfactorial(g) / (lfactorial(g - a) * lfactorial(g - b) * lfactorial(g - c));
+    w3 *= ratio * ratio;
+    return (double)(sqrtl((long double)(2 * a + 1) * (2 * b + 1) * (2 * c + 1)) * w3);
+}
+
+static void build_coupling(const std::vector<int>& alpha, int Q, int s,
+                           const std::vector<std::vector<int>>& gammas, Coupling& cp) {
+    cp.nfield = (int)gammas.size();
+    cp.pair_ptr.assign(1, 0);
+    cp.pair_j.clear();
+    cp.term_ptr.assign(1, 0);
+    cp.term_field.clear();
+    cp.term_val.clear();
+    for (int i = 0; i < Q; ++i) {
+        for (int j = 0; j < Q; ++j) {
+            int nterm = 0;
+            for (int g = 0; g < (int)gammas.size(); ++g) {
+                double v = 1.0;
+                for (int l = 0; l < s && v != 0.0; ++l)
+                    v *= triple(gammas[g][l], alpha[i * s + l], alpha[j * s + l]);
+                if (v != 0.0) {
+                    cp.term_field.push_back(g);
+                    cp.term_val.push_back(v);
+                    ++nterm;
+                }
+            }
+            if (nterm) {
+                cp.pair_j.push_back(j);
+                cp.term_ptr.push_back((int)cp.term_field.size());
+            }
+        }
+        cp.pair_ptr.push_back((int)cp.pair_j.size());
+    }
+}
+
+// ------------------------------------------------- complex symmetric eigen
+
+// Eigenvalues of the complex symmetric tridiagonal matrix (diag d, off-diagonal e with
+// e[i] coupling rows i and i+1) by the implicit QL iteration with complex orthogonal
+// plane rotations (Bowdler-Martin-Reinsch-Wilkinson 1968 QL in the complex symmetric
+// form of Cullum & Willoughby).  Returns false if an eigenvalue fails to converge.
+static bool ql_eigenvalues(std::vector<cplx>& d, std::vector<cplx> e) {
+    const int n = (int)d.size();
+    e.resize(n);
+    e[n - 1] = 0.0;
+    const double eps = 2.2e-16;
+    for (int l = 0; l < n; ++l) {
+        int iter = 0, m;
+        do {
+            for (m = l; m < n - 1; ++m) {
+                double dd = std::abs(d[m]) + std::abs(d[m + 1]);
+                if (std::abs(e[m]) <= eps * dd) break;
+            }
+            if (m != l) {
+                if (++iter > 200) return false;
+                cplx g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                cplx r = std::sqrt(g * g + 1.0);
+                cplx gp = g + r, gm = g - r;
+                g = d[m] - d[l] + e[l] / (std::abs(gp) >= std::abs(gm) ? gp : gm);
+                cplx s = 1.0, c = 1.0, p = 0.0;
+                int i;
+                bool early = false;
+                for (i = m - 1; i >= l; --i) {
+                    cplx f = s * e[i], b = c * e[i];
+                    r = std::sqrt(f * f + g * g);
+                    e[i + 1] = r;
+                    if (std::abs(r) == 0.0) {
+                        d[i + 1] -= p;
+                        e[m] = 0.0;
+                        early = true;
+                        break;
+                    }
+                    s = f / r;
+                    c = g / r;
+                    g = d[i + 1] - p;
+                    r = (d[i] - g) * s + 2.0 * c * b;
+                    p = s * r;
+                    d[i + 1] = g + p;
+                    g = c * r - b;
+                }
+                if (early) continue;
+                d[l] -= p;
+                e[l] = g;
+                e[m] = 0.0;
+            }
+        } while (m != l);
+    }
+    return true;
+}
+
+// Pivoted LU of a complex tridiagonal matrix (sub dl, diag d, super du), row-partial
+// pivoting.  On exit: dl = multipliers, d = U diagonal, du = U first super-diagonal,
+// du2 = U second super-diagonal, piv[i] = 1 when rows i, i+1 were exchanged.
+static bool tri_lu(int n, std::vector<cplx>& dl, std::vector<cplx>& d, std::vector<cplx>& du,
+                   std::vector<cplx>& du2, std::vector<uint8_t>& piv) {
+    du2.assign(std::max(n - 2, 0), 0.0);
+    piv.assign(std::max(n - 1, 0), 0);
+    for (int i = 0; i < n - 1; ++i) {
+        if (std::abs(d[i]) >= std::abs(dl[i])) {
+            if (d[i] == 0.0) return false;
+            cplx l = dl[i] / d[i];
+            dl[i] = l;
+            d[i + 1] -= l * du[i];
+        } else {
+            cplx l = d[i] / dl[i];
+            piv[i] = 1;
+            d[i] = dl[i];
+            dl[i] = l;
+            cplx old_d1 = d[i + 1];
+            cplx old_u = du[i];
+            du[i] = old_d1;
+            d[i + 1] = old_u - l * old_d1;
+            if (i < n - 2) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -l * du[i + 1];
+            }
+        }
+    }
+    return d[n - 1] != 0.0;
+}
+
+static void tri_solve(int n, const std::vector<cplx>& dl, const std::vector<cplx>& d,
+                      const std::vector<cplx>& du, const std::vector<cplx>& du2,
+                      const std::vector<uint8_t>& piv, std::vector<cplx>& b) {
+    for (int i = 0; i < n - 1; ++i) {
+        if (piv[i]) std::swap(b[i], b[i + 1]);
+        b[i + 1] -= dl[i] * b[i];
+    }
+    b[n - 1] /= d[n - 1];
+    if (n >= 2) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / d[n - 2];
+    for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / d[i];
+}
+
+// Eigenpairs of (T - iτE_1) v = μ D v on n nodes (1D absorbing T of Theorem A.2).
+static int mean_eigen(int n, double h, double kbar, std::vector<cplx>& mu, std::vector<cplx>& V) {
+    const double ih2 = 1.0 / (h * h), tau = kbar / h;
+    std::vector<double> dw(n, 1.0);
+    dw[0] = dw[n - 1] = 0.5;
+    // J = D^{-1/2} (T - iτE_1) D^{-1/2}
+    std::vector<cplx> jd(n), je(n - 1);
+    for (int i = 0; i < n; ++i) {
+        double t = (i == 0 || i == n - 1) ? ih2 : 2.0 * ih2;
+        cplx v = t;
+        if (i == 0 || i == n - 1) v -= cplx(0.0, tau);
+        jd[i] = v / dw[i];
+    }
+    for (int i = 0; i < n - 1; ++i) je[i] = -ih2 / std::sqrt(dw[i] * dw[i + 1]);
+    mu = jd;
+    if (!ql_eigenvalues(mu, je)) return fail(SG_ESETUP, "QL eigenvalue iteration did not converge");
+    std::sort(mu.begin(), mu.end(), [](cplx a, cplx b) { return a.real() < b.real(); });
+    // eigenvectors of J by inverse iteration with a slightly perturbed shift
+    V.assign((size_t)n * n, 0.0);
+    double jnorm = 4.0 * ih2 + 2.0 * tau;
+    std::vector<cplx> dl, dd, du, du2, u(n);
+    std::vector<uint8_t> piv;
+    for (int a = 0; a < n; ++a) {
+        cplx sh = mu[a] + cplx(1e-13, 1e-13) * jnorm;
+        dl.assign(je.begin(), je.end());
+        du.assign(je.begin(), je.end());
+        dd.resize(n);
+        for (int i = 0; i < n; ++i) dd[i] = jd[i] - sh;
+        if (!tri_lu(n, dl, dd, du, du2, piv)) return fail(SG_ESETUP, "singular shifted eigen system");
+        for (int i = 0; i < n; ++i) u[i] = 1.0 + 0.37 * std::sin(1.0 + 7.13 * i) + cplx(0, 0.11 * std::cos(3.1 * i));
+        for (int it = 0; it < 3; ++it) {
+            tri_solve(n, dl, dd, du, du2, piv, u);
+            double nr = 0;
+            for (auto& z : u) nr += std::norm(z);
+            nr = std::sqrt(nr);
+            for (auto& z : u) z /= nr;
+        }
+        cplx uu = 0;
+        for (auto& z : u) uu += z * z;
+        cplx sc = 1.0 / std::sqrt(uu);
+        for (int i = 0; i < n; ++i) V[(size_t)i * n + a] = u[i] * sc / std::sqrt(dw[i]);
+    }
+    // validation: residual and D-orthonormality of the eigenvectors
+    double vmax = 0, res = 0;
+    for (size_t i = 0; i < V.size(); ++i) vmax = std::max(vmax, std::abs(V[i]));
+    for (int a = 0; a < n; ++a) {
+        for (int i = 0; i < n; ++i) {
+            double t = (i == 0 || i == n - 1) ? ih2 : 2.0 * ih2;
+            cplx Tv = t * V[(size_t)i * n + a];
+            if (i > 0) Tv -= ih2 * V[(size_t)(i - 1) * n + a];
+            if (i < n - 1) Tv -= ih2 * V[(size_t)(i + 1) * n + a];
+            if (i == 0 || i == n - 1) Tv -= cplx(0, tau) * V[(size_t)i * n + a];
+            cplx r = Tv - mu[a] * dw[i] * V[(size_t)i * n + a];
+            res = std::max(res, std::abs(r));
+        }
+    }
+    res /= (jnorm * vmax);
+    double orth = 0;
+    for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) {
+            cplx acc = 0;
+            for (int i = 0; i < n; ++i) acc += V[(size_t)i * n + a] * dw[i] * V[(size_t)i * n + b];
+            orth = std::max(orth, std::abs(acc - (a == b ? 1.0 : 0.0)));
+        }
+    if (!(res < 1e-10) || !(orth < 1e-8))
+        return fail(SG_ESETUP, "eigenfactor validation failed: residual " + std::to_string(res) +
+                                   ", D-orthonormality defect " + std::to_string(orth));
+    return SG_OK;
+}
+
+// Factors of (T - iτE_1 + σ_a D) for the systems a (1D absorbing T), uploaded row-major.
+static int build_tri(int n, double h, double kbar, const std::vector<cplx>& sig, TriFactors& tf) {
+    const int nsys = (int)sig.size();
+    const double ih2 = 1.0 / (h * h), tau = kbar / h;
+    std::vector<double2> hdl((size_t)std::max(n - 1, 1) * nsys), hdi((size_t)n * nsys),
+        hu1((size_t)std::max(n - 1, 1) * nsys), hu2((size_t)std::max(n - 2, 1) * nsys);
+    std::vector<uint8_t> hp((size_t)std::max(n - 1, 1) * nsys);
+    std::vector<cplx> dl, d, du, du2;
+    std::vector<uint8_t> piv;
+    for (int a = 0; a < nsys; ++a) {
+        dl.assign(n - 1, -ih2);
+        du.assign(n - 1, -ih2);
+        d.resize(n);
+        for (int i = 0; i < n; ++i) {
+            bool bnd = (i == 0 || i == n - 1);
+            d[i] = (bnd ? ih2 : 2.0 * ih2) + sig[a] * (bnd ? 0.5 : 1.0);
+            if (bnd) d[i] -= cplx(0, tau);
+        }
+        if (!tri_lu(n, dl, d, du, du2, piv)) return fail(SG_ESETUP, "singular mean-block tridiagonal system");
+        for (int i = 0; i < n; ++i) {
+            cplx inv = 1.0 / d[i];
+            hdi[(size_t)i * nsys + a] = make_double2(inv.real(), inv.imag());
+        }
+        for (int i = 0; i < n - 1; ++i) {
+            hdl[(size_t)i * nsys + a] = make_double2(dl[i].real(), dl[i].imag());
+            hu1[(size_t)i * nsys + a] = make_double2(du[i].real(), du[i].imag());
+            hp[(size_t)i * nsys + a] = piv[i];
+        }
+        for (int i = 0; i < n - 2; ++i) hu2[(size_t)i * nsys + a] = make_double2(du2[i].real(), du2[i].imag());
+    }
+    tf.len = n;
+    tf.nsys = nsys;
+    SG_HIP(hipMalloc(&tf.dl, hdl.size() * sizeof(double2)));
+    SG_HIP(hipMalloc(&tf.dinv, hdi.size() * sizeof(double2)));
+    SG_HIP(hipMalloc(&tf.du1, hu1.size() * sizeof(double2)));
+    SG_HIP(hipMalloc(&tf.du2, hu2.size() * sizeof(double2)));
+    SG_HIP(hipMalloc(&tf.piv, hp.size()));
+    SG_HIP(hipMemcpy(tf.dl, hdl.data(), hdl.size() * sizeof(double2), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(tf.dinv, hdi.data(), hdi.size() * sizeof(double2), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(tf.du1, hu1.data(), hu1.size() * sizeof(double2), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(tf.du2, hu2.data(), hu2.size() * sizeof(double2), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(tf.piv, hp.data(), hp.size(), hipMemcpyHostToDevice));
+    return SG_OK;
+}
+
+static void free_tri(TriFactors& t) {
+    (void)hipFree(t.dl);
+    (void)hipFree(t.dinv);
+    (void)hipFree(t.du1);
+    (void)hipFree(t.du2);
+    (void)hipFree(t.piv);
+    t = TriFactors{};
+}
+
+Ctx::~Ctx() {
+    (void)hipFree(d_D2);
+    (void)hipFree(d_D1);
+    (void)hipFree(d_prog);
+    (void)hipFree(d_vals);
+    (void)hipFree(d_w);
+    (void)hipFree(fwd.f64);
+    (void)hipFree(fwd.f32);
+    (void)hipFree(fwd.bf_hi);
+    (void)hipFree(fwd.bf_lo);
+    (void)hipFree(inv.f64);
+    (void)hipFree(inv.f32);
+    (void)hipFree(inv.bf_hi);
+    (void)hipFree(inv.bf_lo);
+    for (auto& t : tri) free_tri(t);
+    (void)hipFree(ws.V);
+    (void)hipFree(ws.Z);
+    (void)hipFree(ws.tmp);
+    (void)hipFree(ws.scale);
+    (void)hipFree(ws.coef);
+    (void)hipFree(ws.partial);
+    if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
+    (void)hipFree(d_tmp_pc);
+}
+
+// ------------------------------------------------------------------ setup
+
+int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p || !out) return fail(SG_EINVAL, "null argument");
+    if (p->dim != 1 && p->dim != 2) return fail(SG_EINVAL, "dim must be 1 or 2");
+    if (p->bc != SG_BC_ABSORBING) return fail(SG_EINVAL, "only absorbing boundary conditions are supported");
+    if (p->n < 3 || p->n > 8192) return fail(SG_EINVAL, "n must be in [3, 8192]");
+    if (p->s < 1 || p->s > 8 || p->degree < 0 || p->degree > 8)
+        return fail(SG_EINVAL, "need 1 <= s <= 8 and 0 <= degree <= 8");
+    if (!p->k_fields) return fail(SG_EINVAL, "k_fields is null");
+    std::unique_ptr<Ctx> c(new Ctx());
+    SG_HIP(hipGetDevice(&c->device));
+    c->dim = p->dim;
+    c->n = p->n;
+    c->s = p->s;
+    c->degree = p->degree;
+    c->h = 1.0 / (p->n - 1);
+    c->kbar = p->k_mean;
+    c->beta = p->csl_beta;
+    c->P = 1;
+    for (int d = 0; d < p->dim; ++d) c->P *= p->n;
+    const long long P = c->P;
+    const int s = p->s;
+    for (long long i = 0; i < P; ++i)
+        if (p->k_fields[i] != p->k_mean)
+            return fail(SG_EINVAL, "k_0 must be spatially constant and equal to k_mean");
+    if (!(p->k_mean > 0)) return fail(SG_EINVAL, "k_mean must be positive");
+
+    c->alpha = make_basis(s, p->degree);
+    c->Q = (int)(c->alpha.size() / s);
+    c->nvec = (long long)c->Q * P;
+    const int Q = c->Q;
+
+    // fields of k (degree <= 1) and k² (degree <= 2) in the Ψ_γ basis
+    auto unit = [&](int l) { std::vector<int> g(s, 0); g[l] = 1; return g; };
+    c->gamma1.push_back(std::vector<int>(s, 0));
+    for (int l = 0; l < s; ++l) c->gamma1.push_back(unit(l));
+    c->gamma2 = c->gamma1;
+    for (int l = 0; l < s; ++l) { auto g = std::vector<int>(s, 0); g[l] = 2; c->gamma2.push_back(g); }
+    for (int l = 0; l < s; ++l)
+        for (int m = l + 1; m < s; ++m) { auto g = std::vector<int>(s, 0); g[l] = 1; g[m] = 1; c->gamma2.push_back(g); }
+    build_coupling(c->alpha, Q, s, c->gamma2, c->K);
+    build_coupling(c->alpha, Q, s, c->gamma1, c->B);
+
+    const int n = p->n;
+    std::vector<double> dw(n, 1.0);
+    dw[0] = dw[n - 1] = 0.5;
+    std::vector<double> w(P), e(P);
+    for (long long idx = 0; idx < P; ++idx) {
+        if (p->dim == 1) {
+            w[idx] = dw[idx];
+            e[idx] = (idx == 0 || idx == n - 1) ? 1.0 : 0.0;
+        } else {
+            int i = (int)(idx % n), j = (int)(idx / n);
+            w[idx] = dw[i] * dw[j];
+            e[idx] = (i == 0 || j == 0 || i == n - 1 || j == n - 1) ? 1.0 : 0.0;
+        }
+    }
+    const int ng1 = (int)c->gamma1.size(), ng2 = (int)c->gamma2.size();
+    std::vector<double> D1((size_t)ng1 * P), D2((size_t)ng2 * P);
+    const double r3 = std::sqrt(3.0), r5 = std::sqrt(5.0);
+    for (long long idx = 0; idx < P; ++idx) {
+        const double k0 = p->k_fields[idx];
+        double sumsq = 0;
+        for (int l = 0; l < s; ++l) { double kl = p->k_fields[(size_t)(l + 1) * P + idx]; sumsq += kl * kl; }
+        int g = 0;
+        D2[(size_t)g * P + idx] = w[idx] * (k0 * k0 + sumsq / 3.0);
+        D1[(size_t)g * P + idx] = e[idx] / c->h * k0;
+        ++g;
+        for (int l = 0; l < s; ++l, ++g) {
+            double kl = p->k_fields[(size_t)(l + 1) * P + idx];
+            D2[(size_t)g * P + idx] = w[idx] * 2.0 * k0 * kl / r3;
+            D1[(size_t)g * P + idx] = e[idx] / c->h * kl / r3;
+        }
+        for (int l = 0; l < s; ++l, ++g) {
+            double kl = p->k_fields[(size_t)(l + 1) * P + idx];
+            D2[(size_t)g * P + idx] = w[idx] * 2.0 * kl * kl / (3.0 * r5);
+        }
+        for (int l = 0; l < s; ++l)
+            for (int m = l + 1; m < s; ++m, ++g) {
+                double kl = p->k_fields[(size_t)(l + 1) * P + idx];
+                double km = p->k_fields[(size_t)(m + 1) * P + idx];
+                D2[(size_t)g * P + idx] = w[idx] * 2.0 * kl * km / 3.0;
+            }
+    }
+
+    // packed integer program: K tables, B tables, output order (heaviest outputs first)
+    std::vector<int> prog;
+    auto put = [&](const std::vector<int>& v) { int off = (int)prog.size(); prog.insert(prog.end(), v.begin(), v.end()); return off; };
+    c->kprog_pairptr = put(c->K.pair_ptr);
+    c->kprog_pairj = put(c->K.pair_j);
+    c->kprog_termptr = put(c->K.term_ptr);
+    c->kprog_termfield = put(c->K.term_field);
+    c->bprog_pairptr = put(c->B.pair_ptr);
+    c->bprog_pairj = put(c->B.pair_j);
+    c->bprog_termptr = put(c->B.term_ptr);
+    c->bprog_termfield = put(c->B.term_field);
+    std::vector<int> order(Q);
+    for (int i = 0; i < Q; ++i) order[i] = i;
+    c->out_order_off = put(order);
+    std::vector<double> vals(c->K.term_val);
+    c->kvals_off = 0;
+    c->bvals_off = (int)vals.size();
+    vals.insert(vals.end(), c->B.term_val.begin(), c->B.term_val.end());
+
+    SG_HIP(hipMalloc(&c->d_D2, D2.size() * sizeof(double)));
+    SG_HIP(hipMalloc(&c->d_D1, D1.size() * sizeof(double)));
+    SG_HIP(hipMalloc(&c->d_prog, prog.size() * sizeof(int)));
+    SG_HIP(hipMalloc(&c->d_vals, std::max<size_t>(vals.size(), 1) * sizeof(double)));
+    SG_HIP(hipMalloc(&c->d_w, w.size() * sizeof(double)));
+    SG_HIP(hipMemcpy(c->d_D2, D2.data(), D2.size() * sizeof(double), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(c->d_D1, D1.data(), D1.size() * sizeof(double), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(c->d_prog, prog.data(), prog.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!vals.empty())
+        SG_HIP(hipMemcpy(c->d_vals, vals.data(), vals.size() * sizeof(double), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(c->d_w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+
+    // mean-block factors for A_0 (c = k̄²) and M_0 (c = (1+iβ)k̄²)
+    const double kb = p->k_mean;
+    const cplx cshift[2] = {cplx(kb * kb, 0.0), cplx(kb * kb, p->csl_beta * kb * kb)};
+    if (p->dim == 1) {
+        for (int t = 0; t < 2; ++t) {
+            std::vector<cplx> sig(1, -cshift[t]);
+            int rc = build_tri(n, c->h, kb, sig, c->tri[t]);
+            if (rc) return rc;
+        }
+    } else {
+        int rc = mean_eigen(n, c->h, kb, c->mu, c->Vt);
+        if (rc) return rc;
+        for (int t = 0; t < 2; ++t) {
+            std::vector<cplx> sig(n);
+            for (int a = 0; a < n; ++a) sig[a] = c->mu[a] - cshift[t];
+            rc = build_tri(n, c->h, kb, sig, c->tri[t]);
+            if (rc) return rc;
+        }
+        rc = upload_dense_b(c.get(), stream);
+        if (rc) return rc;
+    }
+    SG_HIP(hipMalloc(&c->d_tmp_pc, (size_t)c->nvec * sizeof(double2)));
+    SG_HIP(hipDeviceSynchronize());
+    c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = c.release();
+    return SG_OK;
+}
+
+}  // namespace sgi

@@ -1,0 +1,178 @@
+// Internal declarations shared by the host setup, the solver drivers and the kernel
+// launch wrappers of the SG Helmholtz library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sg.h"
+
+namespace sgi {
+
+using cplx = std::complex<double>;
+
+void set_error(const std::string& msg);
+const char* last_error();
+int fail(int code, const std::string& msg);
+
+#define SG_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return ::sgi::fail(SG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Coupling program of the matrix-free operator.  For output block i the pairs
+// [pair_ptr[i], pair_ptr[i+1]) list the input blocks j with a nonzero coupling; pair p
+// owns terms [term_ptr[p], term_ptr[p+1]) = (field index γ, triple-product value G_γ[i,j]).
+struct Coupling {
+    int nfield = 0;                     // number of coefficient fields
+    std::vector<int> pair_ptr;          // Q+1
+    std::vector<int> pair_j;            // npairs
+    std::vector<int> term_ptr;          // npairs+1
+    std::vector<int> term_field;        // nterms
+    std::vector<double> term_val;       // nterms
+};
+
+// One pivoted tridiagonal LU factorisation per system (row-partial pivoting).
+// Arrays are indexed [row * nsys + sys] so that consecutive systems are contiguous.
+struct TriFactors {
+    int len = 0, nsys = 0;
+    double2* dl = nullptr;    // multipliers l_i (row i+1 minus l_i * row i), len-1 rows
+    double2* dinv = nullptr;  // 1 / u_ii
+    double2* du1 = nullptr;   // u_{i,i+1}
+    double2* du2 = nullptr;   // u_{i,i+2}
+    uint8_t* piv = nullptr;   // 1 if rows i and i+1 were swapped at step i
+};
+
+// Expanded real form of a complex N×N matrix for the GEMM C = A·B, where A rows are
+// complex-interleaved: Bexp[2k+c][2n+d] with c,d ∈ {0,1} (see precond.hip).
+struct DenseB {
+    double* f64 = nullptr;     // [2N][2N]
+    float* f32 = nullptr;      // [2N][2N]
+    uint16_t* bf_hi = nullptr; // [2N][2N] bf16 bits, packed for the MFMA B operand
+    uint16_t* bf_lo = nullptr;
+};
+
+struct Workspace {
+    int m = 0;                 // restart length the buffers were sized for
+    bool flexible = false;
+    double2* V = nullptr;      // (m+1) vectors
+    double2* Z = nullptr;      // m vectors (flexible only)
+    double2* tmp = nullptr;    // 2 scratch vectors
+    double* scale = nullptr;   // m+1 lazy normalisation factors (device)
+    double2* coef = nullptr;   // device coefficient buffer (2*(m+2) complex)
+    double2* partial = nullptr;// reduction partials
+    int npartial_blocks = 0;
+    double2* host_pinned = nullptr; // pinned host mirror of coef
+};
+
+// Optional per-kernel-class event timing (sg_set_profiling / sg_kernel_times).
+struct Prof {
+    bool on = false;
+    double ms[SG_K_NKINDS] = {};
+    long long cnt[SG_K_NKINDS] = {};
+    double work[SG_K_NKINDS] = {};
+    struct Rec { hipEvent_t a, b; int kind; double work; };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get();
+    void begin(hipStream_t st, hipEvent_t* ev);
+    void end(int kind, double work, hipStream_t st, hipEvent_t ev);
+    int resolve();
+    void reset();
+    ~Prof();
+};
+extern thread_local Prof* g_prof;
+
+// RAII scope around one kernel launch: records events when profiling is on.
+struct KScope {
+    int kind;
+    double work;
+    hipStream_t st;
+    hipEvent_t ev = nullptr;
+    KScope(int k, double w, hipStream_t s) : kind(k), work(w), st(s) {
+        if (g_prof && g_prof->on) g_prof->begin(st, &ev);
+    }
+    ~KScope() {
+        if (ev && g_prof && g_prof->on) g_prof->end(kind, work, st, ev);
+    }
+};
+
+struct Ctx {
+    int dim = 0, n = 0, s = 0, degree = 0, Q = 0;
+    long long P = 0, nvec = 0;
+    double h = 0, kbar = 0, beta = 0;
+    int device = 0;
+    std::vector<int> alpha;            // Q*s multi-indices
+
+    Coupling K;                        // k² coupling (fields D2_γ = w·κ2_γ)
+    Coupling B;                        // boundary k coupling (fields D1_γ = (e/h)·κ1_γ)
+    std::vector<std::vector<int>> gamma2, gamma1;   // multi-indices of the fields
+
+    // device copies
+    double* d_D2 = nullptr;            // [K.nfield][P]
+    double* d_D1 = nullptr;            // [B.nfield][P]
+    int* d_prog = nullptr;             // packed integer tables (K then B)
+    double* d_vals = nullptr;          // packed term values (K then B)
+    int kprog_pairptr = 0, kprog_pairj = 0, kprog_termptr = 0, kprog_termfield = 0;
+    int bprog_pairptr = 0, bprog_pairj = 0, bprog_termptr = 0, bprog_termfield = 0;
+    int kvals_off = 0, bvals_off = 0;
+    int out_order_off = 0;             // output block order (load balance)
+    double* d_w = nullptr;             // node weights w (n^dim)
+
+    // mean-block fast diagonalisation (x direction) and y-direction tridiagonal factors
+    std::vector<cplx> Vt;              // eigenvectors, column a = v_a (N×N, row-major [x][a])
+    std::vector<cplx> mu;              // eigenvalues of (T - iτE)v = μ D v
+    DenseB fwd, inv;                   // B operands for R·Ṽ and W·Ṽᵀ
+    TriFactors tri[2];                 // [0]: mean value A_0, [1]: mean CSL M_0
+    TriFactors tri32[2];               // unused placeholder for reduced-precision factors
+
+    Workspace ws;
+    Prof prof;
+    double2* d_tmp_pc = nullptr;       // preconditioner intermediate (nvec complex)
+    double t_setup_ms = 0;
+
+    ~Ctx();
+};
+
+// setup.cpp
+int build_ctx(const sg_problem* prob, hipStream_t stream, Ctx** out);
+
+// apply.hip
+int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st);
+
+// precond.hip
+int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, hipStream_t st);
+int upload_dense_b(Ctx* c, hipStream_t st);
+
+// krylov.hip
+int ensure_workspace(Ctx* c, int m, bool flexible);
+int launch_multidot(long long n, int nv, const double2* V, long long ldv, const double* scale,
+                    const double2* w, double2* partial, int nblocks, hipStream_t st);
+int launch_reduce(int nblocks, int nv, const double2* partial, const double* scale, double2* out,
+                  hipStream_t st);
+int launch_axpy_dot(long long n, int nv, const double2* V, long long ldv, const double* scale,
+                    const double2* coef, double2* w, double2* partial, int nblocks, bool with_dot,
+                    hipStream_t st);
+int launch_norm2(long long n, const double2* x, double2* partial, int nblocks, hipStream_t st);
+int launch_reduce_norm(int nblocks, const double2* partial, double2* out, hipStream_t st);
+int launch_lincomb(long long n, int nv, const double2* V, long long ldv, const double* scale,
+                   const double2* coef, double2* x, hipStream_t st);
+int launch_axpby(long long n, double2 a, const double2* x, double2 b, const double2* y, double2* out,
+                 hipStream_t st);
+int launch_scale_copy(long long n, double a, const double2* x, double2* out, hipStream_t st);
+int reduction_blocks(long long n);
+
+// gmres.cpp
+int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_precond_cb cb,
+              void* user, bool flexible, sg_solve_stats* st, hipStream_t stream);
+int cgs2_step(long long n, int nv, const double2* V, long long ldv, const double* d_scale,
+              double2* w, double2* partial, int nblocks, double2* d_coef, double2* h_pinned,
+              hipStream_t st);
+
+}  // namespace sgi

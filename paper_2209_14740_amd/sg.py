@@ -1,0 +1,256 @@
+"""ctypes binding of ``libsg.so`` (include/sg.h).  Argument marshalling only.
+
+Tensors are torch ``complex128`` CUDA tensors used purely as device memory; the
+stream is torch's current stream unless one is given.  Every call raises
+``SGError`` on a negative status.  There is no fallback: if the native library is
+missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsg.so")
+
+SG_OK, SG_ENOTCONV, SG_FALLBACK_USED = 0, 1, 2
+SG_PC_NONE, SG_PC_MEAN, SG_PC_CSL_MEAN, SG_PC_MEAN_NET = 0, 1, 2, 3
+SG_PREC_F64, SG_PREC_F32, SG_PREC_BF16X3 = 0, 1, 2
+SG_BC_ABSORBING = 0
+
+PC = {"none": SG_PC_NONE, "mean": SG_PC_MEAN, "csl": SG_PC_CSL_MEAN, "net": SG_PC_MEAN_NET}
+PREC = {"f64": SG_PREC_F64, "f32": SG_PREC_F32, "bf16x3": SG_PREC_BF16X3}
+
+
+class SGError(RuntimeError):
+    pass
+
+
+class Problem(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int), ("bc", C.c_int), ("s", C.c_int), ("degree", C.c_int),
+                ("k_fields", C.POINTER(C.c_double)), ("k_mean", C.c_double), ("csl_beta", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("precond", C.c_int), ("precision", C.c_int),
+                ("tol", C.c_double), ("x0_zero", C.c_int), ("hist", C.POINTER(C.c_double)), ("hist_cap", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int), ("fallback", C.c_int),
+                ("relres_true", C.c_double), ("relres_est", C.c_double), ("t_setup", C.c_double),
+                ("t_precond", C.c_double), ("t_matvec", C.c_double), ("t_orth", C.c_double),
+                ("t_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PRECOND_CB = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def lib():
+    """Load libsg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libsg.so not built: run `python -m paper_2209_14740_amd.build`")
+    L = C.CDLL(_LIB_PATH)
+    vp, i, ll, d = C.c_void_p, C.c_int, C.c_longlong, C.c_double
+    L.sg_setup.argtypes = [C.POINTER(Problem), vp, C.POINTER(vp)]
+    L.sg_destroy.argtypes = [vp]
+    L.sg_destroy.restype = None
+    L.sg_basis.argtypes = [vp, C.POINTER(i), C.POINTER(i)]
+    L.sg_size.argtypes = [vp]
+    L.sg_size.restype = ll
+    L.sg_rhs.argtypes = [vp, C.POINTER(d), vp, vp]
+    L.sg_apply.argtypes = [vp, vp, vp, vp]
+    L.sg_precond.argtypes = [vp, i, i, vp, vp, vp]
+    L.sg_gmres.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
+    L.sg_fgmres.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), PRECOND_CB, vp, C.POINTER(SolveStats), vp]
+    L.sg_cgs2.argtypes = [ll, i, vp, vp, vp, vp]
+    L.sg_norm.argtypes = [ll, vp, C.POINTER(d), vp]
+    L.sg_set_profiling.argtypes = [vp, i]
+    L.sg_kernel_times.argtypes = [vp, i, C.POINTER(d), C.POINTER(ll), C.POINTER(d)]
+    L.sg_strerror.argtypes = [i]
+    L.sg_strerror.restype = C.c_char_p
+    L.sg_last_error.argtypes = []
+    L.sg_last_error.restype = C.c_char_p
+    for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
+                 "sg_cgs2", "sg_norm", "sg_set_profiling", "sg_kernel_times"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int, what: str) -> int:
+    if rc < 0:
+        msg = lib().sg_last_error().decode(errors="replace")
+        raise SGError("%s failed: %s (%s)" % (what, lib().sg_strerror(rc).decode(), msg))
+    return rc
+
+
+def _ptr(t) -> int:
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise SGError("expected a contiguous complex128 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class SG:
+    """One stochastic-Galerkin Helmholtz operator (a handle of the native library)."""
+
+    def __init__(self, dim: int, n: int, s: int, degree: int, k_fields, k_mean: float, beta: float = 0.5,
+                 stream=None):
+        self._h = C.c_void_p()
+        kf = np.ascontiguousarray(k_fields, dtype=np.float64)
+        if kf.shape != (s + 1, n ** dim):
+            raise SGError("k_fields must have shape (s+1, n**dim)")
+        self._kf = kf
+        prob = Problem(dim, n, SG_BC_ABSORBING, s, degree, kf.ctypes.data_as(C.POINTER(C.c_double)),
+                       float(k_mean), float(beta))
+        check(lib().sg_setup(C.byref(prob), C.c_void_p(_stream(stream)), C.byref(self._h)), "sg_setup")
+        self.dim, self.n, self.s, self.degree = dim, n, s, degree
+        q = C.c_int()
+        check(lib().sg_basis(self._h, C.byref(q), None), "sg_basis")
+        self.Q = q.value
+        self.size = int(lib().sg_size(self._h))
+        self._cb_keep = None
+
+    @classmethod
+    def from_instance(cls, inst, stream=None):
+        return cls(inst.dim, inst.n, inst.s, inst.degree, inst.k_fields, inst.k_mean, inst.beta, stream)
+
+    def close(self):
+        if self._h:
+            lib().sg_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def basis(self) -> np.ndarray:
+        q = C.c_int()
+        out = (C.c_int * (self.Q * self.s))()
+        check(lib().sg_basis(self._h, C.byref(q), out), "sg_basis")
+        return np.frombuffer(out, dtype=np.int32).reshape(self.Q, self.s).copy()
+
+    def empty(self):
+        import torch
+        return torch.empty(self.size, dtype=torch.complex128, device="cuda")
+
+    def rhs(self, f, out=None, stream=None):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        b = self.empty() if out is None else out
+        check(lib().sg_rhs(self._h, f.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(_ptr(b)),
+                           C.c_void_p(_stream(stream))), "sg_rhs")
+        return b
+
+    def apply(self, x, y=None, stream=None):
+        y = self.empty() if y is None else y
+        check(lib().sg_apply(self._h, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)), C.c_void_p(_stream(stream))),
+              "sg_apply")
+        return y
+
+    def precond(self, r, z=None, pc: str = "mean", precision: str = "f64", stream=None):
+        z = self.empty() if z is None else z
+        check(lib().sg_precond(self._h, PC[pc], PREC[precision], C.c_void_p(_ptr(r)), C.c_void_p(_ptr(z)),
+                               C.c_void_p(_stream(stream))), "sg_precond")
+        return z
+
+    def _opts(self, restart, maxit, pc, precision, tol, x0_zero, hist):
+        harr = None
+        if hist:
+            harr = (C.c_double * maxit)()
+        o = SolveOpts(restart, maxit, PC[pc], PREC[precision], tol, 1 if x0_zero else 0,
+                      C.cast(harr, C.POINTER(C.c_double)) if harr is not None else None, maxit if hist else 0)
+        return o, harr
+
+    def gmres(self, b, x=None, restart=50, maxit=1000, pc="mean", precision="f64", tol=1e-8, x0_zero=True,
+              hist=False, stream=None):
+        x = self.empty() if x is None else x
+        o, harr = self._opts(restart, maxit, pc, precision, tol, x0_zero, hist)
+        st = SolveStats()
+        rc = check(lib().sg_gmres(self._h, C.c_void_p(_ptr(b)), C.c_void_p(_ptr(x)), C.byref(o), C.byref(st),
+                                  C.c_void_p(_stream(stream))), "sg_gmres")
+        info = st.as_dict()
+        info["status"] = rc
+        if hist:
+            info["hist"] = list(harr)[: st.iters]
+        return x, info
+
+    def fgmres(self, b, x=None, restart=50, maxit=1000, pc="mean", precision="f64", tol=1e-8, x0_zero=True,
+               hist=False, callback=None, stream=None):
+        """Flexible GMRES; ``callback(r, z)`` (torch tensors) replaces the built-in preconditioner."""
+        import torch
+        x = self.empty() if x is None else x
+        o, harr = self._opts(restart, maxit, pc, precision, tol, x0_zero, hist)
+        st = SolveStats()
+        cb = PRECOND_CB()
+        if callback is not None:
+            n = self.size
+
+            def _tramp(user, r, z, s):
+                try:
+                    rt = _wrap_device(r, n)
+                    zt = _wrap_device(z, n)
+                    callback(rt, zt)
+                    return 0
+                except Exception:
+                    return 1
+            cb = PRECOND_CB(_tramp)
+            self._cb_keep = cb
+        rc = check(lib().sg_fgmres(self._h, C.c_void_p(_ptr(b)), C.c_void_p(_ptr(x)), C.byref(o), cb, None,
+                                   C.byref(st), C.c_void_p(_stream(stream))), "sg_fgmres")
+        info = st.as_dict()
+        info["status"] = rc
+        if hist:
+            info["hist"] = list(harr)[: st.iters]
+        return x, info
+
+
+def _wrap_device(ptr, n):
+    """View a raw device pointer of n complex128 values as a torch tensor (no copy)."""
+    import torch
+
+    class _Holder:
+        pass
+
+    h = _Holder()
+    h.__cuda_array_interface__ = {"shape": (n,), "typestr": "<c16", "data": (ptr, False), "version": 2,
+                                  "strides": None}
+    return torch.as_tensor(h, device="cuda")
+
+
+def cgs2(V, w, stream=None):
+    """One CGS2 step against the orthonormal rows of V (nv × n); returns h (nv+1,) and normalises w."""
+    nv, n = V.shape
+    out = (C.c_double * (2 * (nv + 1)))()
+    check(lib().sg_cgs2(n, nv, C.c_void_p(_ptr(V)), C.c_void_p(_ptr(w)), out, C.c_void_p(_stream(stream))),
+          "sg_cgs2")
+    a = np.frombuffer(out, dtype=np.float64)
+    return a[0::2] + 1j * a[1::2]
+
+
+def norm(x, stream=None) -> float:
+    out = C.c_double()
+    check(lib().sg_norm(x.numel(), C.c_void_p(_ptr(x)), C.byref(out), C.c_void_p(_stream(stream))), "sg_norm")
+    return out.value
+
+
+EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
+            "sg_fgmres", "sg_cgs2", "sg_norm", "sg_set_profiling", "sg_kernel_times", "sg_strerror",
+            "sg_last_error"]

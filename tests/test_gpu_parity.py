@@ -1,0 +1,294 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Tolerances (derived from the arithmetic, stated per check):
+  * sg_apply, FP64: componentwise |y - y_ref| <= 1e-12 · (|A| |x|) — a different summation
+    order of at most a few hundred FP64 terms per row changes each row by a few ulps of
+    the row's absolute sum.
+  * sg_precond, FP64: ||z - z_ref||_∞ <= 1e-9 ||z_ref||_∞ — the fast diagonalisation is
+    exact up to rounding amplified by κ(S̄)·cond(Ṽ)² (κ(S̄) <= 1e4, cond(Ṽ) <= 8 at the
+    sizes used), versus the oracle's sparse LU.
+  * sg_precond, FP32 / BF16x3: ||z - z_ref||_∞ <= 2e-4 / 2e-3 ||z_ref||_∞ — unit roundoff
+    6e-8 (FP32) and 2^-16 ≈ 1.5e-5 (BF16x3 hi·hi+hi·lo+lo·hi) amplified the same way.
+  * solves: true relative residual (recomputed by the oracle's assembled A) <= tol and
+    relative solution error against the oracle's direct solve <= 1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import assemble, krylov, precond
+from workloads import config1, config2, config3, small_2d
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2209_14740_amd import sg  # noqa: E402
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rand_vec(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+_SYS = {}
+_XREF = {}
+
+
+def reference_solution(key, S):
+    """Oracle solution: sparse direct for small systems, else oracle GMRES to 1e-12."""
+    if key not in _XREF:
+        if S.A.shape[0] <= 60_000:
+            _XREF[key] = precond.direct_solve(S)
+        else:
+            x, info = krylov.gmres(lambda v: S.A @ v, S.b, precond.mean_value(S), restart=60, tol=1e-12,
+                                   maxit=400)
+            assert info.converged
+            _XREF[key] = x
+    return _XREF[key]
+
+
+def oracle_sys(key, inst):
+    if key not in _SYS:
+        _SYS[key] = assemble.from_instance(inst)
+    return _SYS[key]
+
+
+SMALL = {
+    "c1_1d": config1,
+    "2d_n150_s3_r3": lambda: small_2d(n=150, kbar=12.0, sigma=1.2, s=3, degree=3),
+    "2d_n37_s2_r4": lambda: small_2d(n=37, kbar=7.0, sigma=1.4, s=2, degree=4),
+    "2d_n3_min": lambda: small_2d(n=3, kbar=2.0, sigma=0.2, s=1, degree=1),
+    "2d_n66_s1_r0": lambda: small_2d(n=66, kbar=9.0, sigma=0.9, s=1, degree=0),
+}
+
+
+def test_basis_order_matches_oracle():
+    for key in ("c1_1d", "2d_n150_s3_r3", "2d_n37_s2_r4"):
+        inst = SMALL[key]()
+        op = sg.SG.from_instance(inst)
+        S = oracle_sys(key, inst)
+        np.testing.assert_array_equal(op.basis(), S.alpha)
+        assert op.Q == S.Q and op.size == S.A.shape[0]
+
+
+@pytest.mark.parametrize("key", list(SMALL))
+def test_apply_parity_small(key):
+    inst = SMALL[key]()
+    print("apply parity", key, flush=True)
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    x = rand_vec(S.A.shape[0], 1)
+    y = to_host(op.apply(to_dev(x)))
+    ref = S.A @ x
+    bound = abs(S.A) @ np.abs(x)
+    assert np.all(np.abs(y - ref) <= 1e-12 * bound + 1e-300), np.max(np.abs(y - ref) / bound)
+
+
+@pytest.mark.parametrize("key", ["c1_1d", "2d_n150_s3_r3", "2d_n37_s2_r4"])
+def test_rhs_parity(key):
+    inst = SMALL[key]()
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    b = to_host(op.rhs(inst.f))
+    np.testing.assert_array_equal(b, S.b)
+
+
+@pytest.mark.parametrize("which", ["c2", "c3"])
+def test_apply_parity_full_size_sampled(which):
+    """Full config sizes: sampled rows (corners, edges, interior, random) against the
+    oracle's point-by-point evaluation."""
+    inst = config2() if which == "c2" else config3()
+    print("apply full", which, flush=True)
+    op = sg.SG.from_instance(inst)
+    P, n = inst.points, inst.n
+    x = rand_vec(op.size, 2)
+    y = to_host(op.apply(to_dev(x))).reshape(op.Q, P)
+    rng = np.random.default_rng(3)
+    pts = {0, n - 1, P - n, P - 1, n // 2, (n // 2) * n, (n // 2) * n + n - 1, P - 1 - n // 2,
+           (n // 2) * n + n // 2, 63, 64, 65, 127, 128}
+    pts |= set(rng.integers(0, P, 120).tolist())
+    pts = np.array(sorted(pts))
+    ref = assemble.apply_at_points(inst, x, pts)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(y[:, pts] - ref)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("key", ["c1_1d", "2d_n150_s3_r3", "2d_n37_s2_r4", "2d_n3_min"])
+@pytest.mark.parametrize("pc", ["mean", "csl"])
+def test_precond_parity_f64(key, pc):
+    inst = SMALL[key]()
+    print("precond", key, pc, flush=True)
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    r = rand_vec(S.A.shape[0], 4)
+    P = precond.mean_value(S) if pc == "mean" else precond.mean_csl(S, inst.beta)
+    ref = P(r)
+    z = to_host(op.precond(to_dev(r), pc=pc, precision="f64"))
+    err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-9, err
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 2e-4), ("bf16x3", 2e-3)])
+@pytest.mark.parametrize("key", ["2d_n150_s3_r3", "2d_n37_s2_r4"])
+def test_precond_parity_mixed(key, precision, tol):
+    inst = SMALL[key]()
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    r = rand_vec(S.A.shape[0], 5)
+    ref = precond.mean_value(S)(r)
+    z = to_host(op.precond(to_dev(r), pc="mean", precision=precision))
+    err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+    print("precond", precision, key, "rel err", err, flush=True)
+    assert err <= tol, err
+
+
+def test_precond_in_place_alias():
+    inst = SMALL["2d_n37_s2_r4"]()
+    op = sg.SG.from_instance(inst)
+    r = to_dev(rand_vec(op.size, 6))
+    z = op.precond(r.clone(), pc="mean")
+    r2 = r.clone()
+    op.precond(r2, r2, pc="mean")
+    np.testing.assert_array_equal(to_host(r2), to_host(z))
+
+
+def test_cgs2_parity():
+    rng = np.random.default_rng(7)
+    n, nv = 10_000 + 37, 7
+    M = rng.standard_normal((n, nv)) + 1j * rng.standard_normal((n, nv))
+    Vq, _ = np.linalg.qr(M)
+    V = np.ascontiguousarray(Vq.T)
+    w = rand_vec(n, 8)
+    ref_h = V.conj() @ w
+    wperp = w - V.T @ ref_h
+    wd = to_dev(w)
+    h = sg.cgs2(to_dev(V), wd)
+    out = to_host(wd)
+    assert np.max(np.abs(h[:nv] - ref_h)) <= 1e-13 * np.linalg.norm(w)
+    assert abs(h[nv] - np.linalg.norm(wperp)) <= 1e-13 * np.linalg.norm(w)
+    assert abs(np.linalg.norm(out) - 1.0) <= 1e-14
+    assert np.max(np.abs(V.conj() @ out)) <= 1e-14
+
+
+def test_norm_parity():
+    x = rand_vec(123_457, 9)
+    assert abs(sg.norm(to_dev(x)) - np.linalg.norm(x)) <= 1e-14 * np.linalg.norm(x)
+
+
+# ------------------------------------------------------------------- solves
+
+def _check_solution(S, x, tol, xd=None):
+    relres = np.linalg.norm(S.b - S.A @ x) / np.linalg.norm(S.b)
+    assert relres <= tol * 1.0000001, relres
+    if xd is not None:
+        err = np.max(np.abs(x - xd)) / np.max(np.abs(xd))
+        assert err <= 1e-6, err
+
+
+@pytest.mark.parametrize("pc", ["none", "mean", "csl"])
+def test_gmres_config1(pc):
+    inst = config1()
+    S = oracle_sys("c1_1d", inst)
+    xd = reference_solution("c1_1d", S)
+    op = sg.SG.from_instance(inst)
+    b = op.rhs(inst.f)
+    x, info = op.gmres(b, restart=30, maxit=20000, pc=pc, tol=1e-10)
+    print("c1", pc, info["iters"], info["relres_true"], flush=True)
+    assert info["converged"] == 1 and info["status"] == 0
+    _check_solution(S, to_host(x), 1e-10, xd)
+
+
+@pytest.mark.parametrize("pc", ["mean", "csl"])
+def test_gmres_matches_oracle_iterations(pc):
+    """Same Krylov space: CGS2 on the GPU and MGS in the oracle give the same iteration
+    count (±1 for rounding at the stopping test) and the same solution."""
+    key = "2d_n37_s2_r4"
+    inst = SMALL[key]()
+    S = oracle_sys(key, inst)
+    P = precond.mean_value(S) if pc == "mean" else precond.mean_csl(S, inst.beta)
+    xo, io = krylov.gmres(lambda v: S.A @ v, S.b, P, restart=20, tol=1e-10, maxit=2000)
+    op = sg.SG.from_instance(inst)
+    x, info = op.gmres(op.rhs(inst.f), restart=20, maxit=2000, pc=pc, tol=1e-10)
+    assert abs(info["iters"] - io.iters) <= 1, (info["iters"], io.iters)
+    _check_solution(S, to_host(x), 1e-10, reference_solution(key, S))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x3"])
+def test_fgmres_mixed_small(precision):
+    key = "2d_n150_s3_r3"
+    inst = SMALL[key]()
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    x, info = op.fgmres(op.rhs(inst.f), restart=30, maxit=500, pc="mean", precision=precision, tol=1e-10)
+    print("fgmres", precision, info["iters"], info["relres_true"], flush=True)
+    assert info["converged"] == 1
+    _check_solution(S, to_host(x), 1e-10, reference_solution(key, S))
+
+
+def test_fgmres_callback_matches_builtin():
+    key = "2d_n37_s2_r4"
+    inst = SMALL[key]()
+    op = sg.SG.from_instance(inst)
+    b = op.rhs(inst.f)
+    x1, i1 = op.fgmres(b, restart=20, maxit=500, pc="mean", tol=1e-10)
+    x2, i2 = op.fgmres(b, restart=20, maxit=500, tol=1e-10,
+                       callback=lambda r, z: op.precond(r, z, pc="mean"))
+    assert i1["iters"] == i2["iters"]
+    np.testing.assert_allclose(to_host(x2), to_host(x1), rtol=0, atol=1e-12 * float(x1.abs().max()))
+
+
+def test_gmres_config2_full():
+    """Config 2 at full size, mean-value preconditioner, GMRES(50) to 1e-8; true residual
+    recomputed with the oracle's assembled matrix."""
+    inst = config2()
+    print("c2 solve", flush=True)
+    op = sg.SG.from_instance(inst)
+    x, info = op.gmres(op.rhs(inst.f), restart=50, maxit=500, pc="mean", tol=1e-8)
+    assert info["converged"] == 1
+    S = oracle_sys("c2", inst)
+    _check_solution(S, to_host(x), 1e-8)
+
+
+# --------------------------------------------------------------- edge cases
+
+def test_sigma_zero_one_step():
+    """σ = 0: A = A_0, so A_0-preconditioned GMRES converges in one iteration (breakdown of
+    the Krylov space is the exact solution, Remark 6.1)."""
+    inst = small_2d(n=33, kbar=6.0, sigma=0.0, s=2, degree=2)
+    op = sg.SG.from_instance(inst)
+    x, info = op.gmres(op.rhs(inst.f), restart=10, maxit=10, pc="mean", tol=1e-10)
+    assert info["iters"] == 1 and info["converged"] == 1
+    S = assemble.from_instance(inst)
+    _check_solution(S, to_host(x), 1e-10, precond.direct_solve(S))
+
+
+def test_maxit_returns_not_converged():
+    inst = config1()
+    op = sg.SG.from_instance(inst)
+    x, info = op.gmres(op.rhs(inst.f), restart=5, maxit=3, pc="none", tol=1e-12)
+    assert info["status"] == sg.SG_ENOTCONV and info["converged"] == 0 and info["iters"] == 3
+
+
+def test_invalid_arguments_raise():
+    inst = small_2d(n=17)
+    kf = inst.k_fields.copy()
+    kf[0, 5] += 1.0   # k_0 not constant
+    with pytest.raises(sg.SGError):
+        sg.SG(2, inst.n, inst.s, inst.degree, kf, inst.k_mean)
+    op = sg.SG.from_instance(inst)
+    b = op.rhs(inst.f)
+    with pytest.raises(sg.SGError):
+        op.gmres(b, restart=0)
+    with pytest.raises(sg.SGError):
+        op.apply(b, b)          # aliasing is rejected

@@ -411,3 +411,14 @@ def test_restarted_and_flexible_variants_converge():
             x, info = krylov.gmres(A, S.b, P, restart=30, tol=1e-10, maxit=2000, flexible=flex)
             assert info.converged and info.relres_true <= 1e-10
             assert np.max(np.abs(x - xd)) <= 1e-7 * np.max(np.abs(xd))
+
+
+def test_pointwise_rows_equal_assembled_matrix():
+    """The point-by-point evaluation used for sampled checks equals rows of the assembled A."""
+    for inst in (config1(), small_2d(n=13, s=3, degree=2)):
+        S = assemble.from_instance(inst)
+        rng = np.random.default_rng(5)
+        x = rng.standard_normal(S.A.shape[0]) + 1j * rng.standard_normal(S.A.shape[0])
+        pts = np.array([0, 1, S.P // 2, S.P - 1])
+        full = (S.A @ x).reshape(S.Q, S.P)[:, pts]
+        np.testing.assert_allclose(assemble.apply_at_points(inst, x, pts), full, rtol=1e-13, atol=1e-9)
