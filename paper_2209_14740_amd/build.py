@@ -19,15 +19,16 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsg.so")
 
-SOURCES = ["setup.cpp", "prof.cpp", "abi.cpp", "gmres.cpp", "apply.hip", "precond.hip", "krylov.hip"]
+SOURCES = ["apply_spec_g0.hip", "apply_spec_g1.hip", "apply_spec_g2.hip", "apply_spec_g3.hip", "setup.cpp",
+           "prof.cpp", "abi.cpp", "gmres.cpp", "apply.hip", "precond.hip", "krylov.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+    "-O3", "-std=c++20", "-fPIC", "--offload-arch=" + ARCH,
     # never let the compiler form packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-result", "-I" + INCLUDE, "-I" + CSRC,
+    "-fconstexpr-steps=400000000", "-Wno-unused-result", "-I" + INCLUDE, "-I" + CSRC,
 ]
 
 

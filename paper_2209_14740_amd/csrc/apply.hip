@@ -12,7 +12,7 @@
 // consecutive rows on one XCD so that the y-neighbour rows are L2 hits.
 #include <hip/hip_runtime.h>
 
-#include "sg_internal.h"
+#include "apply_args.h"
 
 namespace sgi {
 
@@ -21,19 +21,7 @@ namespace {
 constexpr int TILE = 64;
 constexpr int TPAD = TILE + 2;
 
-struct ApplyArgs {
-    const double2* x;
-    double2* y;
-    const double* D2;
-    const double* D1;
-    const int* prog;
-    const double* vals;
-    long long P;
-    int n, Q, ng2, ng1, dim;
-    double ih2;
-    int kpp, kpj, ktp, ktf, bpp, bpj, btp, btf, kv, bv;
-    int ntiles_x, nrows;
-};
+
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -172,6 +160,18 @@ int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st) {
     a.bv = c->bvals_off;
     a.ntiles_x = (c->n + TILE - 1) / TILE;
     a.nrows = c->dim == 2 ? c->n : 1;
+    a.KF = c->d_kf;
+    a.k0 = c->kbar;
+    a.ih = 1.0 / c->h;
+    if (c->use_spec_apply) {
+        KScope ks(SG_K_APPLY, (double)c->P * (32.0 * c->Q + 8.0 * c->s), st);
+        const int sv = c->s, rv = c->degree;
+        if (dispatch_spec_g0(sv, rv, a, st) || dispatch_spec_g1(sv, rv, a, st) ||
+            dispatch_spec_g2(sv, rv, a, st) || dispatch_spec_g3(sv, rv, a, st)) {
+            SG_HIP(hipGetLastError());
+            return SG_OK;
+        }
+    }
     const size_t lds = (size_t)c->Q * TPAD * sizeof(double2) + (size_t)c->K.nfield * TILE * sizeof(double);
     if (lds > 160 * 1024) return fail(SG_EINVAL, "sg_apply: Q too large for the LDS tile");
     static bool attr_set = false;

@@ -1,0 +1,35 @@
+// Shared declarations of the SG operator kernels (generic and shape-specialised).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "sg_internal.h"
+
+namespace sgi {
+
+struct ApplyArgs {
+    const double2* x;
+    double2* y;
+    const double* D2;
+    const double* D1;
+    const int* prog;
+    const double* vals;
+    long long P;
+    int n, Q, ng2, ng1, dim;
+    double ih2;
+    int kpp, kpj, ktp, ktf, bpp, bpj, btp, btf, kv, bv;
+    int ntiles_x, nrows;
+    const double* KF;     // k_1..k_s at the nodes ([s][P]) for the shape-specialised kernels
+    double k0, ih;        // constant mean k_0 and 1/h
+};
+
+// Shape-specialised operator launchers, one translation unit per group of (s, r)
+// shapes (apply_spec_g*.hip); each returns 1 if it handled (s, r), else 0.
+int dispatch_spec_g0(int s, int r, const ApplyArgs& a, hipStream_t st);
+int dispatch_spec_g1(int s, int r, const ApplyArgs& a, hipStream_t st);
+int dispatch_spec_g2(int s, int r, const ApplyArgs& a, hipStream_t st);
+int dispatch_spec_g3(int s, int r, const ApplyArgs& a, hipStream_t st);
+
+}  // namespace sgi

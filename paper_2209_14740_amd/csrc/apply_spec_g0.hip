@@ -1,0 +1,9 @@
+// Instantiations of the shape-specialised SG operator: (6, 3).
+#include "apply_spec.inc"
+
+namespace sgi {
+int dispatch_spec_g0(int s, int r, const ApplyArgs& a, hipStream_t st) {
+    SG_SPEC(6, 3)
+    return 0;
+}
+}  // namespace sgi

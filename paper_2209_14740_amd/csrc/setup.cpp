@@ -346,6 +346,7 @@ Ctx::~Ctx() {
     (void)hipFree(d_prog);
     (void)hipFree(d_vals);
     (void)hipFree(d_w);
+    (void)hipFree(d_kf);
     (void)hipFree(fwd.f64);
     (void)hipFree(fwd.f32);
     (void)hipFree(fwd.bf_hi);
@@ -482,6 +483,8 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     if (!vals.empty())
         SG_HIP(hipMemcpy(c->d_vals, vals.data(), vals.size() * sizeof(double), hipMemcpyHostToDevice));
     SG_HIP(hipMemcpy(c->d_w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+    SG_HIP(hipMalloc(&c->d_kf, (size_t)s * P * sizeof(double)));
+    SG_HIP(hipMemcpy(c->d_kf, p->k_fields + P, (size_t)s * P * sizeof(double), hipMemcpyHostToDevice));
 
     // mean-block factors for A_0 (c = k̄²) and M_0 (c = (1+iβ)k̄²)
     const double kb = p->k_mean;

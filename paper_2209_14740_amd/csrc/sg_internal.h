@@ -124,6 +124,7 @@ struct Ctx {
     int kvals_off = 0, bvals_off = 0;
     int out_order_off = 0;             // output block order (load balance)
     double* d_w = nullptr;             // node weights w (n^dim)
+    double* d_kf = nullptr;            // k_1..k_s at the nodes ([s][P])
 
     // mean-block fast diagonalisation (x direction) and y-direction tridiagonal factors
     std::vector<cplx> Vt;              // eigenvectors, column a = v_a (N×N, row-major [x][a])
@@ -134,6 +135,7 @@ struct Ctx {
 
     Workspace ws;
     Prof prof;
+    bool use_spec_apply = true;        // compile-time-specialised operator when available
     double2* d_tmp_pc = nullptr;       // preconditioner intermediate (nvec complex)
     double t_setup_ms = 0;
 

@@ -70,6 +70,7 @@ SMALL = {
     "2d_n37_s2_r4": lambda: small_2d(n=37, kbar=7.0, sigma=1.4, s=2, degree=4),
     "2d_n3_min": lambda: small_2d(n=3, kbar=2.0, sigma=0.2, s=1, degree=1),
     "2d_n66_s1_r0": lambda: small_2d(n=66, kbar=9.0, sigma=0.9, s=1, degree=0),
+    "2d_n41_s5_r2": lambda: small_2d(n=41, kbar=6.0, sigma=0.6, s=5, degree=2),   # generic kernel
 }
 
 
