@@ -57,12 +57,22 @@ int ensure_workspace(Ctx* c, int m, bool flexible) {
 int cgs2_step(long long n, int nv, const double2* V, long long ldv, const double* d_scale, double2* w,
               double2* partial, int nblocks, double2* d_coef, double2* h_pinned, hipStream_t st) {
     int rc;
-    for (int pass = 0; pass < 2; ++pass) {
+    // pass 1 projection
+    if ((rc = launch_multidot(n, nv, V, ldv, d_scale, w, partial, nblocks, st))) return rc;
+    if ((rc = launch_reduce(nblocks, nv, partial, d_scale, d_coef, st))) return rc;
+    // pass 1 update fused with the pass 2 projection, pass 2 update fused with the norm
+    int fused = launch_upd(n, nv, V, ldv, d_scale, d_coef, w, partial, nblocks, true, st);
+    if (fused < 0) return fused;
+    if (fused) {
+        if ((rc = launch_reduce(nblocks, nv, partial, d_scale, d_coef + nv, st))) return rc;
+        if ((rc = launch_upd(n, nv, V, ldv, d_scale, d_coef + nv, w, partial, nblocks, false, st)) < 0) return rc;
+    } else {
+        if ((rc = launch_axpy_dot(n, nv, V, ldv, d_scale, d_coef, w, nullptr, 0, false, st))) return rc;
         if ((rc = launch_multidot(n, nv, V, ldv, d_scale, w, partial, nblocks, st))) return rc;
-        if ((rc = launch_reduce(nblocks, nv, partial, d_scale, d_coef + pass * nv, st))) return rc;
-        if ((rc = launch_axpy_dot(n, nv, V, ldv, d_scale, d_coef + pass * nv, w, nullptr, 0, false, st))) return rc;
+        if ((rc = launch_reduce(nblocks, nv, partial, d_scale, d_coef + nv, st))) return rc;
+        if ((rc = launch_axpy_dot(n, nv, V, ldv, d_scale, d_coef + nv, w, nullptr, 0, false, st))) return rc;
+        if ((rc = launch_norm2(n, w, partial, nblocks, st))) return rc;
     }
-    if ((rc = launch_norm2(n, w, partial, nblocks, st))) return rc;
     if ((rc = launch_reduce_norm(nblocks, partial, d_coef + 2 * nv, st))) return rc;
     SG_HIP(hipMemcpyAsync(h_pinned, d_coef, (size_t)(2 * nv + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
     SG_HIP(hipStreamSynchronize(st));

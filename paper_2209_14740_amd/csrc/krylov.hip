@@ -146,6 +146,71 @@ __global__ __launch_bounds__(RB) void k_axpy(long long n, int nv, const double2*
     }
 }
 
+// Fused CGS2 passes.  For every element i (grid-stride), with c_k = -scale[k]·coef[k]:
+//   w_new[i] = w[i] + Σ_k c_k V_k[i]            (update of the previous pass)
+//   DOT:  partial[b][k] += conj(V_k[i]) · w_new[i]   (projection of the next pass)
+//   NORM: partial[b][0] += |w_new[i]|²
+// The V_k[i] values of the update stay in registers for the projection, so V is read once.
+template <int NV, bool DOT>
+__global__ __launch_bounds__(RB) void k_upd(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                            const double* __restrict__ scale, const double2* __restrict__ coef,
+                                            double2* __restrict__ w, double2* __restrict__ partial) {
+    __shared__ double2 c[NV];
+    __shared__ double2 red[(RB / 64) * NV];
+    for (int k = threadIdx.x; k < nv; k += RB) {
+        const double sk = -(scale ? scale[k] : 1.0);
+        c[k] = make_double2(coef[k].x * sk, coef[k].y * sk);
+    }
+    __syncthreads();
+    constexpr int NA = DOT ? NV : 1;
+    double2 acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
+        double2 v[NV];
+        double2 wi = w[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nv) {
+                v[k] = V[(long long)k * ldv + i];
+                const double2 ck = c[k];
+                wi.x = fma(v[k].x, ck.x, fma(-v[k].y, ck.y, wi.x));
+                wi.y = fma(v[k].x, ck.y, fma(v[k].y, ck.x, wi.y));
+            }
+        w[i] = wi;
+        if constexpr (DOT) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                if (k < nv) {
+                    acc[k].x = fma(v[k].x, wi.x, fma(v[k].y, wi.y, acc[k].x));
+                    acc[k].y = fma(v[k].x, wi.y, fma(-v[k].y, wi.x, acc[k].y));
+                }
+        } else {
+            acc[0].x = fma(wi.x, wi.x, fma(wi.y, wi.y, acc[0].x));
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        acc[k].x = wave_sum(acc[k].x);
+        acc[k].y = wave_sum(acc[k].y);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NA; ++k) red[wv * NV + k] = acc[k];
+    }
+    __syncthreads();
+    const int nout = DOT ? nv : 1;
+    for (int k = threadIdx.x; k < nout; k += RB) {
+        double2 t = red[k];
+        for (int ww = 1; ww < RB / 64; ++ww) {
+            t.x += red[ww * NV + k].x;
+            t.y += red[ww * NV + k].y;
+        }
+        partial[(long long)blockIdx.x * nout + k] = t;
+    }
+}
+
 __global__ __launch_bounds__(RB) void k_axpby(long long n, double2 a, const double2* __restrict__ x, double2 b,
                                               const double2* __restrict__ y, double2* __restrict__ out) {
     for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
@@ -214,6 +279,28 @@ int launch_lincomb(long long n, int nv, const double2* V, long long ldv, const d
     hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, x, 1.0);
     SG_HIP(hipGetLastError());
     return SG_OK;
+}
+
+// Fused update (+ projection or + norm); returns 0 if nv is above the largest fused size.
+int launch_upd(long long n, int nv, const double2* V, long long ldv, const double* scale, const double2* coef,
+               double2* w, double2* partial, int nblocks, bool dot, hipStream_t st) {
+    KScope ks(SG_K_AXPY, 16.0 * (nv + 2) * (double)n, st);
+#define SG_UPD(NV_)                                                                                       \
+    if (nv <= NV_) {                                                                                      \
+        if (dot)                                                                                          \
+            hipLaunchKernelGGL((k_upd<NV_, true>), dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, w, \
+                               partial);                                                                  \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_upd<NV_, false>), dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, w, \
+                               partial);                                                                  \
+        SG_HIP(hipGetLastError());                                                                        \
+        return 1;                                                                                         \
+    }
+    SG_UPD(8)
+    SG_UPD(16)
+    SG_UPD(32)
+#undef SG_UPD
+    return 0;
 }
 
 int launch_norm2(long long n, const double2* x, double2* partial, int nblocks, hipStream_t st) {

@@ -335,6 +335,117 @@ __global__ __launch_bounds__(64) void k_tri(double2* __restrict__ X, TriFactors 
     }
 }
 
+// Segmented pivoted tridiagonal solve (same arithmetic as k_tri, in parallel over row
+// segments).  Thread (k, system) owns rows [k·L, k·L+L) of one system and keeps them in
+// registers.  Forward: run the segment with a zero entering value (segment 0 starts from
+// b_0), exchange the end values through LDS, form the exact entering value from the
+// previous segments with the forward propagators, rerun and keep y_i/u_ii.  Backward: the
+// same with the 2-vector state (x_{i}, x_{i+1}) and the 2x2 propagators, from the last
+// segment upwards.  Data is read once and written once.
+constexpr int SEGL = 32;
+
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {   // a*b + c
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+
+__global__ __launch_bounds__(256) void k_tri_seg(double2* __restrict__ X, TriFactors f, int len, int na, int nq,
+                                                 long long se, long long sa, long long sq, int fa) {
+    __shared__ double2 tf_[256];
+    __shared__ double2 tb_[256][2];
+    const int K = f.K, L = f.L, SYS = 256 / K;
+    const int tid = threadIdx.x, k = tid / SYS, sl = tid - k * SYS;
+    const long long sysg = (long long)blockIdx.x * SYS + sl;
+    const bool valid = sysg < (long long)na * nq;
+    const int a = valid ? (int)(sysg % na) : 0, q = valid ? (int)(sysg / na) : 0;
+    double2* x = X + (long long)q * sq + (long long)a * sa;
+    const int fs = f.nsys, fo = a * fa;
+    const int s0 = k * L, e0 = min(s0 + L, len);
+    double2 b[SEGL + 1];
+#pragma unroll
+    for (int u = 0; u <= SEGL; ++u) {
+        const int i = s0 + u;
+        b[u] = (valid && u <= L && i < len) ? x[(long long)i * se] : make_double2(0.0, 0.0);
+    }
+    // forward, local run
+    double2 cur = (k == 0) ? b[0] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < SEGL; ++u) {
+        const int i = s0 + u;
+        if (i < e0 && i <= len - 2) {
+            const double2 l = f.dl[(long long)i * fs + fo];
+            const double2 nb = b[u + 1];
+            cur = f.piv[(long long)i * fs + fo] ? csub(cur, cmul(l, nb)) : csub(nb, cmul(l, cur));
+        }
+    }
+    tf_[tid] = cur;
+    __syncthreads();
+    double2 S = b[0];
+    if (k > 0) {
+        S = tf_[sl];
+        for (int j = 1; j < k; ++j) S = cfma(f.phi[(long long)j * fs + fo], S, tf_[j * SYS + sl]);
+    }
+    cur = S;
+#pragma unroll
+    for (int u = 0; u < SEGL; ++u) {
+        const int i = s0 + u;
+        if (i < e0) {
+            const double2 di = f.dinv[(long long)i * fs + fo];
+            if (i <= len - 2) {
+                const double2 l = f.dl[(long long)i * fs + fo];
+                const double2 nb = b[u + 1];
+                double2 out, nxt;
+                if (f.piv[(long long)i * fs + fo]) {
+                    out = nb;
+                    nxt = csub(cur, cmul(l, nb));
+                } else {
+                    out = cur;
+                    nxt = csub(nb, cmul(l, cur));
+                }
+                b[u] = cmul(out, di);
+                cur = nxt;
+            } else {
+                b[u] = cmul(cur, di);
+            }
+        }
+    }
+    // backward, local run with a zero entering state
+    double2 x1 = make_double2(0.0, 0.0), x2 = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = SEGL - 1; u >= 0; --u) {
+        const int i = s0 + u;
+        if (i < e0) {
+            const double2 xi = csub(csub(b[u], cmul(f.u1p[(long long)i * fs + fo], x1)),
+                                    cmul(f.u2p[(long long)i * fs + fo], x2));
+            x2 = x1;
+            x1 = xi;
+        }
+    }
+    tb_[tid][0] = x1;
+    tb_[tid][1] = x2;
+    __syncthreads();
+    double2 E0 = make_double2(0.0, 0.0), E1 = make_double2(0.0, 0.0);
+    for (int j = K - 1; j > k; --j) {
+        const double2* ps = f.psi + ((long long)j * fs + fo) * 4;
+        const double2 n0 = cfma(ps[0], E0, cfma(ps[1], E1, tb_[j * SYS + sl][0]));
+        const double2 n1 = cfma(ps[2], E0, cfma(ps[3], E1, tb_[j * SYS + sl][1]));
+        E0 = n0;
+        E1 = n1;
+    }
+    x1 = E0;
+    x2 = E1;
+#pragma unroll
+    for (int u = SEGL - 1; u >= 0; --u) {
+        const int i = s0 + u;
+        if (i < e0) {
+            const double2 xi = csub(csub(b[u], cmul(f.u1p[(long long)i * fs + fo], x1)),
+                                    cmul(f.u2p[(long long)i * fs + fo], x2));
+            if (valid) x[(long long)i * se] = xi;
+            x2 = x1;
+            x1 = xi;
+        }
+    }
+}
+
 static inline uint16_t host_bf16(float f) {
     uint32_t u;
     std::memcpy(&u, &f, 4);
@@ -440,6 +551,13 @@ static int launch_tri(const TriFactors& f, double2* X, int n, int Q, int dim, hi
     const int blk = 64;
     // algorithmic: every element read and written once, factors read once
     KScope ks(SG_K_TRI, 32.0 * na * (double)nq * n + 65.0 * f.nsys * (double)n, st);
+    if (f.L <= SEGL && f.K >= 1) {
+        const int SYS = 256 / f.K;
+        hipLaunchKernelGGL(k_tri_seg, dim3((unsigned)((nth + SYS - 1) / SYS)), dim3(256), 0, st, X, f, n, na, nq, se,
+                           sa, sq, fa);
+        SG_HIP(hipGetLastError());
+        return SG_OK;
+    }
     hipLaunchKernelGGL(k_tri, dim3((unsigned)((nth + blk - 1) / blk)), dim3(blk), 0, st, X, f, n, na, nq, se, sa,
                        sq, fa);
     SG_HIP(hipGetLastError());

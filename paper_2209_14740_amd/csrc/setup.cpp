@@ -318,6 +318,60 @@ static int build_tri(int n, double h, double kbar, const std::vector<cplx>& sig,
     }
     tf.len = n;
     tf.nsys = nsys;
+    // Segmented form of the two substitutions: with K segments of L rows, the forward
+    // carried value obeys c_{i+1} = A_i c_i + B_i b_{i+1} (A_i = 1 after a row exchange,
+    // -l_i otherwise), the backward one X_i = M_i X_{i+1} + (y_i/u_ii, 0) with
+    // M_i = [[-u_{i,i+1}/u_ii, -u_{i,i+2}/u_ii], [1, 0]]; the products of A_i and of M_i over
+    // each segment are the propagators used to join independently computed segments.
+    int K = 1;
+    while (K < 16 && (n + K - 1) / K > 32) K *= 2;
+    const int L = (n + K - 1) / K;
+    tf.K = K;
+    tf.L = L;
+    std::vector<double2> hu1p((size_t)n * nsys, make_double2(0, 0)), hu2p((size_t)n * nsys, make_double2(0, 0));
+    std::vector<double2> hphi((size_t)K * nsys), hpsi((size_t)K * nsys * 4);
+    for (int a = 0; a < nsys; ++a) {
+        auto C = [&](const std::vector<double2>& v, size_t idx) { return cplx(v[idx].x, v[idx].y); };
+        for (int i = 0; i < n; ++i) {
+            const cplx di = C(hdi, (size_t)i * nsys + a);
+            if (i < n - 1) {
+                const cplx u1 = C(hu1, (size_t)i * nsys + a) * di;
+                hu1p[(size_t)i * nsys + a] = make_double2(u1.real(), u1.imag());
+            }
+            if (i < n - 2) {
+                const cplx u2 = C(hu2, (size_t)i * nsys + a) * di;
+                hu2p[(size_t)i * nsys + a] = make_double2(u2.real(), u2.imag());
+            }
+        }
+        for (int k = 0; k < K; ++k) {
+            const int s0 = k * L, e0 = std::min(s0 + L, n);
+            cplx ph = 1.0;
+            for (int i = s0; i < e0 && i <= n - 2; ++i)
+                ph *= hp[(size_t)i * nsys + a] ? cplx(1.0) : -C(hdl, (size_t)i * nsys + a);
+            hphi[(size_t)k * nsys + a] = make_double2(ph.real(), ph.imag());
+            cplx m00 = 1.0, m01 = 0.0, m10 = 0.0, m11 = 1.0;   // product M_s ... M_{e-1}
+            for (int i = e0 - 1; i >= s0; --i) {
+                const cplx u1 = C(hu1p, (size_t)i * nsys + a), u2 = C(hu2p, (size_t)i * nsys + a);
+                // left-multiply by M_i = [[-u1, -u2], [1, 0]]
+                const cplx n00 = -u1 * m00 - u2 * m10, n01 = -u1 * m01 - u2 * m11;
+                const cplx n10 = m00, n11 = m01;
+                m00 = n00; m01 = n01; m10 = n10; m11 = n11;
+            }
+            const size_t o = ((size_t)k * nsys + a) * 4;
+            hpsi[o + 0] = make_double2(m00.real(), m00.imag());
+            hpsi[o + 1] = make_double2(m01.real(), m01.imag());
+            hpsi[o + 2] = make_double2(m10.real(), m10.imag());
+            hpsi[o + 3] = make_double2(m11.real(), m11.imag());
+        }
+    }
+    SG_HIP(hipMalloc(&tf.u1p, hu1p.size() * sizeof(double2)));
+    SG_HIP(hipMalloc(&tf.u2p, hu2p.size() * sizeof(double2)));
+    SG_HIP(hipMalloc(&tf.phi, hphi.size() * sizeof(double2)));
+    SG_HIP(hipMalloc(&tf.psi, hpsi.size() * sizeof(double2)));
+    SG_HIP(hipMemcpy(tf.u1p, hu1p.data(), hu1p.size() * sizeof(double2), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(tf.u2p, hu2p.data(), hu2p.size() * sizeof(double2), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(tf.phi, hphi.data(), hphi.size() * sizeof(double2), hipMemcpyHostToDevice));
+    SG_HIP(hipMemcpy(tf.psi, hpsi.data(), hpsi.size() * sizeof(double2), hipMemcpyHostToDevice));
     SG_HIP(hipMalloc(&tf.dl, hdl.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.dinv, hdi.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.du1, hu1.size() * sizeof(double2)));
@@ -337,6 +391,10 @@ static void free_tri(TriFactors& t) {
     (void)hipFree(t.du1);
     (void)hipFree(t.du2);
     (void)hipFree(t.piv);
+    (void)hipFree(t.u1p);
+    (void)hipFree(t.u2p);
+    (void)hipFree(t.phi);
+    (void)hipFree(t.psi);
     t = TriFactors{};
 }
 

@@ -47,6 +47,12 @@ struct TriFactors {
     double2* du1 = nullptr;   // u_{i,i+1}
     double2* du2 = nullptr;   // u_{i,i+2}
     uint8_t* piv = nullptr;   // 1 if rows i and i+1 were swapped at step i
+    // segmented form (rows split into K segments of L <= 32 rows, see precond.hip)
+    int K = 0, L = 0;
+    double2* u1p = nullptr;   // u_{i,i+1} / u_ii   (len rows, zero past the end)
+    double2* u2p = nullptr;   // u_{i,i+2} / u_ii
+    double2* phi = nullptr;   // forward propagator of segment k: [k][sys]
+    double2* psi = nullptr;   // backward 2x2 propagator of segment k: [k][sys][4]
 };
 
 // Expanded real form of a complex N×N matrix for the GEMM C = A·B, where A rows are
@@ -162,6 +168,8 @@ int launch_axpy_dot(long long n, int nv, const double2* V, long long ldv, const 
                     const double2* coef, double2* w, double2* partial, int nblocks, bool with_dot,
                     hipStream_t st);
 int launch_norm2(long long n, const double2* x, double2* partial, int nblocks, hipStream_t st);
+int launch_upd(long long n, int nv, const double2* V, long long ldv, const double* scale, const double2* coef,
+               double2* w, double2* partial, int nblocks, bool dot, hipStream_t st);
 int launch_reduce_norm(int nblocks, const double2* partial, double2* out, hipStream_t st);
 int launch_lincomb(long long n, int nv, const double2* V, long long ldv, const double* scale,
                    const double2* coef, double2* x, hipStream_t st);
