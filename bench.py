@@ -120,6 +120,62 @@ def matvec_bandwidth(inst, reps):
     return out
 
 
+def batched_config4(count, log):
+    """Batched form: `count` seeded instances (N∈{63,127,255}, Q∈{3..70}) solved by one
+    sg_gmres_batched call (A_0-GMRES(30) to 1e-8, FP64 outer, FP32 preconditioner,
+    autotuned GEMM tiles).  Setup (host eigenfactors + uploads) runs in host threads and
+    is timed separately; solves/s is reported with and without it."""
+    import concurrent.futures as cf
+
+    import torch
+    from paper_2209_14740_amd import sg
+    from workloads import config4_instances
+    insts = config4_instances(count)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        ops = list(ex.map(sg.SG.from_instance, insts))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    bs = [op.rhs(i.f) for op, i in zip(ops, insts)]
+    xs = [op.empty() for op in ops]
+    log("batched: %d instances set up in %.2f s, %d unknowns in total" % (count, t_setup, sum(o.size for o in ops)))
+    t0 = time.perf_counter()
+    tune_ms = sg.autotune(ops, precision="f32", reps=3)
+    t_tune = time.perf_counter() - t0
+    tiles = {}
+    for op in ops:
+        tiles["n%d_q%d" % (op.n, op.Q)] = sg.tune_get(op.n, op.Q, "f32")
+    # warm-up on a small slice (kernel loading), then the whole batch, timed
+    sg.gmres_batched(ops[:8], bs[:8], xs[:8], restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rc, infos = sg.gmres_batched(ops, bs, xs, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    log("batched: %.3f s for %d solves (%.1f solves/s), rc %d" % (t_solve, count, count / t_solve, rc))
+    # the same instances one at a time through sg_gmres (same algorithm and precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for op, b, x in zip(ops, bs, xs):
+        op.gmres(b, x, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log("one at a time: %.3f s (%.1f solves/s)" % (t_seq, count / t_seq))
+    its = np.array([i["iters"] for i in infos])
+    rel = np.array([i["relres_true"] for i in infos])
+    out = {"workload": "%d seeded instances, N in {63,127,255}, kbar~U[5,30], sigma=0.1 kbar, s in 1..4, "
+                       "degree 2..4; A_0-GMRES(30) to 1e-8, FP64 outer, FP32 preconditioner" % count,
+           "solves_per_s": count / t_solve, "solves_per_s_with_setup": count / (t_solve + t_setup),
+           "solve_s": t_solve, "one_at_a_time_solves_per_s": count / t_seq, "setup_s": t_setup, "setup_threads": 8, "autotune_s": t_tune,
+           "autotune_gpu_ms": tune_ms, "tiles": tiles, "all_converged": bool(rc == 0),
+           "iters_mean": float(its.mean()), "iters_max": int(its.max()), "relres_true_max": float(rel.max())}
+    for op in ops:
+        op.close()
+    del bs, xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline():
     """The oracle (numpy/scipy FP64) on the same workload: assembly, block LU of the mean
     block and MGS GMRES(50) to 1e-8, timed on the host; BLAS restricted to one thread
@@ -153,6 +209,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-matvec", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-count", type=int, default=512)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched leg (for profiling); prints its JSON object")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs on one GPU; a run on %d GPUs is not part of this build "
@@ -164,6 +224,9 @@ def main():
     from workloads import config2, config3
 
     torch.cuda.set_device(0)
+    if args.batched_only:
+        print(json.dumps({"batched": batched_config4(args.batched_count, log)}))
+        return
     inst = config2()
     t0 = time.perf_counter()
     op = sg.SG.from_instance(inst)
@@ -230,6 +293,9 @@ def main():
     if not args.no_matvec:
         log("matvec bandwidth on config 3")
         out["matvec"] = matvec_bandwidth(config3(), 20)
+    if not args.no_batched:
+        log("batched config 4")
+        out["batched"] = batched_config4(args.batched_count, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

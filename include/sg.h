@@ -135,6 +135,40 @@ typedef int (*sg_precond_cb)(void* user, const sg_c64* r, sg_c64* z, hipStream_t
 int  sg_fgmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
                sg_precond_cb cb, void* user, sg_solve_stats* stats, hipStream_t stream);
 
+/* Batched right-preconditioned GMRES(m) over `count` independent problems of any
+ * size (instances of a parametric study, each with its own handle).
+ * The algorithm per instance is that of sg_gmres (Section 5 preconditioners, Section 6.3
+ * block reuse); the instances advance in lockstep steps, each phase of a step being one
+ * grouped kernel launch over all active instances, with one host synchronisation per
+ * step.  Instances are admitted from a queue ordered by estimated cost (largest first)
+ * into Krylov workspaces carved from one device arena of at most max(largest instance,
+ * half the free device memory), allocated for the call and freed before it returns.
+ * handles, b and x: host arrays of `count` entries; b[i], x[i] device vectors of
+ * sg_size(handles[i]) complex, x[i] is overwritten (the initial guess is zero, opts
+ * x0_zero is ignored).  A handle may appear only once.  opts->restart must be in
+ * [1, 63]; opts->hist is ignored.  stats: host array of `count` entries or NULL
+ * (t_precond / t_matvec / t_orth are 0; t_total is the wall time from admission to
+ * completion).  The GEMM tile shape of each instance comes from the autotuner table
+ * (sg_autotune / sg_tune_set), 128×128 when absent.  Returns SG_OK if every instance
+ * converged, SG_ENOTCONV if some did not (their stats say which: converged = 0, a
+ * non-finite value gives relres_true = NaN), negative on invalid arguments or a HIP
+ * failure.  Kernel timing, when enabled, is recorded in the profiler of handles[0]. */
+int  sg_gmres_batched(int count, const sg_handle* handles, const sg_c64* const* b, sg_c64* const* x,
+                      const sg_solve_opts* opts, sg_solve_stats* stats, hipStream_t stream);
+
+/* GEMM tile-shape autotuner of the preconditioner transforms: for every distinct
+ * (n, Q) among the 2D handles, times each tile shape (SG_GEMM_TILE_*) on a grouped
+ * launch over up to 8 instances of that shape, `reps` repetitions, and stores the
+ * fastest in a process-wide table keyed by (n, Q, precision).  Uses the handles'
+ * preconditioner scratch (their contents are overwritten) and a temporary device
+ * buffer.  *ms_total (may be NULL) receives the measured GPU time. */
+enum { SG_GEMM_TILE_128x128 = 0, SG_GEMM_TILE_64x128 = 1, SG_GEMM_TILE_64x64 = 2 };
+int  sg_autotune(int count, const sg_handle* handles, int precision, int reps, double* ms_total,
+                 hipStream_t stream);
+/* Read (-1 if absent) or set one entry of the autotuner table. */
+int  sg_tune_get(int n, int Q, int precision);
+int  sg_tune_set(int n, int Q, int precision, int tile);
+
 /* One CGS2 step: orthogonalise w (n complex) against the nv orthonormal columns of
  * V (nv·n complex, vector-major) twice, normalise it in place, and return the nv+1
  * Arnoldi coefficients h_host[0..nv-1] = V^H w (both passes summed), h_host[nv] = ||w||. */

@@ -189,6 +189,54 @@ int sg_norm(long long n, const sg_c64* x, double* out_host, hipStream_t stream) 
     })
 }
 
+int sg_gmres_batched(int count, const sg_handle* handles, const sg_c64* const* b, sg_c64* const* x,
+                     const sg_solve_opts* opts, sg_solve_stats* stats, hipStream_t stream) {
+    SG_TRY({
+        if (count < 0) return fail(SG_EINVAL, "count must be >= 0");
+        if (count == 0) return SG_OK;
+        if (!handles || !b || !x || !opts) return fail(SG_EINVAL, "null argument");
+        std::vector<Ctx*> cs(count);
+        std::vector<const double2*> bs(count);
+        std::vector<double2*> xs(count);
+        for (int i = 0; i < count; ++i) {
+            if (!handles[i]) return fail(SG_EINVAL, "null handle in the batch");
+            cs[i] = ctx(handles[i]);
+            if (int rc = guard_device(cs[i])) return rc;
+            bs[i] = reinterpret_cast<const double2*>(b[i]);
+            xs[i] = reinterpret_cast<double2*>(x[i]);
+        }
+        ProfBind pb(cs[0]);
+        return sgi::run_gmres_batched(count, cs.data(), bs.data(), xs.data(), opts, stats, stream);
+    })
+}
+
+int sg_autotune(int count, const sg_handle* handles, int precision, int reps, double* ms_total, hipStream_t stream) {
+    SG_TRY({
+        if (count < 0 || (count > 0 && !handles)) return fail(SG_EINVAL, "invalid handle list");
+        std::vector<Ctx*> cs(count);
+        for (int i = 0; i < count; ++i) {
+            if (!handles[i]) return fail(SG_EINVAL, "null handle");
+            cs[i] = ctx(handles[i]);
+            if (int rc = guard_device(cs[i])) return rc;
+        }
+        return sgi::autotune(count, cs.data(), precision, reps, ms_total, stream);
+    })
+}
+
+int sg_tune_get(int n, int Q, int precision) {
+    SG_TRY({ return sgi::tune_get(n, Q, precision); })
+}
+
+int sg_tune_set(int n, int Q, int precision, int tile) {
+    SG_TRY({
+        if (tile < 0 || tile >= sgi::SG_GEMM_NCFG) return fail(SG_EINVAL, "unknown tile shape");
+        if (n < 1 || Q < 1 || precision < SG_PREC_F64 || precision > SG_PREC_BF16X3)
+            return fail(SG_EINVAL, "invalid table key");
+        sgi::tune_set(n, Q, precision, tile);
+        return SG_OK;
+    })
+}
+
 int sg_set_profiling(sg_handle h, int on) {
     SG_TRY({
         if (!h) return fail(SG_EINVAL, "null handle");

@@ -25,16 +25,9 @@ constexpr int TPAD = TILE + 2;
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__global__ __launch_bounds__(256) void k_apply(ApplyArgs a) {
-    extern __shared__ double2 smem[];
+__device__ __forceinline__ void apply_tile(const ApplyArgs& a, int tile, double2* smem) {
     double2* vt = smem;                                   // [Q][TPAD]
     double* dt = reinterpret_cast<double*>(smem + (size_t)a.Q * TPAD);   // [ng2][TILE]
-
-    // XCD-aware block → tile mapping: blocks are dispatched round-robin over the 8 XCDs;
-    // the grid is a multiple of 8 and each XCD gets a contiguous band of tiles (rows).
-    const int per = gridDim.x / 8;
-    const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (tile >= a.ntiles_x * a.nrows) return;
     const int row = tile / a.ntiles_x;
     const int x0 = (tile % a.ntiles_x) * TILE;
     const int n = a.n;
@@ -130,10 +123,36 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_apply(ApplyArgs a) {
+    extern __shared__ double2 smem[];
+    // XCD-aware block → tile mapping: blocks are dispatched round-robin over the 8 XCDs;
+    // the grid is a multiple of 8 and each XCD gets a contiguous band of tiles (rows).
+    const int per = gridDim.x / 8;
+    const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= a.ntiles_x * a.nrows) return;
+    apply_tile(a, tile, smem);
+}
+
+// Many operators in one launch: task t owns tiles [start[t], start[t+1]).
+__global__ __launch_bounds__(256) void k_apply_grouped(const ApplyArgs* __restrict__ tasks,
+                                                       const int* __restrict__ start, int ntask, int total) {
+    extern __shared__ double2 smem[];
+    const int per = gridDim.x / 8;
+    const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (v >= total) return;
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    const ApplyArgs a = tasks[lo];
+    apply_tile(a, v - start[lo], smem);
+}
+
 }  // namespace
 
-int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st) {
-    if (x == y) return fail(SG_EINVAL, "sg_apply: x and y must not alias");
+ApplyArgs make_apply_args(const Ctx* c, const double2* x, double2* y) {
     ApplyArgs a;
     a.x = x;
     a.y = y;
@@ -163,6 +182,39 @@ int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st) {
     a.KF = c->d_kf;
     a.k0 = c->kbar;
     a.ih = 1.0 / c->h;
+    return a;
+}
+
+size_t apply_lds_bytes(int Q, int ng2) { return (size_t)Q * TPAD * sizeof(double2) + (size_t)ng2 * TILE * sizeof(double); }
+
+static int set_lds_attr() {
+    // once per process (thread-safe initialisation of a function-local static)
+    static const hipError_t e = [] {
+        hipError_t r = hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (r == hipSuccess)
+            r = hipFuncSetAttribute((const void*)k_apply_grouped, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        return r;
+    }();
+    SG_HIP(e);
+    return SG_OK;
+}
+
+int launch_apply_grouped(const ApplyArgs* d_tasks, const int* d_start, int ntask, int total, size_t lds,
+                         double bytes, hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    if (lds > 160 * 1024) return fail(SG_EINVAL, "sg_apply: Q too large for the LDS tile");
+    int rc = set_lds_attr();
+    if (rc) return rc;
+    KScope ks(SG_K_APPLY, bytes, st);
+    hipLaunchKernelGGL(k_apply_grouped, dim3(((total + 7) / 8) * 8), dim3(256), lds, st, d_tasks, d_start, ntask,
+                       total);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st) {
+    if (x == y) return fail(SG_EINVAL, "sg_apply: x and y must not alias");
+    const ApplyArgs a = make_apply_args(c, x, y);
     if (c->use_spec_apply) {
         KScope ks(SG_K_APPLY, (double)c->P * (32.0 * c->Q + 8.0 * c->s), st);
         const int sv = c->s, rv = c->degree;
@@ -172,13 +224,10 @@ int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st) {
             return SG_OK;
         }
     }
-    const size_t lds = (size_t)c->Q * TPAD * sizeof(double2) + (size_t)c->K.nfield * TILE * sizeof(double);
+    const size_t lds = apply_lds_bytes(c->Q, c->K.nfield);
     if (lds > 160 * 1024) return fail(SG_EINVAL, "sg_apply: Q too large for the LDS tile");
-    static bool attr_set = false;
-    if (!attr_set) {
-        SG_HIP(hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_set = true;
-    }
+    int rc = set_lds_attr();
+    if (rc) return rc;
     const int nblk = ((a.ntiles_x * a.nrows + 7) / 8) * 8;
     KScope ks(SG_K_APPLY, (double)c->P * (32.0 * c->Q + 8.0 * c->K.nfield), st);
     hipLaunchKernelGGL(k_apply, dim3(nblk), dim3(256), lds, st, a);

@@ -25,6 +25,13 @@ struct ApplyArgs {
     double k0, ih;        // constant mean k_0 and 1/h
 };
 
+ApplyArgs make_apply_args(const Ctx* c, const double2* x, double2* y);
+size_t apply_lds_bytes(int Q, int ng2);
+// Generic operator over many (x, y, operator) tasks; task t owns tiles [start[t], start[t+1])
+// (n_tiles = ntiles_x · nrows); lds is the largest apply_lds_bytes of the tasks.
+int launch_apply_grouped(const ApplyArgs* d_tasks, const int* d_start, int ntask, int total, size_t lds,
+                         double bytes, hipStream_t st);
+
 // Shape-specialised operator launchers, one translation unit per group of (s, r)
 // shapes (apply_spec_g*.hip); each returns 1 if it handled (s, r), else 0.
 int dispatch_spec_g0(int s, int r, const ApplyArgs& a, hipStream_t st);

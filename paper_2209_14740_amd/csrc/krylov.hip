@@ -225,6 +225,200 @@ __global__ __launch_bounds__(RB) void k_axpby(long long n, double2 a, const doub
     }
 }
 
+// ---- grouped forms: one launch over the solves of a batch -------------------------------
+
+__device__ __forceinline__ int task_of(const int* __restrict__ start, int ntask, int v) {
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// partial[lb][k] = Σ_{i in local block lb} conj(V_k[i]) · w[i]
+__global__ __launch_bounds__(RB) void k_multidot_g(const VecTask* __restrict__ tasks, const int* __restrict__ start,
+                                                   int ntask) {
+    __shared__ double2 red[(RB / 64) * KG];
+    const int t = task_of(start, ntask, blockIdx.x);
+    const VecTask& g = tasks[t];
+    const int lb = blockIdx.x - start[t];
+    const long long n = g.n, ldv = g.ldv;
+    const int nv = g.nv;
+    const long long stride = (long long)g.nblocks * RB;
+    for (int kg = 0; kg < nv; kg += KG) {
+        double2 acc[KG];
+#pragma unroll
+        for (int k = 0; k < KG; ++k) acc[k] = make_double2(0.0, 0.0);
+        for (long long i = (long long)lb * RB + threadIdx.x; i < n; i += stride) {
+            const double2 wi = g.w[i];
+#pragma unroll
+            for (int k = 0; k < KG; ++k) {
+                if (kg + k < nv) {
+                    const double2 v = g.V[(long long)(kg + k) * ldv + i];
+                    acc[k].x += v.x * wi.x + v.y * wi.y;
+                    acc[k].y += v.x * wi.y - v.y * wi.x;
+                }
+            }
+        }
+        block_reduce(acc, red);
+        if (threadIdx.x < KG && kg + threadIdx.x < nv) g.partial[(long long)lb * nv + kg + threadIdx.x] = red[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// One block per (task, output k): mode 0 out[k] = scale[k]·Σ_b partial[b][k] (nout = nv),
+// mode 1 out[0] = sqrt(Σ_b Re partial[b][0]) (nout = 1).
+__global__ __launch_bounds__(RB) void k_reduce_g(const VecTask* __restrict__ tasks, const int* __restrict__ start,
+                                                 int ntask, int mode) {
+    __shared__ double2 red[RB / 64];
+    const int t = task_of(start, ntask, blockIdx.x);
+    const VecTask& g = tasks[t];
+    const int k = blockIdx.x - start[t];
+    const int nout = mode == 1 ? 1 : g.nv;
+    double sx = 0.0, sy = 0.0;
+    for (int b = threadIdx.x; b < g.nblocks; b += RB) {
+        const double2 p = g.partial[(long long)b * nout + k];
+        sx += p.x;
+        sy += p.y;
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double2(sx, sy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tx = 0.0, ty = 0.0;
+        for (int w = 0; w < RB / 64; ++w) {
+            tx += red[w].x;
+            ty += red[w].y;
+        }
+        if (mode == 1) {
+            g.out[0] = make_double2(sqrt(tx), 0.0);
+        } else {
+            const double s = g.scale ? g.scale[k] : 1.0;
+            g.out[k] = make_double2(s * tx, s * ty);
+        }
+    }
+}
+
+// Fused CGS2 update (+ projection or + squared norm), as k_upd, per task.
+template <int NV, bool DOT>
+__global__ __launch_bounds__(RB) void k_upd_g(const VecTask* __restrict__ tasks, const int* __restrict__ start,
+                                              int ntask) {
+    __shared__ double2 c[NV];
+    __shared__ double2 red[(RB / 64) * NV];
+    const int t = task_of(start, ntask, blockIdx.x);
+    const VecTask& g = tasks[t];
+    const int lb = blockIdx.x - start[t];
+    const int nv = g.nv;
+    const long long n = g.n, ldv = g.ldv;
+    for (int k = threadIdx.x; k < nv; k += RB) {
+        const double sk = -(g.scale ? g.scale[k] : 1.0);
+        c[k] = make_double2(g.coef[k].x * sk, g.coef[k].y * sk);
+    }
+    __syncthreads();
+    constexpr int NA = DOT ? NV : 1;
+    double2 acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
+    const long long stride = (long long)g.nblocks * RB;
+    double2* __restrict__ w = g.w;
+    const double2* __restrict__ V = g.V;
+    for (long long i = (long long)lb * RB + threadIdx.x; i < n; i += stride) {
+        double2 v[NV];
+        double2 wi = w[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nv) {
+                v[k] = V[(long long)k * ldv + i];
+                const double2 ck = c[k];
+                wi.x = fma(v[k].x, ck.x, fma(-v[k].y, ck.y, wi.x));
+                wi.y = fma(v[k].x, ck.y, fma(v[k].y, ck.x, wi.y));
+            }
+        if (nv > 0) w[i] = wi;
+        if constexpr (DOT) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                if (k < nv) {
+                    acc[k].x = fma(v[k].x, wi.x, fma(v[k].y, wi.y, acc[k].x));
+                    acc[k].y = fma(v[k].x, wi.y, fma(-v[k].y, wi.x, acc[k].y));
+                }
+        } else {
+            acc[0].x = fma(wi.x, wi.x, fma(wi.y, wi.y, acc[0].x));
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        acc[k].x = wave_sum(acc[k].x);
+        acc[k].y = wave_sum(acc[k].y);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NA; ++k) red[wv * NV + k] = acc[k];
+    }
+    __syncthreads();
+    const int nout = DOT ? nv : 1;
+    for (int k = threadIdx.x; k < nout; k += RB) {
+        double2 s = red[k];
+        for (int ww = 1; ww < RB / 64; ++ww) {
+            s.x += red[ww * NV + k].x;
+            s.y += red[ww * NV + k].y;
+        }
+        g.partial[(long long)lb * nout + k] = s;
+    }
+}
+
+// w[i] = Σ_k V_k[i] · scale[k] · coef[k]   (written, not accumulated)
+template <int NV>
+__global__ __launch_bounds__(RB) void k_lincomb_g(const VecTask* __restrict__ tasks, const int* __restrict__ start,
+                                                  int ntask) {
+    __shared__ double2 c[NV];
+    const int t = task_of(start, ntask, blockIdx.x);
+    const VecTask& g = tasks[t];
+    const int lb = blockIdx.x - start[t];
+    const int nv = g.nv;
+    for (int k = threadIdx.x; k < nv; k += RB) {
+        const double sk = g.scale ? g.scale[k] : 1.0;
+        c[k] = make_double2(g.coef[k].x * sk, g.coef[k].y * sk);
+    }
+    __syncthreads();
+    const long long stride = (long long)g.nblocks * RB;
+    for (long long i = (long long)lb * RB + threadIdx.x; i < g.n; i += stride) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nv) {
+                const double2 v = g.V[(long long)k * g.ldv + i];
+                const double2 ck = c[k];
+                acc.x = fma(v.x, ck.x, fma(-v.y, ck.y, acc.x));
+                acc.y = fma(v.x, ck.y, fma(v.y, ck.x, acc.y));
+            }
+        g.w[i] = acc;
+    }
+}
+
+// w = a x + b y (y may be null)
+__global__ __launch_bounds__(RB) void k_axpby_g(const VecTask* __restrict__ tasks, const int* __restrict__ start,
+                                                int ntask) {
+    const int t = task_of(start, ntask, blockIdx.x);
+    const VecTask& g = tasks[t];
+    const int lb = blockIdx.x - start[t];
+    const long long stride = (long long)g.nblocks * RB;
+    const double2 a = g.a, b = g.b;
+    for (long long i = (long long)lb * RB + threadIdx.x; i < g.n; i += stride) {
+        const double2 xv = g.x[i];
+        double2 r = make_double2(a.x * xv.x - a.y * xv.y, a.x * xv.y + a.y * xv.x);
+        if (g.y) {
+            const double2 yv = g.y[i];
+            r.x += b.x * yv.x - b.y * yv.y;
+            r.y += b.x * yv.y + b.y * yv.x;
+        }
+        g.w[i] = r;
+    }
+}
+
 }  // namespace
 
 int reduction_blocks(long long n) {
@@ -319,6 +513,74 @@ int launch_axpby(long long n, double2 a, const double2* x, double2 b, const doub
 
 int launch_scale_copy(long long n, double a, const double2* x, double2* out, hipStream_t st) {
     return launch_axpby(n, make_double2(a, 0.0), x, make_double2(0.0, 0.0), nullptr, out, st);
+}
+
+}  // namespace sgi
+
+namespace sgi {
+
+int launch_multidot_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+                            hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_DOT, bytes, st);
+    hipLaunchKernelGGL(k_multidot_g, dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_reduce_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int mode,
+                          hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_NORM, 0.0, st);
+    hipLaunchKernelGGL(k_reduce_g, dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask, mode);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_upd_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv, bool dot,
+                       double bytes, hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_AXPY, bytes, st);
+#define SG_UPDG(NV_)                                                                                          \
+    if (maxnv <= NV_) {                                                                                       \
+        if (dot) hipLaunchKernelGGL((k_upd_g<NV_, true>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);  \
+        else hipLaunchKernelGGL((k_upd_g<NV_, false>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);     \
+        SG_HIP(hipGetLastError());                                                                            \
+        return SG_OK;                                                                                         \
+    }
+    SG_UPDG(8)
+    SG_UPDG(16)
+    SG_UPDG(32)
+    SG_UPDG(64)
+#undef SG_UPDG
+    return fail(SG_EINVAL, "batched solve: restart length above 63");
+}
+
+int launch_lincomb_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv,
+                           double bytes, hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_AXPY, bytes, st);
+#define SG_LCG(NV_)                                                                                   \
+    if (maxnv <= NV_) {                                                                               \
+        hipLaunchKernelGGL((k_lincomb_g<NV_>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask); \
+        SG_HIP(hipGetLastError());                                                                    \
+        return SG_OK;                                                                                 \
+    }
+    SG_LCG(8)
+    SG_LCG(16)
+    SG_LCG(32)
+    SG_LCG(64)
+#undef SG_LCG
+    return fail(SG_EINVAL, "batched solve: restart length above 64");
+}
+
+int launch_axpby_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+                         hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_AXPY, bytes, st);
+    hipLaunchKernelGGL(k_axpby_g, dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
 }
 
 }  // namespace sgi

@@ -34,7 +34,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16X3 = 2 };
 
-constexpr int BM = 128, BN = 128, BK = 32;
+constexpr int BK = 32;
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -43,84 +43,87 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
-template <int MODE>
+// LDS tiles of one K step.  BM = 32·WM rows of A, BN = 32·WN rows of Bt.
+template <int MODE, int BM, int BN>
 struct Lds;
-template <>
-struct Lds<MODE_F64> {
+template <int BM, int BN>
+struct Lds<MODE_F64, BM, BN> {
     static constexpr int PAD = BK + 1;
     double a[BM * PAD];
     double b[BN * PAD];
 };
-template <>
-struct Lds<MODE_F32> {
+template <int BM, int BN>
+struct Lds<MODE_F32, BM, BN> {
     static constexpr int PAD = BK + 1;
     float a[BM * PAD];
     float b[BN * PAD];
 };
-template <>
-struct Lds<MODE_BF16X3> {
+template <int BM, int BN>
+struct Lds<MODE_BF16X3, BM, BN> {
     static constexpr int PAD = BK + 8;
     uint16_t ahi[BM * PAD], alo[BM * PAD];
     uint16_t bhi[BN * PAD], blo[BN * PAD];
 };
 
-// C[M][Nc] = A[M][Kc] · B where Bt[Nc][Kc] (n-major).  A is FP64; C is FP64.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, long long lda,
-                                              const void* __restrict__ Bt0, const void* __restrict__ Bt1,
-                                              long long ldb, double* __restrict__ C, long long ldc,
-                                              int M, int Nc, int Kc, int tiles_m, int tiles_n) {
-    __shared__ Lds<MODE> sm;
-    constexpr int PAD = Lds<MODE>::PAD;
-    const int ntiles = tiles_m * tiles_n;
-    const int per = gridDim.x / 8;
-    const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-contiguous bands
-    if (tile >= ntiles) return;
-    const int tm = tile / tiles_n, tn = tile % tiles_n;
+}  // namespace
+
+namespace {
+
+// One BM×BN output tile (BM = 32·WM, BN = 32·WN) by four waves in a 2×2 layout, each wave
+// owning WM×WN blocks of 16×16.  Global → register prefetch of the next K step overlaps
+// the MFMAs of the current one.
+template <int MODE, int WM, int WN>
+__device__ __forceinline__ void gemm_tile(const GemmTask& g, int tile, Lds<MODE, 32 * WM, 32 * WN>& sm) {
+    constexpr int BM = 32 * WM, BN = 32 * WN;
+    constexpr int PAD = Lds<MODE, BM, BN>::PAD;
+    const double* __restrict__ A = g.A;
+    const long long lda = g.lda, ldb = g.ldb, ldc = g.ldc;
+    const int M = g.M, Nc = g.Nc, Kc = g.Kc;
+    const int tm = tile / g.tiles_n, tn = tile % g.tiles_n;
     const int m0 = tm * BM, n0 = tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv >> 1, wn = wv & 1;
     const int l16 = lane & 15, lq = lane >> 4;
 
     using acc_t = typename std::conditional<MODE == MODE_F64, d4, f4>::type;
-    acc_t acc[4][4];
+    acc_t acc[WM][WN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+        for (int j = 0; j < WN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-    // global → register staging: A tile 128×32 doubles = 2048 double2, 8 per thread
-    double2 ra[8];
-    // B staging per mode
-    double2 rb64[8];
-    float4 rb32[4];
-    uint4 rbh[2], rbl[2];
+    // global → register staging: the A tile is BM×32 doubles = 16·BM double2
+    constexpr int PA = BM / 16, PB64 = BN / 16, PB32 = BN / 32, PB16 = BN / 64 > 0 ? BN / 64 : 1;
+    double2 ra[PA];
+    double2 rb64[MODE == MODE_F64 ? PB64 : 1];
+    float4 rb32[MODE == MODE_F32 ? PB32 : 1];
+    uint4 rbh[PB16], rbl[PB16];
 
     auto load_tiles = [&](int k0) {
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
+        for (int p = 0; p < PA; ++p) {
             const int idx = p * 256 + tid, row = idx >> 4, k = (idx & 15) * 2;
             const int gm = m0 + row, gk = k0 + k;
             ra[p] = (gm < M && gk < Kc) ? *reinterpret_cast<const double2*>(A + (long long)gm * lda + gk)
                                         : make_double2(0.0, 0.0);
         }
         if constexpr (MODE == MODE_F64) {
-            const double* B = reinterpret_cast<const double*>(Bt0);
+            const double* B = reinterpret_cast<const double*>(g.Bt0);
 #pragma unroll
-            for (int p = 0; p < 8; ++p) {
+            for (int p = 0; p < PB64; ++p) {
                 const int idx = p * 256 + tid, row = idx >> 4, k = (idx & 15) * 2;
                 const int gn = n0 + row, gk = k0 + k;
                 rb64[p] = (gn < Nc && gk < Kc) ? *reinterpret_cast<const double2*>(B + (long long)gn * ldb + gk)
                                                : make_double2(0.0, 0.0);
             }
         } else if constexpr (MODE == MODE_F32) {
-            const float* B = reinterpret_cast<const float*>(Bt0);
+            const float* B = reinterpret_cast<const float*>(g.Bt0);
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
+            for (int p = 0; p < PB32; ++p) {
                 const int idx = p * 256 + tid, row = idx >> 3, k = (idx & 7) * 4;
                 const int gn = n0 + row, gk = k0 + k;
                 // Kc is even and ldb a multiple of 4: a float4 is either fully inside or
-                // straddles the end, in which case the tail lanes are read as zero below.
+                // straddles the end, in which case the tail lanes are read as zero.
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (gn < Nc && gk + 3 < Kc) v = *reinterpret_cast<const float4*>(B + (long long)gn * ldb + gk);
                 else if (gn < Nc && gk < Kc) {
@@ -130,14 +133,14 @@ __global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, long
                 rb32[p] = v;
             }
         } else {
-            const uint16_t* Bh = reinterpret_cast<const uint16_t*>(Bt0);
-            const uint16_t* Bl = reinterpret_cast<const uint16_t*>(Bt1);
+            const uint16_t* Bh = reinterpret_cast<const uint16_t*>(g.Bt0);
+            const uint16_t* Bl = reinterpret_cast<const uint16_t*>(g.Bt1);
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
+            for (int p = 0; p < PB16; ++p) {
                 const int idx = p * 256 + tid, row = idx >> 2, k = (idx & 3) * 8;
                 const int gn = n0 + row, gk = k0 + k;
                 uint4 vh = make_uint4(0, 0, 0, 0), vl = make_uint4(0, 0, 0, 0);
-                if (gn < Nc && gk < Kc) {   // ldb is padded to a multiple of 8 with zeros
+                if (row < BN && gn < Nc && gk < Kc) {   // ldb is padded to a multiple of 8 with zeros
                     vh = *reinterpret_cast<const uint4*>(Bh + (long long)gn * ldb + gk);
                     vl = *reinterpret_cast<const uint4*>(Bl + (long long)gn * ldb + gk);
                 }
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, long
 
     auto store_tiles = [&]() {
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
+        for (int p = 0; p < PA; ++p) {
             const int idx = p * 256 + tid, row = idx >> 4, k = (idx & 15) * 2;
             if constexpr (MODE == MODE_F64) {
                 sm.a[row * PAD + k] = ra[p].x;
@@ -168,14 +171,14 @@ __global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, long
         }
         if constexpr (MODE == MODE_F64) {
 #pragma unroll
-            for (int p = 0; p < 8; ++p) {
+            for (int p = 0; p < PB64; ++p) {
                 const int idx = p * 256 + tid, row = idx >> 4, k = (idx & 15) * 2;
                 sm.b[row * PAD + k] = rb64[p].x;
                 sm.b[row * PAD + k + 1] = rb64[p].y;
             }
         } else if constexpr (MODE == MODE_F32) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
+            for (int p = 0; p < PB32; ++p) {
                 const int idx = p * 256 + tid, row = idx >> 3, k = (idx & 7) * 4;
                 sm.b[row * PAD + k] = rb32[p].x;
                 sm.b[row * PAD + k + 1] = rb32[p].y;
@@ -184,10 +187,12 @@ __global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, long
             }
         } else {
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
+            for (int p = 0; p < PB16; ++p) {
                 const int idx = p * 256 + tid, row = idx >> 2, k = (idx & 3) * 8;
-                *reinterpret_cast<uint4*>(&sm.bhi[row * PAD + k]) = rbh[p];
-                *reinterpret_cast<uint4*>(&sm.blo[row * PAD + k]) = rbl[p];
+                if (row < BN) {
+                    *reinterpret_cast<uint4*>(&sm.bhi[row * PAD + k]) = rbh[p];
+                    *reinterpret_cast<uint4*>(&sm.blo[row * PAD + k]) = rbl[p];
+                }
             }
         }
     };
@@ -200,20 +205,23 @@ __global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, long
         __syncthreads();
         if (kt + 1 < nk) load_tiles((kt + 1) * BK);
         if constexpr (MODE == MODE_BF16X3) {
-            bf8 ah[4], al[4], bh[4], bl[4];
+            bf8 ah[WM], al[WM], bh[WN], bl[WN];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = wm * 64 + i * 16 + l16;
+            for (int i = 0; i < WM; ++i) {
+                const int r = wm * (16 * WM) + i * 16 + l16;
                 ah[i] = *reinterpret_cast<const bf8*>(&sm.ahi[r * PAD + lq * 8]);
                 al[i] = *reinterpret_cast<const bf8*>(&sm.alo[r * PAD + lq * 8]);
-                const int cN = wn * 64 + i * 16 + l16;
-                bh[i] = *reinterpret_cast<const bf8*>(&sm.bhi[cN * PAD + lq * 8]);
-                bl[i] = *reinterpret_cast<const bf8*>(&sm.blo[cN * PAD + lq * 8]);
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < WN; ++j) {
+                const int cN = wn * (16 * WN) + j * 16 + l16;
+                bh[j] = *reinterpret_cast<const bf8*>(&sm.bhi[cN * PAD + lq * 8]);
+                bl[j] = *reinterpret_cast<const bf8*>(&sm.blo[cN * PAD + lq * 8]);
+            }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
@@ -222,16 +230,15 @@ __global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, long
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
                 using e_t = typename std::conditional<MODE == MODE_F64, double, float>::type;
-                e_t av[4], bv[4];
+                e_t av[WM], bv[WN];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    av[i] = sm.a[(wm * 64 + i * 16 + l16) * PAD + kk + lq];
-                    bv[i] = sm.b[(wn * 64 + i * 16 + l16) * PAD + kk + lq];
-                }
+                for (int i = 0; i < WM; ++i) av[i] = sm.a[(wm * (16 * WM) + i * 16 + l16) * PAD + kk + lq];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < WN; ++j) bv[j] = sm.b[(wn * (16 * WN) + j * 16 + l16) * PAD + kk + lq];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j) {
                         if constexpr (MODE == MODE_F64)
                             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
                         else
@@ -242,19 +249,56 @@ __global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, long
     }
     // epilogue: the f32-output MFMAs leave D[4*lq + v][l16] of each 16×16 block in lane
     // (lq, l16); the f64 one leaves D[lq + 4*v][l16].
+    double* __restrict__ C = g.C;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = n0 + wn * 64 + j * 16 + l16;
+        for (int j = 0; j < WN; ++j) {
+            const int col = n0 + wn * (16 * WN) + j * 16 + l16;
             if (col >= Nc) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rl = (MODE == MODE_F64) ? (lq + 4 * v) : (lq * 4 + v);
-                const int row = m0 + wm * 64 + i * 16 + rl;
+                const int row = m0 + wm * (16 * WM) + i * 16 + rl;
                 if (row < M) C[(long long)row * ldc + col] = (double)acc[i][j][v];
             }
         }
+}
+
+// Single problem; blocks are dispatched round-robin over the 8 XCDs, so the tile index is
+// remapped to give each XCD a contiguous band of tiles (shared A rows and B in its L2).
+template <int MODE, int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm(GemmTask g) {
+    __shared__ Lds<MODE, 32 * WM, 32 * WN> sm;
+    const int per = gridDim.x / 8;
+    const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= g.tiles_m * g.tiles_n) return;
+    gemm_tile<MODE, WM, WN>(g, tile, sm);
+}
+
+// Index of the task owning virtual block v: the largest t with start[t] <= v.
+__device__ __forceinline__ int find_task(const int* __restrict__ start, int ntask, int v) {
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Many problems in one launch: task t owns tiles [start[t], start[t+1]) of the
+// concatenated tile list; the XCD remap keeps each problem's tiles on few XCDs.
+template <int MODE, int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict__ tasks,
+                                                      const int* __restrict__ start, int ntask, int total) {
+    __shared__ Lds<MODE, 32 * WM, 32 * WN> sm;
+    const int per = gridDim.x / 8;
+    const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (v >= total) return;
+    const int t = find_task(start, ntask, v);
+    const GemmTask g = tasks[t];
+    gemm_tile<MODE, WM, WN>(g, v - start[t], sm);
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -348,13 +392,12 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {   // 
     return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
 
-__global__ __launch_bounds__(256) void k_tri_seg(double2* __restrict__ X, TriFactors f, int len, int na, int nq,
-                                                 long long se, long long sa, long long sq, int fa) {
-    __shared__ double2 tf_[256];
-    __shared__ double2 tb_[256][2];
+__device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const TriFactors& f, int len, int na,
+                                              int nq, long long se, long long sa, long long sq, int fa, int blk,
+                                              double2 (&tf_)[256], double2 (&tb_)[256][2]) {
     const int K = f.K, L = f.L, SYS = 256 / K;
     const int tid = threadIdx.x, k = tid / SYS, sl = tid - k * SYS;
-    const long long sysg = (long long)blockIdx.x * SYS + sl;
+    const long long sysg = (long long)blk * SYS + sl;
     const bool valid = sysg < (long long)na * nq;
     const int a = valid ? (int)(sysg % na) : 0, q = valid ? (int)(sysg / na) : 0;
     double2* x = X + (long long)q * sq + (long long)a * sa;
@@ -446,6 +489,24 @@ __global__ __launch_bounds__(256) void k_tri_seg(double2* __restrict__ X, TriFac
     }
 }
 
+__global__ __launch_bounds__(256) void k_tri_seg(double2* __restrict__ X, TriFactors f, int len, int na, int nq,
+                                                 long long se, long long sa, long long sq, int fa) {
+    __shared__ double2 tf_[256];
+    __shared__ double2 tb_[256][2];
+    tri_seg_block(X, f, len, na, nq, se, sa, sq, fa, blockIdx.x, tf_, tb_);
+}
+
+__global__ __launch_bounds__(256) void k_tri_seg_grouped(const TriTask* __restrict__ tasks,
+                                                         const int* __restrict__ start, int ntask, int total) {
+    __shared__ double2 tf_[256];
+    __shared__ double2 tb_[256][2];
+    const int v = blockIdx.x;
+    if (v >= total) return;
+    const int t = find_task(start, ntask, v);
+    const TriTask& g = tasks[t];
+    tri_seg_block(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], tf_, tb_);
+}
+
 static inline uint16_t host_bf16(float f) {
     uint32_t u;
     std::memcpy(&u, &f, 4);
@@ -512,29 +573,99 @@ int upload_dense_b(Ctx* c, hipStream_t) {
     return upload_one(c->inv, e);
 }
 
-static int launch_gemm(int precision, const double* A, long long lda, const DenseB& B, int N, double* C,
-                       long long ldc, int M, hipStream_t st) {
-    const int Nc = 2 * N, Kc = 2 * N, ldb = bexp_ld(N);
-    const int tiles_m = (M + BM - 1) / BM, tiles_n = (Nc + BN - 1) / BN;
-    const int nt = tiles_m * tiles_n;
-    const int nblk = ((nt + 7) / 8) * 8;
-    KScope ks(SG_K_GEMM, 2.0 * M * (double)Nc * (double)Kc, st);
-    switch (precision) {
-        case SG_PREC_F64:
-            hipLaunchKernelGGL(k_gemm<MODE_F64>, dim3(nblk), dim3(256), 0, st, A, lda, (const void*)B.f64,
-                               (const void*)nullptr, (long long)ldb, C, ldc, M, Nc, Kc, tiles_m, tiles_n);
-            break;
-        case SG_PREC_F32:
-            hipLaunchKernelGGL(k_gemm<MODE_F32>, dim3(nblk), dim3(256), 0, st, A, lda, (const void*)B.f32,
-                               (const void*)nullptr, (long long)ldb, C, ldc, M, Nc, Kc, tiles_m, tiles_n);
-            break;
-        case SG_PREC_BF16X3:
-            hipLaunchKernelGGL(k_gemm<MODE_BF16X3>, dim3(nblk), dim3(256), 0, st, A, lda, (const void*)B.bf_hi,
-                               (const void*)B.bf_lo, (long long)ldb, C, ldc, M, Nc, Kc, tiles_m, tiles_n);
-            break;
-        default:
-            return fail(SG_EINVAL, "unknown precision");
+// Tile shapes of the GEMM (BM × BN): 128×128, 64×128, 64×64.
+static const int kGemmWM[SG_GEMM_NCFG] = {4, 2, 2};
+static const int kGemmWN[SG_GEMM_NCFG] = {4, 4, 2};
+
+void gemm_tiles(int cfg, int M, int Nc, int* tiles_m, int* tiles_n) {
+    const int bm = 32 * kGemmWM[cfg], bn = 32 * kGemmWN[cfg];
+    *tiles_m = (M + bm - 1) / bm;
+    *tiles_n = (Nc + bn - 1) / bn;
+}
+
+GemmTask make_gemm_task(int precision, const double* A, const DenseB& B, int N, double* C, int M, int cfg) {
+    GemmTask g{};
+    g.A = A;
+    g.C = C;
+    g.Bt0 = precision == SG_PREC_F64 ? (const void*)B.f64
+          : precision == SG_PREC_F32 ? (const void*)B.f32 : (const void*)B.bf_hi;
+    g.Bt1 = precision == SG_PREC_BF16X3 ? (const void*)B.bf_lo : nullptr;
+    g.lda = 2LL * N;
+    g.ldc = 2LL * N;
+    g.ldb = bexp_ld(N);
+    g.M = M;
+    g.Nc = 2 * N;
+    g.Kc = 2 * N;
+    gemm_tiles(cfg, M, g.Nc, &g.tiles_m, &g.tiles_n);
+    return g;
+}
+
+template <int MODE>
+static void launch_gemm_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks, const int* d_start, int ntask,
+                            int total, hipStream_t st) {
+    const int nt = d_tasks ? total : g.tiles_m * g.tiles_n;
+    const dim3 grid(((nt + 7) / 8) * 8), blk(256);
+#define SG_GEMM_CFG(C_, WM_, WN_)                                                                          \
+    case C_:                                                                                               \
+        if (d_tasks) hipLaunchKernelGGL((k_gemm_grouped<MODE, WM_, WN_>), grid, blk, 0, st, d_tasks, d_start, ntask, total); \
+        else hipLaunchKernelGGL((k_gemm<MODE, WM_, WN_>), grid, blk, 0, st, g);                              \
+        break;
+    switch (cfg) {
+        SG_GEMM_CFG(0, 4, 4)
+        SG_GEMM_CFG(1, 2, 4)
+        SG_GEMM_CFG(2, 2, 2)
+        default: break;
     }
+#undef SG_GEMM_CFG
+}
+
+static int dispatch_gemm(int precision, int cfg, const GemmTask& g, const GemmTask* d_tasks, const int* d_start,
+                         int ntask, int total, hipStream_t st) {
+    if (cfg < 0 || cfg >= SG_GEMM_NCFG) return fail(SG_EINVAL, "unknown GEMM tile configuration");
+    switch (precision) {
+        case SG_PREC_F64: launch_gemm_cfg<MODE_F64>(cfg, g, d_tasks, d_start, ntask, total, st); break;
+        case SG_PREC_F32: launch_gemm_cfg<MODE_F32>(cfg, g, d_tasks, d_start, ntask, total, st); break;
+        case SG_PREC_BF16X3: launch_gemm_cfg<MODE_BF16X3>(cfg, g, d_tasks, d_start, ntask, total, st); break;
+        default: return fail(SG_EINVAL, "unknown precision");
+    }
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+static int launch_gemm(int precision, const double* A, const DenseB& B, int N, double* C, int M, hipStream_t st) {
+    const GemmTask g = make_gemm_task(precision, A, B, N, C, M, 0);
+    KScope ks(SG_K_GEMM, 2.0 * M * (double)g.Nc * (double)g.Kc, st);
+    return dispatch_gemm(precision, 0, g, nullptr, nullptr, 0, 0, st);
+}
+
+int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const int* d_start, int ntask, int total,
+                        double flops, hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_GEMM, flops, st);
+    return dispatch_gemm(precision, cfg, GemmTask{}, d_tasks, d_start, ntask, total, st);
+}
+
+TriTask make_tri_task(const TriFactors& f, double2* X, int n, int Q, int dim) {
+    TriTask t{};
+    t.X = X;
+    t.f = f;
+    t.len = n;
+    if (dim == 2) {
+        t.na = n; t.nq = Q; t.se = n; t.sa = 1; t.sq = (long long)n * n; t.fa = 1;
+    } else {
+        t.na = 1; t.nq = Q; t.se = 1; t.sa = 0; t.sq = n; t.fa = 0;
+    }
+    const long long nth = (long long)t.na * t.nq;
+    const int sys = f.K >= 1 ? 256 / f.K : 256;
+    t.nblocks = (int)((nth + sys - 1) / sys);
+    return t;
+}
+
+int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+                       hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_TRI, bytes, st);
+    hipLaunchKernelGGL(k_tri_seg_grouped, dim3(total), dim3(256), 0, st, d_tasks, d_start, ntask, total);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
@@ -579,13 +710,11 @@ int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, 
     }
     const int M = c->Q * n;
     double2* t = c->d_tmp_pc;
-    int rc = launch_gemm(precision, reinterpret_cast<const double*>(r), 2LL * n, c->fwd, n,
-                         reinterpret_cast<double*>(t), 2LL * n, M, st);
+    int rc = launch_gemm(precision, reinterpret_cast<const double*>(r), c->fwd, n, reinterpret_cast<double*>(t), M, st);
     if (rc) return rc;
     rc = launch_tri(f, t, n, c->Q, 2, st);
     if (rc) return rc;
-    return launch_gemm(precision, reinterpret_cast<const double*>(t), 2LL * n, c->inv, n,
-                       reinterpret_cast<double*>(z), 2LL * n, M, st);
+    return launch_gemm(precision, reinterpret_cast<const double*>(t), c->inv, n, reinterpret_cast<double*>(z), M, st);
 }
 
 }  // namespace sgi

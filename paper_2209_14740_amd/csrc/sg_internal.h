@@ -64,6 +64,46 @@ struct DenseB {
     uint16_t* bf_lo = nullptr;
 };
 
+// One dense problem C[M][Nc] = A[M][Kc] · B of the preconditioner transforms, Bt[Nc][Kc]
+// n-major in the compute precision; A and C are FP64 (complex interleaved).
+struct GemmTask {
+    const double* A;
+    const void* Bt0;
+    const void* Bt1;
+    double* C;
+    long long lda, ldb, ldc;
+    int M, Nc, Kc, tiles_m, tiles_n;
+};
+enum { SG_GEMM_NCFG = 3 };   // tile shapes 128×128, 64×128, 64×64
+
+// One set of tridiagonal solves: element i of system (q, a) is X[q*sq + a*sa + i*se],
+// the factors of system a are at column a*fa of f.
+struct TriTask {
+    double2* X;
+    TriFactors f;
+    int len, na, nq, fa;
+    long long se, sa, sq;
+    int nblocks;
+};
+
+// One vector operation of a grouped launch (one solve of a batch).  Fields not used by
+// an operation are ignored.
+struct VecTask {
+    const double2* V;        // basis vectors V_k = V + k*ldv
+    long long ldv;
+    const double* scale;     // v_k = scale[k] V_k (device, may be null = 1)
+    const double2* coef;     // update / combination coefficients (device)
+    double2* w;              // vector updated in place (update, norm) or written (axpby)
+    const double2* x;        // axpby operands: w = a x + b y (y may be null)
+    const double2* y;
+    double2 a, b;
+    double2* partial;        // first-stage partial sums [block][nout]
+    double2* out;            // second-stage results
+    long long n;             // vector length
+    int nv;                  // number of basis vectors
+    int nblocks;             // blocks of the first-stage kernels
+};
+
 struct Workspace {
     int m = 0;                 // restart length the buffers were sized for
     bool flexible = false;
@@ -137,7 +177,6 @@ struct Ctx {
     std::vector<cplx> mu;              // eigenvalues of (T - iτE)v = μ D v
     DenseB fwd, inv;                   // B operands for R·Ṽ and W·Ṽᵀ
     TriFactors tri[2];                 // [0]: mean value A_0, [1]: mean CSL M_0
-    TriFactors tri32[2];               // unused placeholder for reduced-precision factors
 
     Workspace ws;
     Prof prof;
@@ -157,6 +196,13 @@ int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st);
 // precond.hip
 int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, hipStream_t st);
 int upload_dense_b(Ctx* c, hipStream_t st);
+void gemm_tiles(int cfg, int M, int Nc, int* tiles_m, int* tiles_n);
+GemmTask make_gemm_task(int precision, const double* A, const DenseB& B, int N, double* C, int M, int cfg);
+int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const int* d_start, int ntask, int total,
+                        double flops, hipStream_t st);
+TriTask make_tri_task(const TriFactors& f, double2* X, int n, int Q, int dim);
+int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+                       hipStream_t st);
 
 // krylov.hip
 int ensure_workspace(Ctx* c, int m, bool flexible);
@@ -177,6 +223,24 @@ int launch_axpby(long long n, double2 a, const double2* x, double2 b, const doub
                  hipStream_t st);
 int launch_scale_copy(long long n, double a, const double2* x, double2* out, hipStream_t st);
 int reduction_blocks(long long n);
+// Grouped forms: task t of d_tasks owns blocks [start[t], start[t+1]) of the launch.
+int launch_multidot_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+                            hipStream_t st);
+int launch_reduce_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int mode,
+                          hipStream_t st);
+int launch_upd_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv, bool dot,
+                       double bytes, hipStream_t st);
+int launch_lincomb_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv,
+                           double bytes, hipStream_t st);
+int launch_axpby_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+                         hipStream_t st);
+
+// batched.cpp
+int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, double2* const* x,
+                      const sg_solve_opts* o, sg_solve_stats* stats, hipStream_t stream);
+int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out, hipStream_t stream);
+int tune_get(int n, int Q, int precision);
+void tune_set(int n, int Q, int precision, int cfg);
 
 // gmres.cpp
 int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_precond_cb cb,

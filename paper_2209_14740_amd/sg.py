@@ -74,6 +74,11 @@ def lib():
     L.sg_fgmres.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), PRECOND_CB, vp, C.POINTER(SolveStats), vp]
     L.sg_cgs2.argtypes = [ll, i, vp, vp, vp, vp]
     L.sg_norm.argtypes = [ll, vp, C.POINTER(d), vp]
+    L.sg_gmres_batched.argtypes = [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
+                                   C.POINTER(SolveStats), vp]
+    L.sg_autotune.argtypes = [i, C.POINTER(vp), i, i, C.POINTER(d), vp]
+    L.sg_tune_get.argtypes = [i, i, i]
+    L.sg_tune_set.argtypes = [i, i, i, i]
     L.sg_set_profiling.argtypes = [vp, i]
     L.sg_kernel_times.argtypes = [vp, i, C.POINTER(d), C.POINTER(ll), C.POINTER(d)]
     L.sg_strerror.argtypes = [i]
@@ -81,7 +86,8 @@ def lib():
     L.sg_last_error.argtypes = []
     L.sg_last_error.restype = C.c_char_p
     for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
-                 "sg_cgs2", "sg_norm", "sg_set_profiling", "sg_kernel_times"):
+                 "sg_cgs2", "sg_norm", "sg_set_profiling", "sg_kernel_times", "sg_gmres_batched", "sg_autotune",
+                 "sg_tune_get", "sg_tune_set"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -235,6 +241,47 @@ def _wrap_device(ptr, n):
     return torch.as_tensor(h, device="cuda")
 
 
+TILES = {"128x128": 0, "64x128": 1, "64x64": 2}
+
+
+def gmres_batched(ops, bs, xs=None, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8, stream=None):
+    """Batched right-preconditioned GMRES over independent operators (``SG`` objects);
+    returns (xs, status, [info per instance])."""
+    cnt = len(ops)
+    if len(bs) != cnt or (xs is not None and len(xs) != cnt):
+        raise SGError("ops, bs and xs must have the same length")
+    xs = [op.empty() for op in ops] if xs is None else xs
+    for op, b, x in zip(ops, bs, xs):
+        if b.numel() != op.size or x.numel() != op.size:
+            raise SGError("vector length does not match its operator")
+    H = (C.c_void_p * cnt)(*[op._h.value for op in ops])
+    B = (C.c_void_p * cnt)(*[_ptr(b) for b in bs])
+    X = (C.c_void_p * cnt)(*[_ptr(x) for x in xs])
+    o = SolveOpts(restart, maxit, PC[pc], PREC[precision], tol, 1, None, 0)
+    st = (SolveStats * cnt)()
+    rc = check(lib().sg_gmres_batched(cnt, H, B, X, C.byref(o), st, C.c_void_p(_stream(stream))),
+               "sg_gmres_batched")
+    return xs, rc, [st[i].as_dict() for i in range(cnt)]
+
+
+def autotune(ops, precision="f32", reps=5, stream=None) -> float:
+    """Tile-shape autotuning of the preconditioner GEMMs for the shapes of ``ops``;
+    returns the GPU milliseconds spent."""
+    cnt = len(ops)
+    H = (C.c_void_p * max(cnt, 1))(*[op._h.value for op in ops])
+    ms = C.c_double()
+    check(lib().sg_autotune(cnt, H, PREC[precision], reps, C.byref(ms), C.c_void_p(_stream(stream))), "sg_autotune")
+    return ms.value
+
+
+def tune_get(n, Q, precision="f32") -> int:
+    return lib().sg_tune_get(n, Q, PREC[precision])
+
+
+def tune_set(n, Q, precision, tile):
+    check(lib().sg_tune_set(n, Q, PREC[precision], TILES.get(tile, tile)), "sg_tune_set")
+
+
 def cgs2(V, w, stream=None):
     """One CGS2 step against the orthonormal rows of V (nv × n); returns h (nv+1,) and normalises w."""
     nv, n = V.shape
@@ -252,5 +299,5 @@ def norm(x, stream=None) -> float:
 
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
-            "sg_fgmres", "sg_cgs2", "sg_norm", "sg_set_profiling", "sg_kernel_times", "sg_strerror",
-            "sg_last_error"]
+            "sg_fgmres", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_cgs2", "sg_norm",
+            "sg_set_profiling", "sg_kernel_times", "sg_strerror", "sg_last_error"]
