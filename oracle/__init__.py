@@ -16,11 +16,11 @@ Modules
   precond   mean-value (A_0), mean-CSL (M_0) and full CSL (M) preconditioners via sparse LU
   krylov    restarted right-preconditioned GMRES(m), FGMRES(m), stationary iteration
   spectral  dense condition numbers, spectra and norm bounds (Theorems 4.1, 5.1, 5.3)
-  mixed     rounding emulation for reduced-precision variants
-  unet      numpy reference of the convolutional correction network
+  unet      numpy reference of the convolutional correction network of the learned
+            preconditioner (forward, backward, Adam, SG vector <-> tensor maps)
 
 Parity status: every function is pinned by tests against values printed in
-the paper, closed forms or invariants, except ``unet`` (no network exists in
-the paper: parity unpinned against the paper; pinned by finite differences)
-and ``mixed`` (emulation only: parity unpinned against the paper).
+the paper, closed forms or invariants.  ``unet`` has no counterpart in the paper
+(parity unpinned against the paper); it is pinned against library correlation,
+adjoint identities, central finite differences and the closed-form Adam step.
 """
