@@ -186,6 +186,7 @@ enum {
     SG_K_DOT = 3,       /* CGS2 multi-dot              (algorithmic bytes)            */
     SG_K_AXPY = 4,      /* CGS2 multi-axpy / updates   (algorithmic bytes)            */
     SG_K_NORM = 5,      /* norms and second-stage reductions (algorithmic bytes)      */
+    SG_K_NET = 6,       /* correction network convolutions (algorithmic flops)        */
     SG_K_NKINDS = 8
 };
 /* on != 0 enables recording and clears the counters. */
@@ -194,6 +195,51 @@ int  sg_set_profiling(sg_handle h, int on);
  * nkinds entries, any may be NULL): total milliseconds, launch count, and the summed
  * algorithmic work (bytes or flops as listed above). */
 int  sg_kernel_times(sg_handle h, int nkinds, double* ms, long long* count, double* work);
+
+/* ---- Learned correction network ----------------------------------------------------
+ * A 3-level convolutional U-Net (widths 32, 64, 128; 3×3 convolutions with ReLU, 2×2
+ * average pooling, nearest upsampling with skip concatenation, linear 1×1 head) that
+ * maps a residual v (2Q channels: Re, Im of each PC block, scaled to unit RMS) and the
+ * s+1 wavenumber coefficient fields k_l/k̄ to a correction of the mean-value block solve
+ * A_0^{-1} v (Section 5), used as the preconditioner
+ *     z = A_0^{-1} v + ||A_0^{-1} v|| / sqrt(Q n²) · N(v)
+ * inside flexible GMRES (pc = SG_PC_MEAN_NET).  Tensors are BF16 with FP32 accumulation on
+ * the matrix cores; master weights, gradients and Adam state are FP32.  Parameters are a
+ * flat FP32 vector: per layer W[c_out][k][k][c_in] then b[c_out], layers enc0a, enc0b,
+ * enc1a, enc1b, bota, botb, dec1a, dec1b, dec0a, dec0b, head. */
+typedef struct sg_net_s* sg_net;
+/* Network for Q PC coefficients and s random variables (c_in = 2Q+s+1, c_out = 2Q),
+ * He-normal weights from a SplitMix64 stream seeded by `seed`; on the current device. */
+int  sg_net_create(int Q, int s, unsigned long long seed, sg_net* out);
+void sg_net_destroy(sg_net net);
+long long sg_net_num_params(sg_net net);
+/* Host FP32 arrays of sg_net_num_params entries; set also resets the Adam state. */
+int  sg_net_get_params(sg_net net, float* host);
+int  sg_net_set_params(sg_net net, const float* host);
+/* Forward pass on `batch` NHWC images of H×H pixels (H a multiple of 4): x device FP32
+ * [batch][H][H][c_in], y device FP32 [batch][H][H][c_out]. */
+int  sg_net_forward_nhwc(sg_net net, int batch, int H, const float* x, float* y, hipStream_t stream);
+/* Mean squared error against t (device FP32 [batch][H][H][c_out]) and its gradient with
+ * respect to the parameters (kept for sg_net_adam_step; copied to grad_host if not NULL). */
+int  sg_net_grad_nhwc(sg_net net, int batch, int H, const float* x, const float* t, double* loss,
+                      float* grad_host, hipStream_t stream);
+/* One Adam step (β1 0.9, β2 0.999, ε 1e-8) with the last computed gradient. */
+int  sg_net_adam_step(sg_net net, float lr, hipStream_t stream);
+/* One training step on `batch` pairs (r_i, e_i) with A e_i = r_i of the problems
+ * handles[i] (2D, same n, Q and s as the network): target N(r_i) = e_i - A_0^{-1} r_i in
+ * the units above, A_0^{-1} in `precision`; mean loss returned in *loss (may be NULL). */
+int  sg_net_train_pairs(sg_net net, int batch, const sg_handle* handles, const sg_c64* const* r,
+                        const sg_c64* const* e, float lr, int precision, double* loss, hipStream_t stream);
+/* Binary parameter file (header with Q, s and the parameter count, then FP32 values). */
+int  sg_net_save(sg_net net, const char* path);
+int  sg_net_load(sg_net net, const char* path);
+/* Attach a network (not owned; NULL detaches) to a handle for SG_PC_MEAN_NET.  With it,
+ * sg_precond computes the learned preconditioner (r and z must not alias) and sg_fgmres
+ * runs one cycle of flexible GMRES with it; if that cycle does not reach the tolerance
+ * (or the network yields non-finite values), plain A_0-preconditioned GMRES continues
+ * from the current iterate (from zero if it is not finite) and the call returns
+ * SG_FALLBACK_USED with stats->fallback = 1. */
+int  sg_attach_net(sg_handle h, sg_net net);
 
 const char* sg_strerror(int status);
 const char* sg_last_error(void);

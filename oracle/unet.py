@@ -31,9 +31,16 @@ s+1 coefficient fields k_l / k̄; the grid is zero-padded to H = W = ceil(n/4)·
 channels 2q, 2q+1 are Re, Im of the correction of block q in units of
 ||A_0^{-1} r|| / sqrt(Q·n²).
 
+Storage precision.  The network keeps its input, its convolution weights and every
+stored activation and activation gradient in bfloat16 (8-bit exponent, 8-bit significand,
+round to nearest even), with biases, the head output, accumulation and parameter
+gradients in higher precision.  ``forward`` and ``loss_and_grad`` take an optional
+rounding function applied at exactly those storage points (``bf16_round``); without it
+they are the exact FP64 definitions.
+
 Parity unpinned against the paper (no network exists there); pinned by the tests
-against library correlation, adjoint identities, central finite differences and the
-closed-form first Adam step.
+against library correlation, adjoint identities, central finite differences, the
+closed-form first Adam step, and exact bfloat16 values.
 """
 from __future__ import annotations
 
@@ -130,22 +137,37 @@ def relu(z):
     return np.maximum(z, 0.0)
 
 
+def bf16_round(a) -> np.ndarray:
+    """Nearest bfloat16 value (ties to even) of each entry, returned as float64: the float32
+    value of the entry with its 16 low significand bits rounded away."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _identity(a):
+    return a
+
+
 # ---- the network ------------------------------------------------------------------------
 
-def forward(theta: np.ndarray, x: np.ndarray, c_out: int, keep: bool = False):
-    """Network output for one NHWC input; with keep=True also the intermediate tensors."""
-    P = unflatten(theta, x.shape[2], c_out)
-    t = {"x": x}
+def forward(theta: np.ndarray, x: np.ndarray, c_out: int, keep: bool = False, rnd=None):
+    """Network output for one NHWC input; with keep=True also the intermediate tensors.
+    rnd: rounding applied to the input, the weights and every stored activation."""
+    rnd = rnd or _identity
+    P = {k: (rnd(w), b) for k, (w, b) in unflatten(theta, x.shape[2], c_out).items()}
+    t = {"x": rnd(x)}
 
     def cr(name, inp):
-        return relu(conv(inp, *P[name]))
+        return rnd(relu(conv(inp, *P[name])))
 
-    t["e0a"] = cr("enc0a", x)
+    t["e0a"] = cr("enc0a", t["x"])
     t["s0"] = cr("enc0b", t["e0a"])
-    t["p0"] = pool(t["s0"])
+    t["p0"] = rnd(pool(t["s0"]))
     t["e1a"] = cr("enc1a", t["p0"])
     t["s1"] = cr("enc1b", t["e1a"])
-    t["p1"] = pool(t["s1"])
+    t["p1"] = rnd(pool(t["s1"]))
     t["ba"] = cr("bota", t["p1"])
     t["bt"] = cr("botb", t["ba"])
     t["c1"] = np.concatenate([up(t["bt"]), t["s1"]], axis=2)
@@ -155,6 +177,7 @@ def forward(theta: np.ndarray, x: np.ndarray, c_out: int, keep: bool = False):
     t["d0a"] = cr("dec0a", t["c0"])
     t["d0"] = cr("dec0b", t["d0a"])
     t["y"] = conv(t["d0"], *P["head"])
+    t["P"] = P
     return (t["y"], t) if keep else t["y"]
 
 
@@ -162,14 +185,16 @@ def loss(y: np.ndarray, target: np.ndarray) -> float:
     return float(np.mean((y - target) ** 2))
 
 
-def loss_and_grad(theta: np.ndarray, x: np.ndarray, target: np.ndarray):
-    """Loss and its gradient with respect to theta (flat) and to the input x."""
+def loss_and_grad(theta: np.ndarray, x: np.ndarray, target: np.ndarray, rnd=None):
+    """Loss and its gradient with respect to theta (flat) and to the input x.  rnd: rounding
+    of the forward pass (see ``forward``) and of every stored activation gradient."""
+    rnd = rnd or _identity
     c_in, c_out = x.shape[2], target.shape[2]
-    P = unflatten(theta, c_in, c_out)
-    y, t = forward(theta, x, c_out, keep=True)
+    y, t = forward(theta, x, c_out, keep=True, rnd=rnd)
+    P = t["P"]
     L = loss(y, target)
     g = {}
-    dy = 2.0 * (y - target) / y.size
+    dy = rnd(2.0 * (y - target) / y.size)
 
     def back(name, inp, out, dout):
         # out = relu(conv(inp)) except for the head (no activation)
@@ -178,24 +203,24 @@ def loss_and_grad(theta: np.ndarray, x: np.ndarray, target: np.ndarray):
         g[name] = (dw, db)
         return dx
 
-    dd0 = back("head", t["d0"], None, dy)
-    dd0a = back("dec0b", t["d0a"], t["d0"], dd0)
-    dc0 = back("dec0a", t["c0"], t["d0a"], dd0a)
+    dd0 = rnd(back("head", t["d0"], None, dy))
+    dd0a = rnd(back("dec0b", t["d0a"], t["d0"], dd0))
+    dc0 = rnd(back("dec0a", t["c0"], t["d0a"], dd0a))
     w1 = WIDTHS[1]
-    dd1 = up_backward(dc0[:, :, :w1])
+    dd1 = rnd(up_backward(dc0[:, :, :w1]))
     ds0 = dc0[:, :, w1:].copy()
-    dd1a = back("dec1b", t["d1a"], t["d1"], dd1)
-    dc1 = back("dec1a", t["c1"], t["d1a"], dd1a)
+    dd1a = rnd(back("dec1b", t["d1a"], t["d1"], dd1))
+    dc1 = rnd(back("dec1a", t["c1"], t["d1a"], dd1a))
     w2 = WIDTHS[2]
-    dbt = up_backward(dc1[:, :, :w2])
+    dbt = rnd(up_backward(dc1[:, :, :w2]))
     ds1 = dc1[:, :, w2:].copy()
-    dba = back("botb", t["ba"], t["bt"], dbt)
-    dp1 = back("bota", t["p1"], t["ba"], dba)
-    ds1 += pool_backward(dp1)
-    de1a = back("enc1b", t["e1a"], t["s1"], ds1)
-    dp0 = back("enc1a", t["p0"], t["e1a"], de1a)
-    ds0 += pool_backward(dp0)
-    de0a = back("enc0b", t["e0a"], t["s0"], ds0)
+    dba = rnd(back("botb", t["ba"], t["bt"], dbt))
+    dp1 = rnd(back("bota", t["p1"], t["ba"], dba))
+    ds1 = rnd(ds1 + pool_backward(dp1))
+    de1a = rnd(back("enc1b", t["e1a"], t["s1"], ds1))
+    dp0 = rnd(back("enc1a", t["p0"], t["e1a"], de1a))
+    ds0 = rnd(ds0 + pool_backward(dp0))
+    de0a = rnd(back("enc0b", t["e0a"], t["s0"], ds0))
     dx = back("enc0a", t["x"], t["e0a"], de0a)
     return L, flatten(g, c_in, c_out), dx
 

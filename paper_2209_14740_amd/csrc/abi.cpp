@@ -2,10 +2,12 @@
 // into status codes; none aborts.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
 
+#include "net_internal.h"
 #include "sg_internal.h"
 
 using sgi::Ctx;
@@ -103,6 +105,12 @@ int sg_precond(sg_handle h, int pc, int precision, const sg_c64* r, sg_c64* z, h
         Ctx* c = ctx(h);
         if (int rc = guard_device(c)) return rc;
         ProfBind pb(c);
+        if (pc == SG_PC_MEAN_NET) {
+            if (!c->net) return fail(SG_EINVAL, "sg_precond: no network attached");
+            if (precision < SG_PREC_F64 || precision > SG_PREC_BF16X3) return fail(SG_EINVAL, "unknown precision");
+            return sgi::net_precond(c->net, c, precision, reinterpret_cast<const double2*>(r),
+                                    reinterpret_cast<double2*>(z), stream);
+        }
         return sgi::launch_precond(c, pc, precision, reinterpret_cast<const double2*>(r),
                                    reinterpret_cast<double2*>(z), stream);
     })
@@ -127,8 +135,40 @@ int sg_fgmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts
         Ctx* c = ctx(h);
         if (int rc = guard_device(c)) return rc;
         ProfBind pb(c);
-        return sgi::run_gmres(c, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), opts, cb, user,
-                              true, stats, stream);
+        const double2* bb = reinterpret_cast<const double2*>(b);
+        double2* xx = reinterpret_cast<double2*>(x);
+        if (cb || !opts || opts->precond != SG_PC_MEAN_NET)
+            return sgi::run_gmres(c, bb, xx, opts, cb, user, true, stats, stream);
+        if (!c->net) return fail(SG_EINVAL, "sg_fgmres: no network attached");
+        // one cycle of FGMRES with the learned preconditioner
+        sg_solve_opts o1 = *opts;
+        o1.maxit = std::min(opts->maxit, opts->restart);
+        sg_solve_stats s1{};
+        int rc = sgi::run_gmres(c, bb, xx, &o1, nullptr, nullptr, true, &s1, stream);
+        if (rc == SG_OK) {
+            if (stats) *stats = s1;
+            return SG_OK;
+        }
+        if (rc < 0 && rc != SG_ENONFINITE && rc != SG_EBREAKDOWN) return rc;
+        // fallback: plain A_0-preconditioned GMRES, warm-started when the iterate is usable
+        const bool warm = rc == SG_ENOTCONV && std::isfinite(s1.relres_true) && s1.relres_true < 1.0;
+        sg_solve_opts o2 = *opts;
+        o2.precond = SG_PC_MEAN;
+        o2.x0_zero = warm ? 0 : 1;
+        o2.maxit = std::max(1, opts->maxit - s1.iters);
+        o2.hist = opts->hist && opts->hist_cap > s1.iters ? opts->hist + s1.iters : nullptr;
+        o2.hist_cap = o2.hist ? opts->hist_cap - s1.iters : 0;
+        sg_solve_stats s2{};
+        rc = sgi::run_gmres(c, bb, xx, &o2, nullptr, nullptr, false, &s2, stream);
+        s2.iters += s1.iters;
+        s2.restarts += s1.restarts;
+        s2.fallback = 1;
+        s2.t_precond += s1.t_precond;
+        s2.t_matvec += s1.t_matvec;
+        s2.t_orth += s1.t_orth;
+        s2.t_total += s1.t_total;
+        if (stats) *stats = s2;
+        return rc == SG_OK ? SG_FALLBACK_USED : rc;
     })
 }
 
@@ -233,6 +273,124 @@ int sg_tune_set(int n, int Q, int precision, int tile) {
         if (n < 1 || Q < 1 || precision < SG_PREC_F64 || precision > SG_PREC_BF16X3)
             return fail(SG_EINVAL, "invalid table key");
         sgi::tune_set(n, Q, precision, tile);
+        return SG_OK;
+    })
+}
+
+static sgi::Net* netp(sg_net n) { return reinterpret_cast<sgi::Net*>(n); }
+
+static int guard_net(sgi::Net* n) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SG_EHIP, "hipGetDevice failed");
+    if (dev != n->device) return fail(SG_EINVAL, "network was created on another device");
+    return SG_OK;
+}
+
+int sg_net_create(int Q, int s, unsigned long long seed, sg_net* out) {
+    SG_TRY({
+        if (!out) return fail(SG_EINVAL, "out is null");
+        *out = nullptr;
+        sgi::Net* n = nullptr;
+        int rc = sgi::net_create(Q, s, seed, &n);
+        if (rc) return rc;
+        *out = reinterpret_cast<sg_net>(n);
+        return SG_OK;
+    })
+}
+
+void sg_net_destroy(sg_net net) {
+    try {
+        delete netp(net);
+    } catch (...) {
+    }
+}
+
+long long sg_net_num_params(sg_net net) { return net ? netp(net)->nparams : 0; }
+
+int sg_net_get_params(sg_net net, float* host) {
+    SG_TRY({
+        if (!net || !host) return fail(SG_EINVAL, "null argument");
+        if (int rc = guard_net(netp(net))) return rc;
+        return sgi::net_get_params(netp(net), host);
+    })
+}
+
+int sg_net_set_params(sg_net net, const float* host) {
+    SG_TRY({
+        if (!net || !host) return fail(SG_EINVAL, "null argument");
+        if (int rc = guard_net(netp(net))) return rc;
+        return sgi::net_set_params(netp(net), host);
+    })
+}
+
+int sg_net_forward_nhwc(sg_net net, int batch, int H, const float* x, float* y, hipStream_t stream) {
+    SG_TRY({
+        if (!net || !x || !y) return fail(SG_EINVAL, "null argument");
+        if (int rc = guard_net(netp(net))) return rc;
+        return sgi::net_forward_nhwc(netp(net), batch, H, x, y, stream);
+    })
+}
+
+int sg_net_grad_nhwc(sg_net net, int batch, int H, const float* x, const float* t, double* loss, float* grad_host,
+                     hipStream_t stream) {
+    SG_TRY({
+        if (!net || !x || !t) return fail(SG_EINVAL, "null argument");
+        if (int rc = guard_net(netp(net))) return rc;
+        return sgi::net_grad_nhwc(netp(net), batch, H, x, t, loss, grad_host, stream);
+    })
+}
+
+int sg_net_adam_step(sg_net net, float lr, hipStream_t stream) {
+    SG_TRY({
+        if (!net || !(lr > 0)) return fail(SG_EINVAL, "invalid argument");
+        if (int rc = guard_net(netp(net))) return rc;
+        return sgi::net_adam_step(netp(net), lr, stream);
+    })
+}
+
+int sg_net_train_pairs(sg_net net, int batch, const sg_handle* handles, const sg_c64* const* r, const sg_c64* const* e,
+                       float lr, int precision, double* loss, hipStream_t stream) {
+    SG_TRY({
+        if (!net || !handles || !r || !e || batch < 1 || !(lr > 0)) return fail(SG_EINVAL, "invalid argument");
+        if (precision < SG_PREC_F64 || precision > SG_PREC_BF16X3) return fail(SG_EINVAL, "unknown precision");
+        if (int rc = guard_net(netp(net))) return rc;
+        std::vector<Ctx*> cs(batch);
+        std::vector<const double2*> rs(batch), es(batch);
+        for (int i = 0; i < batch; ++i) {
+            if (!handles[i]) return fail(SG_EINVAL, "null handle");
+            cs[i] = ctx(handles[i]);
+            rs[i] = reinterpret_cast<const double2*>(r[i]);
+            es[i] = reinterpret_cast<const double2*>(e[i]);
+        }
+        return sgi::net_train_pairs(netp(net), batch, cs.data(), rs.data(), es.data(), lr, precision, loss, stream);
+    })
+}
+
+int sg_net_save(sg_net net, const char* path) {
+    SG_TRY({
+        if (!net || !path) return fail(SG_EINVAL, "null argument");
+        return sgi::net_save(netp(net), path);
+    })
+}
+
+int sg_net_load(sg_net net, const char* path) {
+    SG_TRY({
+        if (!net || !path) return fail(SG_EINVAL, "null argument");
+        return sgi::net_load(netp(net), path);
+    })
+}
+
+int sg_attach_net(sg_handle h, sg_net net) {
+    SG_TRY({
+        if (!h) return fail(SG_EINVAL, "null handle");
+        Ctx* c = ctx(h);
+        if (net) {
+            sgi::Net* n = netp(net);
+            if (n->device != c->device) return fail(SG_EINVAL, "network and handle are on different devices");
+            if (c->dim != 2 || n->Q != c->Q || n->s != c->s)
+                return fail(SG_EINVAL, "network shape does not match the problem (2D, same Q and s)");
+        }
+        c->net = netp(net);
         return SG_OK;
     })
 }

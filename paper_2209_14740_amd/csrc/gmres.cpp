@@ -113,8 +113,10 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
     if (o->restart < 1 || o->restart > 512) return fail(SG_EINVAL, "restart must be in [1, 512]");
     if (o->maxit < 1) return fail(SG_EINVAL, "maxit must be >= 1");
     if (!(o->tol > 0)) return fail(SG_EINVAL, "tol must be positive");
-    if (!cb && (o->precond < SG_PC_NONE || o->precond > SG_PC_CSL_MEAN))
+    if (!cb && (o->precond < SG_PC_NONE || o->precond > SG_PC_MEAN_NET))
         return fail(SG_EINVAL, "unsupported built-in preconditioner");
+    if (!cb && o->precond == SG_PC_MEAN_NET && (!c->net || !flexible))
+        return fail(SG_EINVAL, "the learned preconditioner needs an attached network and flexible GMRES");
     const int m = o->restart;
     int rc = ensure_workspace(c, m, flexible);
     if (rc) return rc;
@@ -129,6 +131,7 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             int r = cb(user, reinterpret_cast<const sg_c64*>(in), reinterpret_cast<sg_c64*>(out), stream);
             return r == 0 ? SG_OK : fail(SG_EINVAL, "preconditioner callback returned " + std::to_string(r));
         }
+        if (o->precond == SG_PC_MEAN_NET) return net_precond(c->net, c, o->precision, in, out, stream);
         return launch_precond(c, o->precond, o->precision, in, out, stream);
     };
 

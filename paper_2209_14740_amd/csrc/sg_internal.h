@@ -149,6 +149,8 @@ struct KScope {
     }
 };
 
+struct Net;
+
 struct Ctx {
     int dim = 0, n = 0, s = 0, degree = 0, Q = 0;
     long long P = 0, nvec = 0;
@@ -182,6 +184,7 @@ struct Ctx {
     Prof prof;
     bool use_spec_apply = true;        // compile-time-specialised operator when available
     double2* d_tmp_pc = nullptr;       // preconditioner intermediate (nvec complex)
+    Net* net = nullptr;                // attached correction network (not owned)
     double t_setup_ms = 0;
 
     ~Ctx();
@@ -241,6 +244,9 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
 int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out, hipStream_t stream);
 int tune_get(int n, int Q, int precision);
 void tune_set(int n, int Q, int precision, int cfg);
+
+// net.cpp
+int net_precond(Net* n, Ctx* c, int precision, const double2* v, double2* z, hipStream_t st);
 
 // gmres.cpp
 int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_precond_cb cb,

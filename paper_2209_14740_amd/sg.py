@@ -79,6 +79,21 @@ def lib():
     L.sg_autotune.argtypes = [i, C.POINTER(vp), i, i, C.POINTER(d), vp]
     L.sg_tune_get.argtypes = [i, i, i]
     L.sg_tune_set.argtypes = [i, i, i, i]
+    f = C.c_float
+    L.sg_net_create.argtypes = [i, i, C.c_ulonglong, C.POINTER(vp)]
+    L.sg_net_destroy.argtypes = [vp]
+    L.sg_net_destroy.restype = None
+    L.sg_net_num_params.argtypes = [vp]
+    L.sg_net_num_params.restype = ll
+    L.sg_net_get_params.argtypes = [vp, C.POINTER(f)]
+    L.sg_net_set_params.argtypes = [vp, C.POINTER(f)]
+    L.sg_net_forward_nhwc.argtypes = [vp, i, i, vp, vp, vp]
+    L.sg_net_grad_nhwc.argtypes = [vp, i, i, vp, vp, C.POINTER(d), C.POINTER(f), vp]
+    L.sg_net_adam_step.argtypes = [vp, f, vp]
+    L.sg_net_train_pairs.argtypes = [vp, i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), f, i, C.POINTER(d), vp]
+    L.sg_net_save.argtypes = [vp, C.c_char_p]
+    L.sg_net_load.argtypes = [vp, C.c_char_p]
+    L.sg_attach_net.argtypes = [vp, vp]
     L.sg_set_profiling.argtypes = [vp, i]
     L.sg_kernel_times.argtypes = [vp, i, C.POINTER(d), C.POINTER(ll), C.POINTER(d)]
     L.sg_strerror.argtypes = [i]
@@ -87,7 +102,9 @@ def lib():
     L.sg_last_error.restype = C.c_char_p
     for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
                  "sg_cgs2", "sg_norm", "sg_set_profiling", "sg_kernel_times", "sg_gmres_batched", "sg_autotune",
-                 "sg_tune_get", "sg_tune_set"):
+                 "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
+                 "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step", "sg_net_train_pairs", "sg_net_save",
+                 "sg_net_load", "sg_attach_net"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -132,6 +149,7 @@ class SG:
         self.Q = q.value
         self.size = int(lib().sg_size(self._h))
         self._cb_keep = None
+        self._net = None
 
     @classmethod
     def from_instance(cls, inst, stream=None):
@@ -147,6 +165,11 @@ class SG:
             self.close()
         except Exception:
             pass
+
+    def attach_net(self, net):
+        """Attach a ``Net`` (or None) for pc="net"; the handle keeps a reference."""
+        check(lib().sg_attach_net(self._h, net._h if net is not None else None), "sg_attach_net")
+        self._net = net
 
     def basis(self) -> np.ndarray:
         q = C.c_int()
@@ -282,6 +305,83 @@ def tune_set(n, Q, precision, tile):
     check(lib().sg_tune_set(n, Q, PREC[precision], TILES.get(tile, tile)), "sg_tune_set")
 
 
+class Net:
+    """The learned correction network (``sg_net_*``)."""
+
+    def __init__(self, Q: int, s: int, seed: int = 0):
+        self._h = C.c_void_p()
+        check(lib().sg_net_create(Q, s, seed, C.byref(self._h)), "sg_net_create")
+        self.Q, self.s = Q, s
+        self.c_in, self.c_out = 2 * Q + s + 1, 2 * Q
+        self.num_params = int(lib().sg_net_num_params(self._h))
+
+    def close(self):
+        if self._h:
+            lib().sg_net_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.num_params, dtype=np.float32)
+        check(lib().sg_net_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))), "sg_net_get_params")
+        return out
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.size != self.num_params:
+            raise SGError("expected %d parameters" % self.num_params)
+        check(lib().sg_net_set_params(self._h, th.ctypes.data_as(C.POINTER(C.c_float))), "sg_net_set_params")
+
+    @staticmethod
+    def _f32(t, shape):
+        import torch
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == shape):
+            raise SGError("expected a contiguous float32 CUDA tensor of shape %s" % (shape,))
+        return t.data_ptr()
+
+    def forward_nhwc(self, x, stream=None):
+        import torch
+        B, H = x.shape[0], x.shape[1]
+        y = torch.empty((B, H, H, self.c_out), dtype=torch.float32, device="cuda")
+        check(lib().sg_net_forward_nhwc(self._h, B, H, C.c_void_p(self._f32(x, (B, H, H, self.c_in))),
+                                        C.c_void_p(y.data_ptr()), C.c_void_p(_stream(stream))), "sg_net_forward_nhwc")
+        return y
+
+    def grad_nhwc(self, x, t, stream=None):
+        B, H = x.shape[0], x.shape[1]
+        loss = C.c_double()
+        g = np.empty(self.num_params, dtype=np.float32)
+        check(lib().sg_net_grad_nhwc(self._h, B, H, C.c_void_p(self._f32(x, (B, H, H, self.c_in))),
+                                     C.c_void_p(self._f32(t, (B, H, H, self.c_out))), C.byref(loss),
+                                     g.ctypes.data_as(C.POINTER(C.c_float)), C.c_void_p(_stream(stream))),
+              "sg_net_grad_nhwc")
+        return loss.value, g
+
+    def adam_step(self, lr, stream=None):
+        check(lib().sg_net_adam_step(self._h, float(lr), C.c_void_p(_stream(stream))), "sg_net_adam_step")
+
+    def train_pairs(self, ops, rs, es, lr, precision="f64", stream=None) -> float:
+        cnt = len(ops)
+        H = (C.c_void_p * cnt)(*[op._h.value for op in ops])
+        R = (C.c_void_p * cnt)(*[_ptr(r) for r in rs])
+        E = (C.c_void_p * cnt)(*[_ptr(e) for e in es])
+        loss = C.c_double()
+        check(lib().sg_net_train_pairs(self._h, cnt, H, R, E, float(lr), PREC[precision], C.byref(loss),
+                                       C.c_void_p(_stream(stream))), "sg_net_train_pairs")
+        return loss.value
+
+    def save(self, path):
+        check(lib().sg_net_save(self._h, str(path).encode()), "sg_net_save")
+
+    def load(self, path):
+        check(lib().sg_net_load(self._h, str(path).encode()), "sg_net_load")
+
+
 def cgs2(V, w, stream=None):
     """One CGS2 step against the orthonormal rows of V (nv × n); returns h (nv+1,) and normalises w."""
     nv, n = V.shape
@@ -300,4 +400,6 @@ def norm(x, stream=None) -> float:
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
             "sg_fgmres", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_cgs2", "sg_norm",
-            "sg_set_profiling", "sg_kernel_times", "sg_strerror", "sg_last_error"]
+            "sg_set_profiling", "sg_kernel_times", "sg_net_create", "sg_net_destroy", "sg_net_num_params",
+            "sg_net_get_params", "sg_net_set_params", "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step",
+            "sg_net_train_pairs", "sg_net_save", "sg_net_load", "sg_attach_net", "sg_strerror", "sg_last_error"]

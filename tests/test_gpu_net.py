@@ -1,0 +1,259 @@
+"""GPU parity of the learned correction network (sg_net_*) and of the learned
+preconditioner inside FGMRES, against the numpy FP64 oracle (oracle/unet.py).
+
+Tolerances.  The GPU keeps the input, the convolution weights and every stored activation
+and activation gradient in BF16 (unit roundoff 2^-8) and accumulates in FP32.  The oracle
+is run twice: with the same BF16 rounding at the same storage points (oracle
+``rnd=bf16_round``) and exactly.  Against the rounded oracle the only differences are
+the accumulation order and precision (FP32 against FP64, about 1e-6 relative per value),
+which now and then move a value across a BF16 rounding boundary (one BF16 step, 2^-7
+relative at most): held to 5e-3 (relative L2) on the output and, since the gradient sums
+below amplify such flips by the same cancellation factor (about 25) as the rounding
+itself, to 2e-2 on each layer's gradient.  Against the exact oracle the storage rounding itself shows: about 4e-3 on the
+forward output, but 5-13 % on the parameter gradients of random targets, whose sums
+over pixels cancel strongly and so amplify the rounding of their terms (the rounded
+oracle reproduces these figures); held to 1e-2 and 0.2.  Adam is FP32 arithmetic on the
+same gradient: 1e-5 relative.  Solves are held to the FP64 true residual and to the
+oracle's direct solution (1e-6), whatever the network does.
+"""
+import numpy as np
+import pytest
+
+from oracle import assemble, precond, unet
+from workloads import config5_instance, small_2d
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2209_14740_amd import learned, sg  # noqa: E402
+
+Q, S = 2, 1
+CIN, COUT = 2 * Q + S + 1, 2 * Q
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def dev32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def random_theta(seed):
+    rng = np.random.default_rng(seed)
+    th = unet.he_init(CIN, COUT, rng)
+    # small non-zero biases everywhere
+    off = 0
+    for _, k, ci, co in unet.layers(CIN, COUT):
+        off += co * k * k * ci
+        th[off:off + co] = rng.standard_normal(co) * 0.05
+        off += co
+    return th
+
+
+@pytest.fixture(scope="module")
+def small_net():
+    net = sg.Net(Q, S, seed=1)
+    yield net
+    net.close()
+
+
+def test_net_shapes_and_params_round_trip(small_net):
+    assert small_net.num_params == unet.num_params(CIN, COUT)
+    th = random_theta(0).astype(np.float32)
+    small_net.set_params(th)
+    np.testing.assert_array_equal(small_net.get_params(), th)
+
+
+@pytest.mark.parametrize("H", [16, 20])
+def test_net_forward_matches_oracle(small_net, H):
+    th = random_theta(1)
+    small_net.set_params(th.astype(np.float32))
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((3, H, H, CIN))
+    y = small_net.forward_nhwc(dev32(x)).cpu().numpy()
+    th64 = th.astype(np.float32).astype(np.float64)
+    for b in range(3):
+        e_r = rel(y[b], unet.forward(th64, x[b], COUT, rnd=unet.bf16_round))
+        e_x = rel(y[b], unet.forward(th64, x[b], COUT))
+        print("forward H=%d sample %d rel err vs rounded %.3e, vs exact %.3e" % (H, b, e_r, e_x), flush=True)
+        assert e_r <= 5e-3 and e_x <= 1e-2
+
+
+def test_net_gradient_matches_oracle(small_net):
+    th = random_theta(3).astype(np.float32).astype(np.float64)
+    small_net.set_params(th.astype(np.float32))
+    rng = np.random.default_rng(4)
+    B, H = 2, 16
+    x = rng.standard_normal((B, H, H, CIN))
+    t = rng.standard_normal((B, H, H, COUT))
+    loss, g = small_net.grad_nhwc(dev32(x), dev32(t))
+    for label, rnd, tol_layer in (("rounded", unet.bf16_round, 2e-2), ("exact", None, 0.2)):
+        res = [unet.loss_and_grad(th, x[b], t[b], rnd=rnd) for b in range(B)]
+        Lref = np.mean([r_[0] for r_ in res])
+        gref = np.mean([r_[1] for r_ in res], axis=0)
+        print("vs %s oracle: loss %.6e / %.6e, gradient rel err %.3e" % (label, loss, Lref, rel(g, gref)), flush=True)
+        off = 0
+        for name, k, ci, co in unet.layers(CIN, COUT):
+            nw = co * k * k * ci
+            ew, eb = rel(g[off:off + nw], gref[off:off + nw]), rel(g[off + nw:off + nw + co], gref[off + nw:off + nw + co])
+            print("  layer %s: weights %.3e bias %.3e" % (name, ew, eb), flush=True)
+            assert max(ew, eb) <= tol_layer, (label, name)
+            off += nw + co
+        assert abs(loss - Lref) <= 1e-3 * Lref
+
+
+def test_adam_step_matches_oracle(small_net):
+    th = random_theta(5).astype(np.float32)
+    small_net.set_params(th)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((1, 16, 16, CIN))
+    t = rng.standard_normal((1, 16, 16, COUT))
+    _, g = small_net.grad_nhwc(dev32(x), dev32(t))
+    small_net.adam_step(1e-3)
+    th1, m, v = unet.adam_step(th.astype(np.float64), 0.0, 0.0, g.astype(np.float64), 1, 1e-3)
+    np.testing.assert_allclose(small_net.get_params(), th1, rtol=1e-5, atol=1e-7)
+    # second step with a new gradient continues from the same moments
+    _, g2 = small_net.grad_nhwc(dev32(x), dev32(t))
+    small_net.adam_step(1e-3)
+    th2, _, _ = unet.adam_step(th1, m, v, g2.astype(np.float64), 2, 1e-3)
+    np.testing.assert_allclose(small_net.get_params(), th2, rtol=1e-5, atol=1e-7)
+
+
+def test_training_decreases_loss(small_net):
+    small_net.set_params(random_theta(7).astype(np.float32))
+    rng = np.random.default_rng(8)
+    x = dev32(rng.standard_normal((4, 16, 16, CIN)))
+    t = dev32(np.tanh(rng.standard_normal((4, 16, 16, COUT))))
+    l0, _ = small_net.grad_nhwc(x, t)
+    for _ in range(60):
+        small_net.grad_nhwc(x, t)
+        small_net.adam_step(3e-3)
+    l1, _ = small_net.grad_nhwc(x, t)
+    print("loss", l0, "->", l1, flush=True)
+    assert l1 < 0.5 * l0
+
+
+def test_save_load(tmp_path, small_net):
+    th = random_theta(9).astype(np.float32)
+    small_net.set_params(th)
+    small_net.save(tmp_path / "n.bin")
+    other = sg.Net(Q, S, seed=99)
+    other.load(tmp_path / "n.bin")
+    np.testing.assert_array_equal(other.get_params(), th)
+    wrong = sg.Net(Q + 1, S)
+    with pytest.raises(sg.SGError):
+        wrong.load(tmp_path / "n.bin")
+
+
+INST = small_2d(n=33, kbar=8.0, sigma=0.8, s=2, degree=2)   # Q = 6
+
+
+@pytest.fixture(scope="module")
+def sg_op():
+    op = sg.SG.from_instance(INST)
+    yield op
+    op.close()
+
+
+def test_learned_precond_matches_oracle(sg_op):
+    net = sg.Net(sg_op.Q, INST.s, seed=3)
+    th = unet.he_init(net.c_in, net.c_out, np.random.default_rng(10)).astype(np.float32)
+    net.set_params(th)
+    sg_op.attach_net(net)
+    S_ = assemble.from_instance(INST)
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(sg_op.size) + 1j * rng.standard_normal(sg_op.size)
+    z = sg_op.precond(torch.from_numpy(v).cuda(), pc="net", precision="f64").cpu().numpy()
+    z0 = precond.mean_value(S_)(v)
+    x = unet.pack_input(v, INST.k_fields, INST.k_mean, sg_op.Q, INST.n)
+    y = unet.forward(th.astype(np.float64), x, net.c_out, rnd=unet.bf16_round)
+    corr = unet.unpack_output(y, np.linalg.norm(z0), sg_op.Q, INST.n)
+    print("correction size %.3e, error %.3e" % (np.linalg.norm(corr) / np.linalg.norm(z0), rel(z - z0, corr)))
+    assert rel(z - z0, corr) <= 5e-3
+    sg_op.attach_net(None)
+
+
+def _solve_check(op, inst, x):
+    S_ = assemble.from_instance(inst)
+    xh = x.cpu().numpy()
+    xref = precond.direct_solve(S_)
+    r = np.linalg.norm(S_.b - S_.A @ xh) / np.linalg.norm(S_.b)
+    return r, rel(xh, xref)
+
+
+def test_fgmres_with_network_converges(sg_op):
+    net = sg.Net(sg_op.Q, INST.s, seed=4)
+    sg_op.attach_net(net)
+    b = sg_op.rhs(INST.f)
+    x, info = sg_op.fgmres(b, restart=30, maxit=300, pc="net", precision="f64", tol=1e-8)
+    r, e = _solve_check(sg_op, INST, x)
+    print("net fgmres", info["status"], info["iters"], info["fallback"], r, e, flush=True)
+    assert info["status"] in (sg.SG_OK, sg.SG_FALLBACK_USED)
+    assert r <= 1.05e-8 and e <= 1e-6
+    sg_op.attach_net(None)
+
+
+def test_fallback_on_bad_network(sg_op):
+    net = sg.Net(sg_op.Q, INST.s, seed=5)
+    th = net.get_params()
+    th *= 50.0                       # a network that makes the preconditioner useless
+    net.set_params(th)
+    sg_op.attach_net(net)
+    b = sg_op.rhs(INST.f)
+    x, info = sg_op.fgmres(b, restart=10, maxit=400, pc="net", precision="f64", tol=1e-8)
+    r, e = _solve_check(sg_op, INST, x)
+    print("bad net", info["status"], info["iters"], info["fallback"], r, e, flush=True)
+    assert info["status"] == sg.SG_FALLBACK_USED and info["fallback"] == 1
+    assert r <= 1.05e-8 and e <= 1e-6
+    sg_op.attach_net(None)
+    with pytest.raises(sg.SGError):
+        sg_op.fgmres(b, pc="net")        # no network attached
+    with pytest.raises(sg.SGError):
+        sg_op.gmres(b, pc="net")         # needs the flexible method
+
+
+def test_trained_network_gain():
+    """Ablation: a network trained on pairs from plain solves of one family of problems
+    against the same FGMRES without it, on held-out problems of the family."""
+    n = 33
+    train_inst = [config5_instance(10000 + i, n=n) for i in range(8)]
+    test_inst = [config5_instance(i, n=n) for i in range(2)]
+    ops = [sg.SG.from_instance(i) for i in train_inst + test_inst]
+    try:
+        samples = []
+        for op, inst in zip(ops[:8], train_inst):
+            for r, e in learned.solver_pairs(op, op.rhs(inst.f), cycle=2, max_pairs=8):
+                samples.append((op, r, e))
+        held = []
+        for op, inst in zip(ops[8:], test_inst):
+            held += [(op, r, e) for r, e in learned.solver_pairs(op, op.rhs(inst.f), cycle=2, max_pairs=4)]
+        net = sg.Net(35, 4, seed=0)
+
+        def held_loss():
+            th = net.get_params()
+            ls = [net.train_pairs([o], [r], [e], 1e-30) for o, r, e in held]
+            net.set_params(th)
+            return float(np.mean(ls))
+
+        l_before = held_loss()
+        learned.train(net, samples, steps=150, batch=8, lr=1e-3)
+        l_after = held_loss()
+        print("pairs %d, held-out loss %.4e -> %.4e" % (len(samples), l_before, l_after), flush=True)
+        assert l_after < l_before
+        for op, inst in zip(ops[8:], test_inst):
+            b = op.rhs(inst.f)
+            _, i0 = op.fgmres(b, restart=50, maxit=500, pc="mean", precision="f64", tol=1e-8)
+            op.attach_net(net)
+            x, i1 = op.fgmres(b, restart=50, maxit=500, pc="net", precision="f64", tol=1e-8)
+            op.attach_net(None)
+            r, e = _solve_check(op, inst, x)
+            print("%s: A_0 FGMRES %d iterations, learned %d iterations (status %d, fallback %d), relres %.2e"
+                  % (inst.name, i0["iters"], i1["iters"], i1["status"], i1["fallback"], r), flush=True)
+            assert r <= 1.05e-8 and e <= 1e-6
+    finally:
+        for op in ops:
+            op.close()

@@ -116,3 +116,35 @@ def test_pack_unpack_round_trip():
     np.testing.assert_allclose(x[4, 7, 2 * 1 + 1], r[1 * n * n + 4 * n + 7].imag * s, rtol=1e-13)
     c = rng.standard_normal(Q * n * n) + 1j * rng.standard_normal(Q * n * n)
     np.testing.assert_allclose(unet.unpack_output(unet.pack_target(c, 2.5, Q, n), 2.5, Q, n), c, rtol=1e-13)
+
+
+def test_bf16_round_exact_values():
+    # representable values are fixed points; halfway cases go to the even significand;
+    # the relative rounding error is at most the unit roundoff 2^-8 of an 8-bit significand
+    vals = np.array([1.0, -2.0, 0.0, 1.0 + 2 ** -7, 3.0 * 2 ** -130, 65280.0])
+    np.testing.assert_array_equal(unet.bf16_round(vals), vals)
+    assert unet.bf16_round(1.0 + 2 ** -8) == 1.0                    # tie, even neighbour 1.0
+    assert unet.bf16_round(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6      # tie, even neighbour 1+2^-6
+    assert unet.bf16_round(1.0 + 2 ** -8 + 2 ** -20) == 1.0 + 2 ** -7
+    assert unet.bf16_round(-(1.0 + 2 ** -8 + 2 ** -20)) == -(1.0 + 2 ** -7)
+    x = np.random.default_rng(7).standard_normal(10000) * 10.0 ** np.random.default_rng(8).integers(-20, 20, 10000)
+    r = unet.bf16_round(x)
+    assert np.all(np.abs(r - x) <= 2.0 ** -8 * np.abs(x) * (1 + 1e-4))
+    assert np.max(np.abs(r - x) / np.abs(x)) > 2.0 ** -9          # and the bound is attained
+    # the bfloat16 grid: 8 significant bits
+    m, _ = np.frexp(r)
+    assert np.all((m * 2 ** 8) == np.round(m * 2 ** 8))
+
+
+def test_rounded_network_is_the_exact_one_on_bf16_data():
+    # with data already on the bfloat16 grid and rounding that changes nothing, the rounded
+    # forward pass equals the exact one; with real rounding it stays close
+    rng, theta, x, t = _small_problem(seed=11)
+    y0 = unet.forward(theta, x, 4)
+    y1 = unet.forward(theta, x, 4, rnd=lambda a: a)
+    np.testing.assert_array_equal(y0, y1)
+    y2 = unet.forward(theta, x, 4, rnd=unet.bf16_round)
+    assert np.linalg.norm(y2 - y0) <= 2e-2 * np.linalg.norm(y0)
+    L, g, _ = unet.loss_and_grad(theta, x, t, rnd=unet.bf16_round)
+    L0, g0, _ = unet.loss_and_grad(theta, x, t)
+    assert abs(L - L0) <= 1e-2 * L0
