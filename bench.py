@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "time to rel.res 1e-8 + SG matvec HBM GB/s; plain FP64 vs mixed/learned"
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
-KIND = {0: "sg_apply", 1: "fd_gemm", 2: "tri_sweep", 3: "cgs2_multidot", 4: "cgs2_axpy", 5: "norm_reduce"}
+KIND = {0: "sg_apply", 1: "fd_gemm", 2: "tri_sweep", 3: "cgs2_multidot", 4: "cgs2_axpy", 5: "norm_reduce", 6: "net"}
 
 # HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a copy kernel of known size.  Valid only for the kernel
@@ -176,6 +176,94 @@ def batched_config4(count, log):
     return out
 
 
+def learned_config5(n_pairs, n_eval, log):
+    """Learned form: the correction network is trained on the GPU on `n_pairs` (residual,
+    error) pairs from plain solves of seeds 10000+ (streamed: 8 problems at a time, each
+    pair used once), then FGMRES(50) with z = A_0^{-1} v + N(v) (A_0 in BF16x3) is compared
+    on seeds 0..n_eval-1 with plain FP64 GMRES(50) and with the same FGMRES without the
+    network, all to the FP64 true relative residual 1e-8."""
+    import concurrent.futures as cf
+
+    import torch
+    from paper_2209_14740_amd import learned, sg
+    from workloads import config5_instance
+    net = sg.Net(35, 4, seed=0)
+    rng = np.random.default_rng(0)
+    seen, seed, losses = 0, 10000, []
+    t_gen = t_train = 0.0
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        while seen < n_pairs:
+            t0 = time.perf_counter()
+            insts = [config5_instance(seed + i) for i in range(8)]
+            seed += 8
+            ops = list(ex.map(sg.SG.from_instance, insts))
+            samples = []
+            for op, inst in zip(ops, insts):
+                samples += [(op, r, e) for r, e in learned.solver_pairs(op, op.rhs(inst.f), cycle=2, max_pairs=16)]
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            order = rng.permutation(len(samples))
+            for k in range(0, len(order), 8):
+                idx = order[k:k + 8]
+                losses.append(net.train_pairs([samples[i][0] for i in idx], [samples[i][1] for i in idx],
+                                              [samples[i][2] for i in idx], 1e-3, "f64"))
+            seen += len(samples)
+            t_train += time.perf_counter() - t1
+            t_gen += t1 - t0
+            del samples
+            for op in ops:
+                op.close()
+            if len(losses) % 64 < 8:
+                log("learned: %d pairs, loss %.4e" % (seen, np.mean(losses[-8:])))
+    torch.cuda.empty_cache()
+    res = {"plain_f64_gmres": [], "a0_bf16x3_fgmres": [], "learned_fgmres": []}
+    fallbacks = 0
+    net_ms = None
+    for sd in range(n_eval):
+        inst = config5_instance(sd)
+        op = sg.SG.from_instance(inst)
+        b = op.rhs(inst.f)
+        x = op.empty()
+        for name, fn, kw in (("plain_f64_gmres", op.gmres, dict(pc="mean", precision="f64")),
+                             ("a0_bf16x3_fgmres", op.fgmres, dict(pc="mean", precision="bf16x3")),
+                             ("learned_fgmres", op.fgmres, dict(pc="net", precision="bf16x3"))):
+            if name == "learned_fgmres":
+                op.attach_net(net)
+            fn(b, x, restart=50, maxit=1000, tol=1e-8, **kw)       # warm-up
+            if name == "learned_fgmres" and sd == 0:
+                set_profiling(op, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = fn(b, x, restart=50, maxit=1000, tol=1e-8, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if name == "learned_fgmres" and sd == 0:
+                prof = kernel_profile(op)
+                set_profiling(op, False)
+                if "net" in prof:
+                    net_ms = prof["net"]["ms"]
+                    res["net_conv_TFLOPs"] = prof["net"]["work"] / (prof["net"]["ms"] * 1e-3) / 1e12
+            if name == "learned_fgmres":
+                fallbacks += info["fallback"]
+                op.attach_net(None)
+            res[name].append((t, info["iters"], info["relres_true"]))
+        op.close()
+    out = {"workload": "255x255, kbar~U[10,30], sigma=0.15 kbar, s=4, degree 3 (Q=35); U-Net widths 32/64/128, "
+                       "BF16 with FP32 accumulation; trained on %d pairs from plain solves (seeds 10000+), "
+                       "evaluated on seeds 0..%d" % (seen, n_eval - 1),
+           "pairs": seen, "train_steps": len(losses), "pair_generation_s": t_gen, "training_s": t_train,
+           "loss_first": float(np.mean(losses[:8])), "loss_last": float(np.mean(losses[-8:])),
+           "fallbacks": fallbacks, "net_conv_ms_in_one_solve": net_ms,
+           "net_conv_TFLOPs": res.pop("net_conv_TFLOPs", None)}
+    for name in ("plain_f64_gmres", "a0_bf16x3_fgmres", "learned_fgmres"):
+        arr = np.array(res[name])
+        out[name] = {"s_mean": float(arr[:, 0].mean()), "iters_mean": float(arr[:, 1].mean()),
+                     "relres_true_max": float(arr[:, 2].max())}
+    out["learned_speedup_vs_plain"] = out["plain_f64_gmres"]["s_mean"] / out["learned_fgmres"]["s_mean"]
+    net.close()
+    return out
+
+
 def cpu_baseline():
     """The oracle (numpy/scipy FP64) on the same workload: assembly, block LU of the mean
     block and MGS GMRES(50) to 1e-8, timed on the host; BLAS restricted to one thread
@@ -213,6 +301,11 @@ def main():
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched leg (for profiling); prints its JSON object")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-pairs", type=int, default=8192)
+    ap.add_argument("--learned-eval", type=int, default=64)
+    ap.add_argument("--learned-only", action="store_true",
+                    help="run only the learned leg; prints its JSON object")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs on one GPU; a run on %d GPUs is not part of this build "
@@ -226,6 +319,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batched_only:
         print(json.dumps({"batched": batched_config4(args.batched_count, log)}))
+        return
+    if args.learned_only:
+        print(json.dumps({"learned": learned_config5(args.learned_pairs, args.learned_eval, log)}))
         return
     inst = config2()
     t0 = time.perf_counter()
@@ -296,6 +392,9 @@ def main():
     if not args.no_batched:
         log("batched config 4")
         out["batched"] = batched_config4(args.batched_count, log)
+    if not args.no_learned:
+        log("learned config 5")
+        out["learned"] = learned_config5(args.learned_pairs, args.learned_eval, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

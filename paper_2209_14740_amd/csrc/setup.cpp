@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -255,6 +256,16 @@ static int mean_eigen(int n, double h, double kbar, std::vector<cplx>& mu, std::
         }
         cplx uu = 0;
         for (auto& z : u) uu += z * z;
+        // refine the eigenvalue by the (unconjugated) Rayleigh quotient uᵀJu / uᵀu, which is
+        // second-order accurate for the complex symmetric J
+        cplx uju = 0;
+        for (int i = 0; i < n; ++i) {
+            cplx ju = jd[i] * u[i];
+            if (i > 0) ju += je[i - 1] * u[i - 1];
+            if (i < n - 1) ju += je[i] * u[i + 1];
+            uju += u[i] * ju;
+        }
+        mu[a] = uju / uu;
         cplx sc = 1.0 / std::sqrt(uu);
         for (int i = 0; i < n; ++i) V[(size_t)i * n + a] = u[i] * sc / std::sqrt(dw[i]);
     }
@@ -281,8 +292,12 @@ static int mean_eigen(int n, double h, double kbar, std::vector<cplx>& mu, std::
             orth = std::max(orth, std::abs(acc - (a == b ? 1.0 : 0.0)));
         }
     if (!(res < 1e-10) || !(orth < 1e-8))
-        return fail(SG_ESETUP, "eigenfactor validation failed: residual " + std::to_string(res) +
-                                   ", D-orthonormality defect " + std::to_string(orth));
+    {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "eigenfactor validation failed: residual %.3e, D-orthonormality defect %.3e", res,
+                      orth);
+        return fail(SG_ESETUP, msg);
+    }
     return SG_OK;
 }
 
