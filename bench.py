@@ -152,6 +152,17 @@ def batched_config4(count, log):
     _, rc, infos = sg.gmres_batched(ops, bs, xs, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t0
+    # per-kernel-class split of the same batched solve (events recorded on the launch stream;
+    # timed separately so that the event overhead stays out of solves/s)
+    set_profiling(ops[0], True)
+    sg.gmres_batched(ops, bs, xs, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
+    prof = kernel_profile(ops[0])
+    set_profiling(ops[0], False)
+    kern = {}
+    for k, v in prof.items():
+        rate = v["work"] / (v["ms"] * 1e-3)
+        kern[k] = {"ms": v["ms"], "launches": v["launches"],
+                   ("TFLOP/s" if k == "fd_gemm" else "GB/s"): rate / (1e12 if k == "fd_gemm" else 1e9)}
     log("batched: %.3f s for %d solves (%.1f solves/s), rc %d" % (t_solve, count, count / t_solve, rc))
     # the same instances one at a time through sg_gmres (same algorithm and precision)
     torch.cuda.synchronize()
@@ -168,7 +179,8 @@ def batched_config4(count, log):
            "solves_per_s": count / t_solve, "solves_per_s_with_setup": count / (t_solve + t_setup),
            "solve_s": t_solve, "one_at_a_time_solves_per_s": count / t_seq, "setup_s": t_setup, "setup_threads": 8, "autotune_s": t_tune,
            "autotune_gpu_ms": tune_ms, "tiles": tiles, "all_converged": bool(rc == 0),
-           "iters_mean": float(its.mean()), "iters_max": int(its.max()), "relres_true_max": float(rel.max())}
+           "iters_mean": float(its.mean()), "iters_max": int(its.max()), "relres_true_max": float(rel.max()),
+           "kernels": kern}
     for op in ops:
         op.close()
     del bs, xs
@@ -302,6 +314,11 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched leg (for profiling); prints its JSON object")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="run only the SG-operator bandwidth leg; prints its JSON object")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one elementwise copy kernel of 1 GiB in and 1 GiB out first (HBM counter "
+                         "calibration under rocprofv3 --pmc)")
     ap.add_argument("--learned-pairs", type=int, default=8192)
     ap.add_argument("--learned-eval", type=int, default=64)
     ap.add_argument("--learned-only", action="store_true",
@@ -317,6 +334,16 @@ def main():
     from workloads import config2, config3
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
+        del src, dst
+    if args.matvec_only:
+        print(json.dumps({"matvec": matvec_bandwidth(config3(), 20)}))
+        return
     if args.batched_only:
         print(json.dumps({"batched": batched_config4(args.batched_count, log)}))
         return

@@ -6,4 +6,8 @@ int dispatch_spec_g0(int s, int r, const ApplyArgs& a, hipStream_t st) {
     SG_SPEC(6, 3)
     return 0;
 }
+int dispatch_spec_grouped_g0(int s, int r, const ApplyArgs* d, const int* ds, int nt, int tot, hipStream_t st) {
+    SG_SPEC_G(6, 3)
+    return 0;
+}
 }  // namespace sgi

@@ -14,4 +14,16 @@ int dispatch_spec_g3(int s, int r, const ApplyArgs& a, hipStream_t st) {
     SG_SPEC(3, 2)
     return 0;
 }
+int dispatch_spec_grouped_g3(int s, int r, const ApplyArgs* d, const int* ds, int nt, int tot, hipStream_t st) {
+    SG_SPEC_G(1, 1)
+    SG_SPEC_G(1, 2)
+    SG_SPEC_G(1, 3)
+    SG_SPEC_G(1, 4)
+    SG_SPEC_G(1, 5)
+    SG_SPEC_G(2, 1)
+    SG_SPEC_G(2, 2)
+    SG_SPEC_G(2, 3)
+    SG_SPEC_G(3, 2)
+    return 0;
+}
 }  // namespace sgi

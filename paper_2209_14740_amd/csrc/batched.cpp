@@ -261,7 +261,8 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
     bool any_notconv = false;
 
     Group<VecTask> g_copy, g_lin, g_xupd, g_res, g_mdot, g_red1, g_upd1, g_red2, g_updn, g_redn, g_pcopy;
-    Group<ApplyArgs> g_apply;
+    Group<ApplyArgs> g_apply;                                  // generic operator
+    std::map<std::pair<int, int>, Group<ApplyArgs>> g_spec;   // shape-specialised operator per (s, r)
     Group<TriTask> g_tri;
     std::vector<Group<GemmTask>> g_fwd(SG_GEMM_NCFG), g_inv(SG_GEMM_NCFG);
     std::vector<double> hscale_tab((size_t)S * (m + 2), 1.0);
@@ -324,6 +325,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                          &g_pcopy})
             gp->clear();
         g_apply.clear();
+        for (auto& kv : g_spec) kv.second.clear();
         g_tri.clear();
         for (auto& gg : g_fwd) gg.clear();
         for (auto& gg : g_inv) gg.clear();
@@ -344,7 +346,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         // the staging buffer may be reallocated by ensure(): size it generously first
         {
             const size_t per = sizeof(VecTask) * 12 + sizeof(ApplyArgs) + sizeof(TriTask) + 2 * sizeof(GemmTask) + 32 * 4;
-            rc = stg.ensure(align_up(stg.used) + (size_t)active.size() * per + 64 * ALIGN * 2);
+            rc = stg.ensure(align_up(stg.used) + (size_t)active.size() * per + 128 * ALIGN * 2);
             if (rc) return rc;
         }
         unsigned char* const dev_before = stg.dev;
@@ -409,12 +411,21 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
             }
         }
         size_t lds = 0;
+        auto add_apply = [&](Ctx* c, const double2* xin, double2* yout) {
+            const ApplyArgs aa = make_apply_args(c, xin, yout);
+            const double abytes = (double)c->P * (32.0 * c->Q + 8.0 * c->K.nfield);
+            if (c->dim == 2 && c->use_spec_apply && dispatch_spec_grouped(c->s, c->degree, nullptr, nullptr, 0, 0, nullptr)) {
+                g_spec[{c->s, c->degree}].add(aa, spec_row_blocks(c->n), abytes);
+            } else {
+                g_apply.add(aa, aa.ntiles_x * aa.nrows, abytes);
+                lds = std::max(lds, apply_lds_bytes(c->Q, c->K.nfield));
+            }
+        };
         for (int sI : active) {
             Slot& s = slots[sI];
             Ctx* c = s.c;
             const long long n = c->nvec;
             double2* coef = d_coef + (size_t)sI * CW;
-            const double abytes = (double)c->P * (32.0 * c->Q + 8.0 * c->K.nfield);
             if (s.phase == END) {
                 VecTask t = vt_base(s);
                 t.x = s.x;
@@ -423,8 +434,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                 t.b = make_double2(1, 0);
                 t.w = s.x;
                 g_xupd.add(t, s.nblk, 48.0 * n);
-                const ApplyArgs aa = make_apply_args(c, s.x, s.ut);
-                g_apply.add(aa, aa.ntiles_x * aa.nrows, abytes);
+                add_apply(c, s.x, s.ut);
                 VecTask r = vt_base(s);
                 r.x = s.b;
                 r.y = s.ut;
@@ -432,11 +442,8 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                 r.b = make_double2(-1, 0);
                 r.w = s.V;
                 g_res.add(r, s.nblk, 48.0 * n);
-                lds = std::max(lds, apply_lds_bytes(c->Q, c->K.nfield));
             } else if (s.phase == ARN) {
-                const ApplyArgs aa = make_apply_args(c, s.zt, s.V + (size_t)(s.j + 1) * n);
-                g_apply.add(aa, aa.ntiles_x * aa.nrows, abytes);
-                lds = std::max(lds, apply_lds_bytes(c->Q, c->K.nfield));
+                add_apply(c, s.zt, s.V + (size_t)(s.j + 1) * n);
                 const int nv = s.j + 1;
                 VecTask t = vt_base(s);
                 t.V = s.V;
@@ -482,6 +489,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                          &g_redn})
             stg.put_group(*gp);
         stg.put_group(g_apply);
+        for (auto& kv : g_spec) stg.put_group(kv.second);
         stg.put_group(g_tri);
         for (auto& gg : g_fwd) stg.put_group(gg);
         for (auto& gg : g_inv) stg.put_group(gg);
@@ -516,6 +524,14 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         if ((rc = launch_apply_grouped(stg.dtasks(g_apply), stg.dstart(g_apply), g_apply.n(), g_apply.total(), lds,
                                        g_apply.work, stream)))
             return rc;
+        for (auto& kv : g_spec) {
+            Group<ApplyArgs>& gg = kv.second;
+            if (gg.n() == 0) continue;
+            KScope ks(SG_K_APPLY, gg.work, stream);
+            dispatch_spec_grouped(kv.first.first, kv.first.second, stg.dtasks(gg), stg.dstart(gg), gg.n(), gg.total(),
+                                  stream);
+            SG_HIP(hipGetLastError());
+        }
         if ((rc = launch_axpby_grouped(stg.dtasks(g_res), stg.dstart(g_res), g_res.n(), g_res.total(), g_res.work,
                                        stream)))
             return rc;
