@@ -276,6 +276,33 @@ def learned_config5(n_pairs, n_eval, log):
     return out
 
 
+def paper_context():
+    """The paper's own timed 1D experiment (Section 6: k̄ = 50, θ = 0.1, degree 3, point
+    source, A_0 as right preconditioner, full GMRES to 1e-12), for context only."""
+    import torch
+    from paper_2209_14740_amd import sg
+    from workloads import one_d_paper
+    inst = one_d_paper(50.0, 0.1, 3)
+    t0 = time.perf_counter()
+    op = sg.SG.from_instance(inst)
+    t_setup = time.perf_counter() - t0
+    b = op.rhs(inst.f)
+    x = op.empty()
+    kw = dict(restart=512, maxit=2000, pc="mean", precision="f64", tol=1e-12)
+    op.gmres(b, x, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        _, info = op.gmres(b, x, **kw)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / 5
+    op.close()
+    return {"workload": "1D model problem of Section 6: kbar=50, theta=0.1, degree 3 (Q=4), %d nodes, point "
+                        "source; A_0 right preconditioner, GMRES without restart to 1e-12" % inst.n,
+            "gpu_solve_s": t, "gpu_setup_s": t_setup, "iters": info["iters"], "relres_true": info["relres_true"],
+            "paper_s": 0.0148, "paper_machine": "MATLAB R2020b on an i7-7500U @ 2.70GHz, LU of one block included"}
+
+
 def cpu_baseline():
     """The oracle (numpy/scipy FP64) on the same workload: assembly, block LU of the mean
     block and MGS GMRES(50) to 1e-8, timed on the host; BLAS restricted to one thread
@@ -416,6 +443,8 @@ def main():
     if not args.no_matvec:
         log("matvec bandwidth on config 3")
         out["matvec"] = matvec_bandwidth(config3(), 20)
+    log("paper context (Section 6, 1D)")
+    out["paper_context"] = paper_context()
     if not args.no_batched:
         log("batched config 4")
         out["batched"] = batched_config4(args.batched_count, log)
