@@ -384,19 +384,35 @@ def main():
     b = op.rhs(inst.f)
     x = op.empty()
     common = dict(restart=50, maxit=1000, tol=1e-8)
+    # GEMM tile shapes of this problem from the autotuner (part of setup)
+    t0 = time.perf_counter()
+    for prec in ("f64", "f32", "bf16x3"):
+        sg.autotune([op], prec, reps=5)
+    tune_s = time.perf_counter() - t0
+    tiles = {p_: sg.tune_get(op.n, op.Q, p_) for p_ in ("f64", "f32", "bf16x3")}
 
     log("setup %.2f s; warmup" % setup_s)
-    # plain FP64 (the headline): warmup, then the timed steps with kernel event timing
+    # plain FP64 (the headline).  An untimed pass with events around every kernel class gives
+    # the per-class split and names the dominant class; the timed steps then record HIP events
+    # on the launch stream around that class only (a few per iteration), so the roofline comes
+    # from the timed region itself.
     for _ in range(args.warmup):
         op.gmres(b, x, pc="mean", precision="f64", **common)
     set_profiling(op, True)
+    for _ in range(args.steps):
+        op.gmres(b, x, pc="mean", precision="f64", **common)
+    prof = kernel_profile(op)
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    dom_kind = [k for k, v in KIND.items() if v == dom][0]
+    set_profiling(op, True)
+    sg.check(sg.lib().sg_profile_kinds(op._h, 1 << dom_kind), "sg_profile_kinds")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         _, info = op.gmres(b, x, pc="mean", precision="f64", **common)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / args.steps
-    prof = kernel_profile(op)
+    prof_dom = kernel_profile(op)
     set_profiling(op, False)
     x_plain = x.clone()
     if not info["converged"]:
@@ -415,7 +431,7 @@ def main():
         forms[name] = {"s": t, "iters": inf["iters"], "relres_true": inf["relres_true"],
                        "max_rel_diff_vs_plain": err, "speedup_vs_plain": t_plain / t}
 
-    roof = roofline_of(prof)
+    roof = roofline_of(prof_dom)
     out = {
         "metric": METRIC,
         "value": t_plain,
@@ -432,7 +448,8 @@ def main():
         "config": {"workload": "2D 255x255 nodes, k=20+2*sum_l sin-modes*xi_l (s=4), total degree 3 (Q=35), "
                                "2,275,875 complex unknowns; mean-value preconditioned GMRES(50) to true "
                                "relres 1e-8 from x=0",
-                   "setup_s": setup_s, "iters": info["iters"], "relres_true": info["relres_true"]},
+                   "setup_s": setup_s, "autotune_s": tune_s, "gemm_tiles": tiles, "iters": info["iters"],
+                   "relres_true": info["relres_true"]},
         "roofline": roof,
         "kernels": prof,
         "forms": forms,

@@ -162,7 +162,8 @@ int  sg_gmres_batched(int count, const sg_handle* handles, const sg_c64* const* 
  * fastest in a process-wide table keyed by (n, Q, precision).  Uses the handles'
  * preconditioner scratch (their contents are overwritten) and a temporary device
  * buffer.  *ms_total (may be NULL) receives the measured GPU time. */
-enum { SG_GEMM_TILE_128x128 = 0, SG_GEMM_TILE_64x128 = 1, SG_GEMM_TILE_64x64 = 2 };
+enum { SG_GEMM_TILE_128x128 = 0, SG_GEMM_TILE_64x128 = 1, SG_GEMM_TILE_64x64 = 2, SG_GEMM_TILE_64x32 = 3,
+       SG_GEMM_TILE_32x64 = 4 };
 int  sg_autotune(int count, const sg_handle* handles, int precision, int reps, double* ms_total,
                  hipStream_t stream);
 /* Read (-1 if absent) or set one entry of the autotuner table. */
@@ -189,8 +190,11 @@ enum {
     SG_K_NET = 6,       /* correction network convolutions (algorithmic flops)        */
     SG_K_NKINDS = 8
 };
-/* on != 0 enables recording and clears the counters. */
+/* on != 0 enables recording (of every kind) and clears the counters. */
 int  sg_set_profiling(sg_handle h, int on);
+/* Restrict recording to the kinds whose bit (1u << kind) is set in mask (after
+ * sg_set_profiling, which resets the mask to all kinds). */
+int  sg_profile_kinds(sg_handle h, unsigned mask);
 /* Synchronises the pending events and returns, per class k < nkinds (host arrays of
  * nkinds entries, any may be NULL): total milliseconds, launch count, and the summed
  * algorithmic work (bytes or flops as listed above). */

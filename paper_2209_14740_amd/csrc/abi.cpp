@@ -401,6 +401,15 @@ int sg_set_profiling(sg_handle h, int on) {
         Ctx* c = ctx(h);
         c->prof.reset();
         c->prof.on = on != 0;
+        c->prof.mask = ~0u;
+        return SG_OK;
+    })
+}
+
+int sg_profile_kinds(sg_handle h, unsigned mask) {
+    SG_TRY({
+        if (!h) return fail(SG_EINVAL, "null handle");
+        ctx(h)->prof.mask = mask;
         return SG_OK;
     })
 }

@@ -511,7 +511,9 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
             if ((rc = launch_gemm_grouped(prec, cfg, stg.dtasks(g_fwd[cfg]), stg.dstart(g_fwd[cfg]), g_fwd[cfg].n(),
                                           g_fwd[cfg].total(), g_fwd[cfg].work, stream)))
                 return rc;
-        if ((rc = launch_tri_grouped(stg.dtasks(g_tri), stg.dstart(g_tri), g_tri.n(), g_tri.total(), g_tri.work,
+        int max_seg = 0;
+        for (const TriTask& tt : g_tri.tasks) max_seg = std::max(max_seg, tt.f.L);
+        if ((rc = launch_tri_grouped(stg.dtasks(g_tri), stg.dstart(g_tri), g_tri.n(), g_tri.total(), max_seg, g_tri.work,
                                      stream)))
             return rc;
         for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg)

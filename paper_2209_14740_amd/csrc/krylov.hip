@@ -146,71 +146,6 @@ __global__ __launch_bounds__(RB) void k_axpy(long long n, int nv, const double2*
     }
 }
 
-// Fused CGS2 passes.  For every element i (grid-stride), with c_k = -scale[k]·coef[k]:
-//   w_new[i] = w[i] + Σ_k c_k V_k[i]            (update of the previous pass)
-//   DOT:  partial[b][k] += conj(V_k[i]) · w_new[i]   (projection of the next pass)
-//   NORM: partial[b][0] += |w_new[i]|²
-// The V_k[i] values of the update stay in registers for the projection, so V is read once.
-template <int NV, bool DOT>
-__global__ __launch_bounds__(RB) void k_upd(long long n, int nv, const double2* __restrict__ V, long long ldv,
-                                            const double* __restrict__ scale, const double2* __restrict__ coef,
-                                            double2* __restrict__ w, double2* __restrict__ partial) {
-    __shared__ double2 c[NV];
-    __shared__ double2 red[(RB / 64) * NV];
-    for (int k = threadIdx.x; k < nv; k += RB) {
-        const double sk = -(scale ? scale[k] : 1.0);
-        c[k] = make_double2(coef[k].x * sk, coef[k].y * sk);
-    }
-    __syncthreads();
-    constexpr int NA = DOT ? NV : 1;
-    double2 acc[NA];
-#pragma unroll
-    for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
-    for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
-        double2 v[NV];
-        double2 wi = w[i];
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-            if (k < nv) {
-                v[k] = V[(long long)k * ldv + i];
-                const double2 ck = c[k];
-                wi.x = fma(v[k].x, ck.x, fma(-v[k].y, ck.y, wi.x));
-                wi.y = fma(v[k].x, ck.y, fma(v[k].y, ck.x, wi.y));
-            }
-        w[i] = wi;
-        if constexpr (DOT) {
-#pragma unroll
-            for (int k = 0; k < NV; ++k)
-                if (k < nv) {
-                    acc[k].x = fma(v[k].x, wi.x, fma(v[k].y, wi.y, acc[k].x));
-                    acc[k].y = fma(v[k].x, wi.y, fma(-v[k].y, wi.x, acc[k].y));
-                }
-        } else {
-            acc[0].x = fma(wi.x, wi.x, fma(wi.y, wi.y, acc[0].x));
-        }
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NA; ++k) {
-        acc[k].x = wave_sum(acc[k].x);
-        acc[k].y = wave_sum(acc[k].y);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < NA; ++k) red[wv * NV + k] = acc[k];
-    }
-    __syncthreads();
-    const int nout = DOT ? nv : 1;
-    for (int k = threadIdx.x; k < nout; k += RB) {
-        double2 t = red[k];
-        for (int ww = 1; ww < RB / 64; ++ww) {
-            t.x += red[ww * NV + k].x;
-            t.y += red[ww * NV + k].y;
-        }
-        partial[(long long)blockIdx.x * nout + k] = t;
-    }
-}
-
 __global__ __launch_bounds__(RB) void k_axpby(long long n, double2 a, const double2* __restrict__ x, double2 b,
                                               const double2* __restrict__ y, double2* __restrict__ out) {
     for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
@@ -222,6 +157,94 @@ __global__ __launch_bounds__(RB) void k_axpby(long long n, double2 a, const doub
             r.y += b.x * yv.y + b.y * yv.x;
         }
         out[i] = r;
+    }
+}
+
+// CGS2 passes with the basis split across the waves of a block: wave wv owns the vectors
+// k = wv, wv+4, wv+8, ... (at most NVW of them) over a chunk of 64 consecutive elements, so
+// each lane keeps only its NVW basis values and accumulators in registers.
+//   MODE 0  projection:  partial[b][k] = Σ conj(V_k[i]) w[i]
+//   MODE 1  update + next projection:  w ← w − Σ_k c_k V_k (c_k = scale_k coef_k), then
+//           partial[b][k] = Σ conj(V_k[i]) w_new[i] with the V_k values still in registers
+//   MODE 2  update + squared norm:  partial[b][0] = Σ |w_new[i]|²
+// The four per-wave partial sums of the update meet in a double-buffered LDS array, so one
+// barrier per chunk suffices; every wave forms the same w_new, wave 0 stores it.
+template <int NVW, int MODE>
+__global__ __launch_bounds__(RB) void k_cgs(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                            const double* __restrict__ scale, const double2* __restrict__ coef,
+                                            double2* __restrict__ w, double2* __restrict__ partial) {
+    __shared__ double2 part[2][RB / 64][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double2 c[NVW];
+    int nk = 0;
+#pragma unroll
+    for (int m = 0; m < NVW; ++m) {
+        const int k = wv + 4 * m;
+        if (k < nv) {
+            nk = m + 1;
+            if (MODE != 0) {
+                const double sk = -(scale ? scale[k] : 1.0);
+                c[m] = make_double2(coef[k].x * sk, coef[k].y * sk);
+            }
+        }
+    }
+    double2 acc[NVW];
+#pragma unroll
+    for (int m = 0; m < NVW; ++m) acc[m] = make_double2(0.0, 0.0);
+    double nrm = 0.0;
+    int buf = 0;
+    for (long long c0 = (long long)blockIdx.x * 64; c0 < n; c0 += (long long)gridDim.x * 64, buf ^= 1) {
+        const long long i = c0 + lane;
+        const bool ok = i < n;
+        double2 v[NVW];
+#pragma unroll
+        for (int m = 0; m < NVW; ++m)
+            v[m] = (m < nk && ok) ? V[(long long)(wv + 4 * m) * ldv + i] : make_double2(0.0, 0.0);
+        if constexpr (MODE == 0) {
+            const double2 wi = ok ? w[i] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int m = 0; m < NVW; ++m) {
+                acc[m].x = fma(v[m].x, wi.x, fma(v[m].y, wi.y, acc[m].x));
+                acc[m].y = fma(v[m].x, wi.y, fma(-v[m].y, wi.x, acc[m].y));
+            }
+        } else {
+            double2 p = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int m = 0; m < NVW; ++m)
+                if (m < nk) {
+                    p.x = fma(v[m].x, c[m].x, fma(-v[m].y, c[m].y, p.x));
+                    p.y = fma(v[m].x, c[m].y, fma(v[m].y, c[m].x, p.y));
+                }
+            part[buf][wv][lane] = p;
+            __syncthreads();
+            double2 wn = ok ? w[i] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < RB / 64; ++q) {
+                wn.x += part[buf][q][lane].x;
+                wn.y += part[buf][q][lane].y;
+            }
+            if (wv == 0 && ok) w[i] = wn;
+            if constexpr (MODE == 1) {
+#pragma unroll
+                for (int m = 0; m < NVW; ++m) {
+                    acc[m].x = fma(v[m].x, wn.x, fma(v[m].y, wn.y, acc[m].x));
+                    acc[m].y = fma(v[m].x, wn.y, fma(-v[m].y, wn.x, acc[m].y));
+                }
+            } else {
+                if (wv == 0) nrm = fma(wn.x, wn.x, fma(wn.y, wn.y, nrm));
+            }
+        }
+    }
+    if constexpr (MODE == 2) {
+        nrm = wave_sum(nrm);
+        if (wv == 0 && lane == 0) partial[blockIdx.x] = make_double2(nrm, 0.0);
+    } else {
+#pragma unroll
+        for (int m = 0; m < NVW; ++m) {
+            const double sx = wave_sum(acc[m].x), sy = wave_sum(acc[m].y);
+            if (lane == 0 && m < nk) partial[(long long)blockIdx.x * nv + wv + 4 * m] = make_double2(sx, sy);
+        }
     }
 }
 
@@ -435,9 +458,35 @@ static unsigned grid_for(long long n) {
     return (unsigned)b;
 }
 
-int launch_multidot(long long n, int nv, const double2* V, long long ldv, const double*, const double2* w,
+static int launch_cgs(int mode, long long n, int nv, const double2* V, long long ldv, const double* scale,
+                      const double2* coef, double2* w, double2* partial, int nblocks, hipStream_t st) {
+    const int nvw = (nv + 3) / 4;
+#define SG_CGS(NVW_)                                                                                          \
+    if (nvw <= NVW_) {                                                                                        \
+        if (mode == 0)                                                                                        \
+            hipLaunchKernelGGL((k_cgs<NVW_, 0>), dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, w, partial); \
+        else if (mode == 1)                                                                                   \
+            hipLaunchKernelGGL((k_cgs<NVW_, 1>), dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, w, partial); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_cgs<NVW_, 2>), dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, w, partial); \
+        SG_HIP(hipGetLastError());                                                                            \
+        return 1;                                                                                             \
+    }
+    SG_CGS(1)
+    SG_CGS(2)
+    SG_CGS(4)
+    SG_CGS(8)
+    SG_CGS(16)
+#undef SG_CGS
+    return 0;
+}
+
+int launch_multidot(long long n, int nv, const double2* V, long long ldv, const double* scale, const double2* w,
                     double2* partial, int nblocks, hipStream_t st) {
     KScope ks(SG_K_DOT, 16.0 * (nv + 1) * (double)n, st);
+    const int r = launch_cgs(0, n, nv, V, ldv, scale, nullptr, const_cast<double2*>(w), partial, nblocks, st);
+    if (r < 0) return r;
+    if (r == 1) return SG_OK;
     hipLaunchKernelGGL(k_multidot, dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, w, partial);
     SG_HIP(hipGetLastError());
     return SG_OK;
@@ -475,26 +524,12 @@ int launch_lincomb(long long n, int nv, const double2* V, long long ldv, const d
     return SG_OK;
 }
 
-// Fused update (+ projection or + norm); returns 0 if nv is above the largest fused size.
+// Fused update (+ projection or + norm); returns 1 if handled, 0 if nv is above the
+// largest fused size (64), negative on error.
 int launch_upd(long long n, int nv, const double2* V, long long ldv, const double* scale, const double2* coef,
                double2* w, double2* partial, int nblocks, bool dot, hipStream_t st) {
     KScope ks(SG_K_AXPY, 16.0 * (nv + 2) * (double)n, st);
-#define SG_UPD(NV_)                                                                                       \
-    if (nv <= NV_) {                                                                                      \
-        if (dot)                                                                                          \
-            hipLaunchKernelGGL((k_upd<NV_, true>), dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, w, \
-                               partial);                                                                  \
-        else                                                                                              \
-            hipLaunchKernelGGL((k_upd<NV_, false>), dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, scale, coef, w, \
-                               partial);                                                                  \
-        SG_HIP(hipGetLastError());                                                                        \
-        return 1;                                                                                         \
-    }
-    SG_UPD(8)
-    SG_UPD(16)
-    SG_UPD(32)
-#undef SG_UPD
-    return 0;
+    return launch_cgs(dot ? 1 : 2, n, nv, V, ldv, scale, coef, w, partial, nblocks, st);
 }
 
 int launch_norm2(long long n, const double2* x, double2* partial, int nblocks, hipStream_t st) {

@@ -380,18 +380,17 @@ __global__ __launch_bounds__(64) void k_tri(double2* __restrict__ X, TriFactors 
 }
 
 // Segmented pivoted tridiagonal solve (same arithmetic as k_tri, in parallel over row
-// segments).  Thread (k, system) owns rows [k·L, k·L+L) of one system and keeps them in
-// registers.  Forward: run the segment with a zero entering value (segment 0 starts from
+// segments).  Thread (k, system) owns rows [k·L, k·L+L) (L <= SEGL) of one system and
+// keeps them in registers.  Forward: run the segment with a zero entering value (segment 0 starts from
 // b_0), exchange the end values through LDS, form the exact entering value from the
 // previous segments with the forward propagators, rerun and keep y_i/u_ii.  Backward: the
 // same with the 2-vector state (x_{i}, x_{i+1}) and the 2x2 propagators, from the last
 // segment upwards.  Data is read once and written once.
-constexpr int SEGL = 32;
-
 __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {   // a*b + c
     return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
 
+template <int SEGL>
 __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const TriFactors& f, int len, int na,
                                               int nq, long long se, long long sa, long long sq, int fa, int blk,
                                               double2 (&tf_)[256], double2 (&tb_)[256][2]) {
@@ -489,13 +488,15 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     }
 }
 
+template <int SEGL>
 __global__ __launch_bounds__(256) void k_tri_seg(double2* __restrict__ X, TriFactors f, int len, int na, int nq,
                                                  long long se, long long sa, long long sq, int fa) {
     __shared__ double2 tf_[256];
     __shared__ double2 tb_[256][2];
-    tri_seg_block(X, f, len, na, nq, se, sa, sq, fa, blockIdx.x, tf_, tb_);
+    tri_seg_block<SEGL>(X, f, len, na, nq, se, sa, sq, fa, blockIdx.x, tf_, tb_);
 }
 
+template <int SEGL>
 __global__ __launch_bounds__(256) void k_tri_seg_grouped(const TriTask* __restrict__ tasks,
                                                          const int* __restrict__ start, int ntask, int total) {
     __shared__ double2 tf_[256];
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(256) void k_tri_seg_grouped(const TriTask* __restri
     if (v >= total) return;
     const int t = find_task(start, ntask, v);
     const TriTask& g = tasks[t];
-    tri_seg_block(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], tf_, tb_);
+    tri_seg_block<SEGL>(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], tf_, tb_);
 }
 
 static inline uint16_t host_bf16(float f) {
@@ -573,9 +574,9 @@ int upload_dense_b(Ctx* c, hipStream_t) {
     return upload_one(c->inv, e);
 }
 
-// Tile shapes of the GEMM (BM × BN): 128×128, 64×128, 64×64.
-static const int kGemmWM[SG_GEMM_NCFG] = {4, 2, 2};
-static const int kGemmWN[SG_GEMM_NCFG] = {4, 4, 2};
+// Tile shapes of the GEMM (BM × BN): 128×128, 64×128, 64×64, 64×32, 32×64.
+static const int kGemmWM[SG_GEMM_NCFG] = {4, 2, 2, 2, 1};
+static const int kGemmWN[SG_GEMM_NCFG] = {4, 4, 2, 1, 2};
 
 void gemm_tiles(int cfg, int M, int Nc, int* tiles_m, int* tiles_n) {
     const int bm = 32 * kGemmWM[cfg], bn = 32 * kGemmWN[cfg];
@@ -614,6 +615,8 @@ static void launch_gemm_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks,
         SG_GEMM_CFG(0, 4, 4)
         SG_GEMM_CFG(1, 2, 4)
         SG_GEMM_CFG(2, 2, 2)
+        SG_GEMM_CFG(3, 2, 1)
+        SG_GEMM_CFG(4, 1, 2)
         default: break;
     }
 #undef SG_GEMM_CFG
@@ -633,9 +636,12 @@ static int dispatch_gemm(int precision, int cfg, const GemmTask& g, const GemmTa
 }
 
 static int launch_gemm(int precision, const double* A, const DenseB& B, int N, double* C, int M, hipStream_t st) {
-    const GemmTask g = make_gemm_task(precision, A, B, N, C, M, 0);
+    // tile shape from the autotuner table when this (n, Q, precision) was tuned
+    int cfg = tune_get(N, M / N, precision);
+    if (cfg < 0 || cfg >= SG_GEMM_NCFG) cfg = 0;
+    const GemmTask g = make_gemm_task(precision, A, B, N, C, M, cfg);
     KScope ks(SG_K_GEMM, 2.0 * M * (double)g.Nc * (double)g.Kc, st);
-    return dispatch_gemm(precision, 0, g, nullptr, nullptr, 0, 0, st);
+    return dispatch_gemm(precision, cfg, g, nullptr, nullptr, 0, 0, st);
 }
 
 int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const int* d_start, int ntask, int total,
@@ -661,11 +667,13 @@ TriTask make_tri_task(const TriFactors& f, double2* X, int n, int Q, int dim) {
     return t;
 }
 
-int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, int max_seg, double bytes,
                        hipStream_t st) {
     if (ntask <= 0 || total <= 0) return SG_OK;
+    if (max_seg > 32) return fail(SG_EINVAL, "grid too large for the grouped tridiagonal sweep");
     KScope ks(SG_K_TRI, bytes, st);
-    hipLaunchKernelGGL(k_tri_seg_grouped, dim3(total), dim3(256), 0, st, d_tasks, d_start, ntask, total);
+    if (max_seg <= 16) hipLaunchKernelGGL(k_tri_seg_grouped<16>, dim3(total), dim3(256), 0, st, d_tasks, d_start, ntask, total);
+    else hipLaunchKernelGGL(k_tri_seg_grouped<32>, dim3(total), dim3(256), 0, st, d_tasks, d_start, ntask, total);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
@@ -682,10 +690,11 @@ static int launch_tri(const TriFactors& f, double2* X, int n, int Q, int dim, hi
     const int blk = 64;
     // algorithmic: every element read and written once, factors read once
     KScope ks(SG_K_TRI, 32.0 * na * (double)nq * n + 65.0 * f.nsys * (double)n, st);
-    if (f.L <= SEGL && f.K >= 1) {
+    if (f.L <= 32 && f.K >= 1) {
         const int SYS = 256 / f.K;
-        hipLaunchKernelGGL(k_tri_seg, dim3((unsigned)((nth + SYS - 1) / SYS)), dim3(256), 0, st, X, f, n, na, nq, se,
-                           sa, sq, fa);
+        const dim3 grid((unsigned)((nth + SYS - 1) / SYS));
+        if (f.L <= 16) hipLaunchKernelGGL(k_tri_seg<16>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa);
+        else hipLaunchKernelGGL(k_tri_seg<32>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa);
         SG_HIP(hipGetLastError());
         return SG_OK;
     }

@@ -47,7 +47,7 @@ struct TriFactors {
     double2* du1 = nullptr;   // u_{i,i+1}
     double2* du2 = nullptr;   // u_{i,i+2}
     uint8_t* piv = nullptr;   // 1 if rows i and i+1 were swapped at step i
-    // segmented form (rows split into K segments of L <= 32 rows, see precond.hip)
+    // segmented form (rows split into K segments of L rows, L <= 16 up to n = 512, see precond.hip)
     int K = 0, L = 0;
     double2* u1p = nullptr;   // u_{i,i+1} / u_ii   (len rows, zero past the end)
     double2* u2p = nullptr;   // u_{i,i+2} / u_ii
@@ -74,7 +74,7 @@ struct GemmTask {
     long long lda, ldb, ldc;
     int M, Nc, Kc, tiles_m, tiles_n;
 };
-enum { SG_GEMM_NCFG = 3 };   // tile shapes 128×128, 64×128, 64×64
+enum { SG_GEMM_NCFG = 5 };   // tile shapes 128×128, 64×128, 64×64, 64×32, 32×64
 
 // One set of tridiagonal solves: element i of system (q, a) is X[q*sq + a*sa + i*se],
 // the factors of system a are at column a*fa of f.
@@ -120,6 +120,7 @@ struct Workspace {
 // Optional per-kernel-class event timing (sg_set_profiling / sg_kernel_times).
 struct Prof {
     bool on = false;
+    unsigned mask = ~0u;            // kinds recorded when on (bit k = kind k)
     double ms[SG_K_NKINDS] = {};
     long long cnt[SG_K_NKINDS] = {};
     double work[SG_K_NKINDS] = {};
@@ -142,7 +143,7 @@ struct KScope {
     hipStream_t st;
     hipEvent_t ev = nullptr;
     KScope(int k, double w, hipStream_t s) : kind(k), work(w), st(s) {
-        if (g_prof && g_prof->on) g_prof->begin(st, &ev);
+        if (g_prof && g_prof->on && ((g_prof->mask >> k) & 1u)) g_prof->begin(st, &ev);
     }
     ~KScope() {
         if (ev && g_prof && g_prof->on) g_prof->end(kind, work, st, ev);
@@ -196,6 +197,10 @@ int build_ctx(const sg_problem* prob, hipStream_t stream, Ctx** out);
 // apply.hip
 int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st);
 
+// batched.cpp (autotuner table)
+int tune_get(int n, int Q, int precision);
+void tune_set(int n, int Q, int precision, int cfg);
+
 // precond.hip
 int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, hipStream_t st);
 int upload_dense_b(Ctx* c, hipStream_t st);
@@ -204,7 +209,7 @@ GemmTask make_gemm_task(int precision, const double* A, const DenseB& B, int N, 
 int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const int* d_start, int ntask, int total,
                         double flops, hipStream_t st);
 TriTask make_tri_task(const TriFactors& f, double2* X, int n, int Q, int dim);
-int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, int max_seg, double bytes,
                        hipStream_t st);
 
 // krylov.hip

@@ -95,6 +95,7 @@ def lib():
     L.sg_net_load.argtypes = [vp, C.c_char_p]
     L.sg_attach_net.argtypes = [vp, vp]
     L.sg_set_profiling.argtypes = [vp, i]
+    L.sg_profile_kinds.argtypes = [vp, C.c_uint]
     L.sg_kernel_times.argtypes = [vp, i, C.POINTER(d), C.POINTER(ll), C.POINTER(d)]
     L.sg_strerror.argtypes = [i]
     L.sg_strerror.restype = C.c_char_p
@@ -104,7 +105,7 @@ def lib():
                  "sg_cgs2", "sg_norm", "sg_set_profiling", "sg_kernel_times", "sg_gmres_batched", "sg_autotune",
                  "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
                  "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step", "sg_net_train_pairs", "sg_net_save",
-                 "sg_net_load", "sg_attach_net"):
+                 "sg_net_load", "sg_attach_net", "sg_profile_kinds"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -264,7 +265,7 @@ def _wrap_device(ptr, n):
     return torch.as_tensor(h, device="cuda")
 
 
-TILES = {"128x128": 0, "64x128": 1, "64x64": 2}
+TILES = {"128x128": 0, "64x128": 1, "64x64": 2, "64x32": 3, "32x64": 4}
 
 
 def gmres_batched(ops, bs, xs=None, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8, stream=None):
@@ -400,6 +401,6 @@ def norm(x, stream=None) -> float:
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
             "sg_fgmres", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_cgs2", "sg_norm",
-            "sg_set_profiling", "sg_kernel_times", "sg_net_create", "sg_net_destroy", "sg_net_num_params",
+            "sg_set_profiling", "sg_profile_kinds", "sg_kernel_times", "sg_net_create", "sg_net_destroy", "sg_net_num_params",
             "sg_net_get_params", "sg_net_set_params", "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step",
             "sg_net_train_pairs", "sg_net_save", "sg_net_load", "sg_attach_net", "sg_strerror", "sg_last_error"]
