@@ -538,7 +538,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                                        stream)))
             return rc;
         if ((rc = launch_multidot_grouped(stg.dtasks(g_mdot), stg.dstart(g_mdot), g_mdot.n(), g_mdot.total(),
-                                          g_mdot.work, stream)))
+                                          g_upd1.maxnv, g_mdot.work, stream)))
             return rc;
         if ((rc = launch_reduce_grouped(stg.dtasks(g_red1), stg.dstart(g_red1), g_red1.n(), g_red1.total(), 0, stream)))
             return rc;

@@ -170,9 +170,9 @@ __global__ __launch_bounds__(RB) void k_axpby(long long n, double2 a, const doub
 // The four per-wave partial sums of the update meet in a double-buffered LDS array, so one
 // barrier per chunk suffices; every wave forms the same w_new, wave 0 stores it.
 template <int NVW, int MODE>
-__global__ __launch_bounds__(RB) void k_cgs(long long n, int nv, const double2* __restrict__ V, long long ldv,
-                                            const double* __restrict__ scale, const double2* __restrict__ coef,
-                                            double2* __restrict__ w, double2* __restrict__ partial) {
+__device__ __forceinline__ void cgs_block(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                          const double* __restrict__ scale, const double2* __restrict__ coef,
+                                          double2* __restrict__ w, double2* __restrict__ partial, int lb, int nb) {
     __shared__ double2 part[2][RB / 64][64];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(RB) void k_cgs(long long n, int nv, const double2* 
     for (int m = 0; m < NVW; ++m) acc[m] = make_double2(0.0, 0.0);
     double nrm = 0.0;
     int buf = 0;
-    for (long long c0 = (long long)blockIdx.x * 64; c0 < n; c0 += (long long)gridDim.x * 64, buf ^= 1) {
+    for (long long c0 = (long long)lb * 64; c0 < n; c0 += (long long)nb * 64, buf ^= 1) {
         const long long i = c0 + lane;
         const bool ok = i < n;
         double2 v[NVW];
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(RB) void k_cgs(long long n, int nv, const double2* 
                 wn.x += part[buf][q][lane].x;
                 wn.y += part[buf][q][lane].y;
             }
-            if (wv == 0 && ok) w[i] = wn;
+            if (wv == 0 && ok && nv > 0) w[i] = wn;
             if constexpr (MODE == 1) {
 #pragma unroll
                 for (int m = 0; m < NVW; ++m) {
@@ -238,14 +238,21 @@ __global__ __launch_bounds__(RB) void k_cgs(long long n, int nv, const double2* 
     }
     if constexpr (MODE == 2) {
         nrm = wave_sum(nrm);
-        if (wv == 0 && lane == 0) partial[blockIdx.x] = make_double2(nrm, 0.0);
+        if (wv == 0 && lane == 0) partial[lb] = make_double2(nrm, 0.0);
     } else {
 #pragma unroll
         for (int m = 0; m < NVW; ++m) {
             const double sx = wave_sum(acc[m].x), sy = wave_sum(acc[m].y);
-            if (lane == 0 && m < nk) partial[(long long)blockIdx.x * nv + wv + 4 * m] = make_double2(sx, sy);
+            if (lane == 0 && m < nk) partial[(long long)lb * nv + wv + 4 * m] = make_double2(sx, sy);
         }
     }
+}
+
+template <int NVW, int MODE>
+__global__ __launch_bounds__(RB) void k_cgs(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                            const double* __restrict__ scale, const double2* __restrict__ coef,
+                                            double2* __restrict__ w, double2* __restrict__ partial) {
+    cgs_block<NVW, MODE>(n, nv, V, ldv, scale, coef, w, partial, blockIdx.x, gridDim.x);
 }
 
 // ---- grouped forms: one launch over the solves of a batch -------------------------------
@@ -260,35 +267,13 @@ __device__ __forceinline__ int task_of(const int* __restrict__ start, int ntask,
     return lo;
 }
 
-// partial[lb][k] = Σ_{i in local block lb} conj(V_k[i]) · w[i]
-__global__ __launch_bounds__(RB) void k_multidot_g(const VecTask* __restrict__ tasks, const int* __restrict__ start,
-                                                   int ntask) {
-    __shared__ double2 red[(RB / 64) * KG];
+// The three CGS2 passes of cgs_block, per task.
+template <int NVW, int MODE>
+__global__ __launch_bounds__(RB) void k_cgs_g(const VecTask* __restrict__ tasks, const int* __restrict__ start,
+                                              int ntask) {
     const int t = task_of(start, ntask, blockIdx.x);
     const VecTask& g = tasks[t];
-    const int lb = blockIdx.x - start[t];
-    const long long n = g.n, ldv = g.ldv;
-    const int nv = g.nv;
-    const long long stride = (long long)g.nblocks * RB;
-    for (int kg = 0; kg < nv; kg += KG) {
-        double2 acc[KG];
-#pragma unroll
-        for (int k = 0; k < KG; ++k) acc[k] = make_double2(0.0, 0.0);
-        for (long long i = (long long)lb * RB + threadIdx.x; i < n; i += stride) {
-            const double2 wi = g.w[i];
-#pragma unroll
-            for (int k = 0; k < KG; ++k) {
-                if (kg + k < nv) {
-                    const double2 v = g.V[(long long)(kg + k) * ldv + i];
-                    acc[k].x += v.x * wi.x + v.y * wi.y;
-                    acc[k].y += v.x * wi.y - v.y * wi.x;
-                }
-            }
-        }
-        block_reduce(acc, red);
-        if (threadIdx.x < KG && kg + threadIdx.x < nv) g.partial[(long long)lb * nv + kg + threadIdx.x] = red[threadIdx.x];
-        __syncthreads();
-    }
+    cgs_block<NVW, MODE>(g.n, g.nv, g.V, g.ldv, g.scale, g.coef, g.w, g.partial, blockIdx.x - start[t], g.nblocks);
 }
 
 // One block per (task, output k): mode 0 out[k] = scale[k]·Σ_b partial[b][k] (nout = nv),
@@ -322,74 +307,6 @@ __global__ __launch_bounds__(RB) void k_reduce_g(const VecTask* __restrict__ tas
             const double s = g.scale ? g.scale[k] : 1.0;
             g.out[k] = make_double2(s * tx, s * ty);
         }
-    }
-}
-
-// Fused CGS2 update (+ projection or + squared norm), as k_upd, per task.
-template <int NV, bool DOT>
-__global__ __launch_bounds__(RB) void k_upd_g(const VecTask* __restrict__ tasks, const int* __restrict__ start,
-                                              int ntask) {
-    __shared__ double2 c[NV];
-    __shared__ double2 red[(RB / 64) * NV];
-    const int t = task_of(start, ntask, blockIdx.x);
-    const VecTask& g = tasks[t];
-    const int lb = blockIdx.x - start[t];
-    const int nv = g.nv;
-    const long long n = g.n, ldv = g.ldv;
-    for (int k = threadIdx.x; k < nv; k += RB) {
-        const double sk = -(g.scale ? g.scale[k] : 1.0);
-        c[k] = make_double2(g.coef[k].x * sk, g.coef[k].y * sk);
-    }
-    __syncthreads();
-    constexpr int NA = DOT ? NV : 1;
-    double2 acc[NA];
-#pragma unroll
-    for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
-    const long long stride = (long long)g.nblocks * RB;
-    double2* __restrict__ w = g.w;
-    const double2* __restrict__ V = g.V;
-    for (long long i = (long long)lb * RB + threadIdx.x; i < n; i += stride) {
-        double2 v[NV];
-        double2 wi = w[i];
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-            if (k < nv) {
-                v[k] = V[(long long)k * ldv + i];
-                const double2 ck = c[k];
-                wi.x = fma(v[k].x, ck.x, fma(-v[k].y, ck.y, wi.x));
-                wi.y = fma(v[k].x, ck.y, fma(v[k].y, ck.x, wi.y));
-            }
-        if (nv > 0) w[i] = wi;
-        if constexpr (DOT) {
-#pragma unroll
-            for (int k = 0; k < NV; ++k)
-                if (k < nv) {
-                    acc[k].x = fma(v[k].x, wi.x, fma(v[k].y, wi.y, acc[k].x));
-                    acc[k].y = fma(v[k].x, wi.y, fma(-v[k].y, wi.x, acc[k].y));
-                }
-        } else {
-            acc[0].x = fma(wi.x, wi.x, fma(wi.y, wi.y, acc[0].x));
-        }
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NA; ++k) {
-        acc[k].x = wave_sum(acc[k].x);
-        acc[k].y = wave_sum(acc[k].y);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < NA; ++k) red[wv * NV + k] = acc[k];
-    }
-    __syncthreads();
-    const int nout = DOT ? nv : 1;
-    for (int k = threadIdx.x; k < nout; k += RB) {
-        double2 s = red[k];
-        for (int ww = 1; ww < RB / 64; ++ww) {
-            s.x += red[ww * NV + k].x;
-            s.y += red[ww * NV + k].y;
-        }
-        g.partial[(long long)lb * nout + k] = s;
     }
 }
 
@@ -444,8 +361,10 @@ __global__ __launch_bounds__(RB) void k_axpby_g(const VecTask* __restrict__ task
 
 }  // namespace
 
+// First-stage blocks of the reductions: about four 64-element chunks per block (short
+// dependent chains for small vectors), at most MAXBLK.
 int reduction_blocks(long long n) {
-    long long b = (n + RB * 4 - 1) / (RB * 4);
+    long long b = (n + RB - 1) / RB;
     if (b < 1) b = 1;
     if (b > MAXBLK) b = MAXBLK;
     return (int)b;
@@ -554,13 +473,31 @@ int launch_scale_copy(long long n, double a, const double2* x, double2* out, hip
 
 namespace sgi {
 
-int launch_multidot_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+static int launch_cgs_grouped(int mode, const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv,
+                              hipStream_t st) {
+    const int nvw = (maxnv + 3) / 4;
+#define SG_CGSG(NVW_)                                                                                         \
+    if (nvw <= NVW_) {                                                                                        \
+        if (mode == 0) hipLaunchKernelGGL((k_cgs_g<NVW_, 0>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask); \
+        else if (mode == 1) hipLaunchKernelGGL((k_cgs_g<NVW_, 1>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask); \
+        else hipLaunchKernelGGL((k_cgs_g<NVW_, 2>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);  \
+        SG_HIP(hipGetLastError());                                                                            \
+        return SG_OK;                                                                                         \
+    }
+    SG_CGSG(1)
+    SG_CGSG(2)
+    SG_CGSG(4)
+    SG_CGSG(8)
+    SG_CGSG(16)
+#undef SG_CGSG
+    return fail(SG_EINVAL, "batched solve: restart length above 64");
+}
+
+int launch_multidot_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv, double bytes,
                             hipStream_t st) {
     if (ntask <= 0 || total <= 0) return SG_OK;
     KScope ks(SG_K_DOT, bytes, st);
-    hipLaunchKernelGGL(k_multidot_g, dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);
-    SG_HIP(hipGetLastError());
-    return SG_OK;
+    return launch_cgs_grouped(0, d_tasks, d_start, ntask, total, maxnv, st);
 }
 
 int launch_reduce_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int mode,
@@ -576,19 +513,7 @@ int launch_upd_grouped(const VecTask* d_tasks, const int* d_start, int ntask, in
                        double bytes, hipStream_t st) {
     if (ntask <= 0 || total <= 0) return SG_OK;
     KScope ks(SG_K_AXPY, bytes, st);
-#define SG_UPDG(NV_)                                                                                          \
-    if (maxnv <= NV_) {                                                                                       \
-        if (dot) hipLaunchKernelGGL((k_upd_g<NV_, true>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);  \
-        else hipLaunchKernelGGL((k_upd_g<NV_, false>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);     \
-        SG_HIP(hipGetLastError());                                                                            \
-        return SG_OK;                                                                                         \
-    }
-    SG_UPDG(8)
-    SG_UPDG(16)
-    SG_UPDG(32)
-    SG_UPDG(64)
-#undef SG_UPDG
-    return fail(SG_EINVAL, "batched solve: restart length above 63");
+    return launch_cgs_grouped(dot ? 1 : 2, d_tasks, d_start, ntask, total, maxnv, st);
 }
 
 int launch_lincomb_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv,

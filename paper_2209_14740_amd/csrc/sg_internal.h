@@ -232,7 +232,7 @@ int launch_axpby(long long n, double2 a, const double2* x, double2 b, const doub
 int launch_scale_copy(long long n, double a, const double2* x, double2* out, hipStream_t st);
 int reduction_blocks(long long n);
 // Grouped forms: task t of d_tasks owns blocks [start[t], start[t+1]) of the launch.
-int launch_multidot_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, double bytes,
+int launch_multidot_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv, double bytes,
                             hipStream_t st);
 int launch_reduce_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int mode,
                           hipStream_t st);
