@@ -265,6 +265,151 @@ __device__ __forceinline__ void gemm_tile(const GemmTask& g, int tile, Lds<MODE,
         }
 }
 
+// 3M complex product, FP64: C = A·B with complex A [M][K] (interleaved), B [K][N] given as
+// three real n-major planes Br, Bi, Bs = Br + Bi.  Per 16×16 complex output block and K step:
+// P1 += Ar·Br, P2 += Ai·Bi, P3 += (Ar+Ai)·Bs on v_mfma_f64_16x16x4f64; then Re = P1 − P2,
+// Im = P3 − P1 − P2.  Three real products per complex multiply-add instead of the four of
+// the expanded real form.  BM = 32·WM complex rows, BN = 32·WN complex columns, BK3 complex
+// k per LDS stage; the A planes are formed while staging.
+constexpr int BK3 = 16;
+
+template <int BM, int BN>
+struct Lds3 {
+    static constexpr int PAD = BK3 + 1;
+    double ar[BM * PAD], ai[BM * PAD], as[BM * PAD];
+    double br[BN * PAD], bi[BN * PAD], bs[BN * PAD];
+};
+
+template <int WM, int WN>
+__device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32 * WM, 32 * WN>& sm) {
+    constexpr int BM = 32 * WM, BN = 32 * WN;
+    constexpr int PAD = Lds3<BM, BN>::PAD;
+    const int M = g.M, N = g.Nc / 2, K = g.Kc / 2;   // complex sizes
+    const int tm = tile / g.tiles_n, tn = tile % g.tiles_n;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv >> 1, wn = wv & 1;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const double* __restrict__ A = g.A;
+    const double* __restrict__ Br = reinterpret_cast<const double*>(g.Bt0);
+    const double* __restrict__ Bi = reinterpret_cast<const double*>(g.Bt1);
+    const double* __restrict__ Bs = reinterpret_cast<const double*>(g.Bt2);
+    const long long lda = g.lda, ldb = g.ldb;
+
+    d4 p1[WM][WN], p2[WM][WN], p3[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = d4{0, 0, 0, 0};
+
+    // staging: A tile BM × BK3 complex = 16·BM double2 (BM/16 per thread); B planes
+    // BN × BK3 doubles each, loaded as double2 pairs along k (8·BN pairs, BN/32 per thread)
+    constexpr int PA = BM / 16, PB = BN / 32;
+    double2 ra[PA];
+    double2 rbr[PB], rbi[PB], rbs[PB];
+    auto load_tiles = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p) {
+            const int idx = p * 256 + tid, row = idx >> 4, k = idx & 15;
+            const int gm = m0 + row, gk = k0 + k;
+            ra[p] = (gm < M && gk < K) ? *reinterpret_cast<const double2*>(A + (long long)gm * lda + 2 * gk)
+                                       : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int idx = p * 256 + tid, row = idx >> 3, k = (idx & 7) * 2;
+            const int gn = n0 + row, gk = k0 + k;
+            // K is padded to an even ld with zero columns: a pair is inside or fully zero
+            const bool ok = gn < N && gk < K;
+            const long long off = (long long)gn * ldb + gk;
+            rbr[p] = ok ? *reinterpret_cast<const double2*>(Br + off) : make_double2(0.0, 0.0);
+            rbi[p] = ok ? *reinterpret_cast<const double2*>(Bi + off) : make_double2(0.0, 0.0);
+            rbs[p] = ok ? *reinterpret_cast<const double2*>(Bs + off) : make_double2(0.0, 0.0);
+        }
+    };
+    auto store_tiles = [&]() {
+#pragma unroll
+        for (int p = 0; p < PA; ++p) {
+            const int idx = p * 256 + tid, row = idx >> 4, k = idx & 15;
+            sm.ar[row * PAD + k] = ra[p].x;
+            sm.ai[row * PAD + k] = ra[p].y;
+            sm.as[row * PAD + k] = ra[p].x + ra[p].y;
+        }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int idx = p * 256 + tid, row = idx >> 3, k = (idx & 7) * 2;
+            sm.br[row * PAD + k] = rbr[p].x;
+            sm.br[row * PAD + k + 1] = rbr[p].y;
+            sm.bi[row * PAD + k] = rbi[p].x;
+            sm.bi[row * PAD + k + 1] = rbi[p].y;
+            sm.bs[row * PAD + k] = rbs[p].x;
+            sm.bs[row * PAD + k + 1] = rbs[p].y;
+        }
+    };
+
+    const int nk = (K + BK3 - 1) / BK3;
+    load_tiles(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        if (kt + 1 < nk) load_tiles((kt + 1) * BK3);
+#pragma unroll
+        for (int kk = 0; kk < BK3; kk += 4) {
+            double xr[WM], xi[WM], xs[WM], yr[WN], yi[WN], ys[WN];
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                const int r = (wm * (16 * WM) + i * 16 + l16) * PAD + kk + lq;
+                xr[i] = sm.ar[r];
+                xi[i] = sm.ai[r];
+                xs[i] = sm.as[r];
+            }
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                const int c = (wn * (16 * WN) + j * 16 + l16) * PAD + kk + lq;
+                yr[j] = sm.br[c];
+                yi[j] = sm.bi[c];
+                ys[j] = sm.bs[c];
+            }
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) {
+                    p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[i], yr[j], p1[i][j], 0, 0, 0);
+                    p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[i], yi[j], p2[i][j], 0, 0, 0);
+                    p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[i], ys[j], p3[i][j], 0, 0, 0);
+                }
+        }
+    }
+    // the f64 MFMA leaves D[lq + 4v][l16] of each 16×16 block in lane (lq, l16)
+    double* __restrict__ C = g.C;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            const int col = n0 + wn * (16 * WN) + j * 16 + l16;
+            if (col >= N) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * (16 * WM) + i * 16 + lq + 4 * v;
+                if (row < M) {
+                    const double re = p1[i][j][v] - p2[i][j][v];
+                    const double im = p3[i][j][v] - p1[i][j][v] - p2[i][j][v];
+                    *reinterpret_cast<double2*>(C + (long long)row * g.ldc + 2 * col) = make_double2(re, im);
+                }
+            }
+        }
+}
+
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm3m(GemmTask g) {
+    __shared__ Lds3<32 * WM, 32 * WN> sm;
+    const int per = gridDim.x / 8;
+    const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= g.tiles_m * g.tiles_n) return;
+    gemm3m_tile<WM, WN>(g, tile, sm);
+}
+
 // Single problem; blocks are dispatched round-robin over the 8 XCDs, so the tile index is
 // remapped to give each XCD a contiguous band of tiles (shared A rows and B in its L2).
 template <int MODE, int WM, int WN>
@@ -299,6 +444,18 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
     const int t = find_task(start, ntask, v);
     const GemmTask g = tasks[t];
     gemm_tile<MODE, WM, WN>(g, v - start[t], sm);
+}
+
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm3m_grouped(const GemmTask* __restrict__ tasks,
+                                                        const int* __restrict__ start, int ntask, int total) {
+    __shared__ Lds3<32 * WM, 32 * WN> sm;
+    const int per = gridDim.x / 8;
+    const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (v >= total) return;
+    const int t = find_task(start, ntask, v);
+    const GemmTask g = tasks[t];
+    gemm3m_tile<WM, WN>(g, v - start[t], sm);
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -538,6 +695,23 @@ static void expand_bt(int N, const std::vector<cplx>& B /* [k][n] */, std::vecto
         }
 }
 
+// 3M planes of the complex N×N matrix B[k][n]: n-major [n][k] rows of ld doubles (zero
+// padded), Re, Im and Re+Im one after the other.
+static int upload_planes(DenseB& d, int N, const std::vector<cplx>& B, int ld) {
+    const size_t plane = (size_t)N * ld;
+    std::vector<double> h(3 * plane, 0.0);
+    for (int k = 0; k < N; ++k)
+        for (int n = 0; n < N; ++n) {
+            const cplx b = B[(size_t)k * N + n];
+            h[(size_t)n * ld + k] = b.real();
+            h[plane + (size_t)n * ld + k] = b.imag();
+            h[2 * plane + (size_t)n * ld + k] = b.real() + b.imag();
+        }
+    SG_HIP(hipMalloc(&d.p3, h.size() * sizeof(double)));
+    SG_HIP(hipMemcpy(d.p3, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    return SG_OK;
+}
+
 static int upload_one(DenseB& d, const std::vector<double>& e) {
     const size_t cnt = e.size();
     std::vector<float> f32(cnt);
@@ -571,17 +745,21 @@ int upload_dense_b(Ctx* c, hipStream_t) {
     int rc = upload_one(c->fwd, e);
     if (rc) return rc;
     expand_bt(N, Bi, e, ld);
-    return upload_one(c->inv, e);
+    if ((rc = upload_one(c->inv, e))) return rc;
+    if ((rc = upload_planes(c->fwd, N, Bf, ld))) return rc;
+    return upload_planes(c->inv, N, Bi, ld);
 }
 
-// Tile shapes of the GEMM (BM × BN): 128×128, 64×128, 64×64, 64×32, 32×64.
-static const int kGemmWM[SG_GEMM_NCFG] = {4, 2, 2, 2, 1};
-static const int kGemmWN[SG_GEMM_NCFG] = {4, 4, 2, 1, 2};
+// Tile shapes (see SG_GEMM_NCFG): BM = 32·WM rows; BN = 32·WN real columns for the
+// expanded real form (cfg < 5), 32·WN complex columns for the 3M form (cfg >= 5).
+static const int kGemmWM[SG_GEMM_NCFG] = {4, 2, 2, 2, 1, 1, 2, 1, 2};
+static const int kGemmWN[SG_GEMM_NCFG] = {4, 4, 2, 1, 2, 1, 1, 2, 2};
 
 void gemm_tiles(int cfg, int M, int Nc, int* tiles_m, int* tiles_n) {
     const int bm = 32 * kGemmWM[cfg], bn = 32 * kGemmWN[cfg];
+    const int cols = cfg >= SG_GEMM_NCFG_REAL ? Nc / 2 : Nc;   // 3M tiles count complex columns
     *tiles_m = (M + bm - 1) / bm;
-    *tiles_n = (Nc + bn - 1) / bn;
+    *tiles_n = (cols + bn - 1) / bn;
 }
 
 GemmTask make_gemm_task(int precision, const double* A, const DenseB& B, int N, double* C, int M, int cfg) {
@@ -591,6 +769,13 @@ GemmTask make_gemm_task(int precision, const double* A, const DenseB& B, int N, 
     g.Bt0 = precision == SG_PREC_F64 ? (const void*)B.f64
           : precision == SG_PREC_F32 ? (const void*)B.f32 : (const void*)B.bf_hi;
     g.Bt1 = precision == SG_PREC_BF16X3 ? (const void*)B.bf_lo : nullptr;
+    g.Bt2 = nullptr;
+    if (cfg >= SG_GEMM_NCFG_REAL) {   // 3M planes, FP64
+        const size_t plane = (size_t)N * bexp_ld(N);
+        g.Bt0 = B.p3;
+        g.Bt1 = B.p3 + plane;
+        g.Bt2 = B.p3 + 2 * plane;
+    }
     g.lda = 2LL * N;
     g.ldc = 2LL * N;
     g.ldb = bexp_ld(N);
@@ -622,9 +807,34 @@ static void launch_gemm_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks,
 #undef SG_GEMM_CFG
 }
 
+static void launch_gemm3m_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks, const int* d_start, int ntask,
+                              int total, hipStream_t st) {
+    const int nt = d_tasks ? total : g.tiles_m * g.tiles_n;
+    const dim3 grid(((nt + 7) / 8) * 8), blk(256);
+#define SG_GEMM3(C_, WM_, WN_)                                                                              \
+    case C_:                                                                                                \
+        if (d_tasks) hipLaunchKernelGGL((k_gemm3m_grouped<WM_, WN_>), grid, blk, 0, st, d_tasks, d_start, ntask, total); \
+        else hipLaunchKernelGGL((k_gemm3m<WM_, WN_>), grid, blk, 0, st, g);                                    \
+        break;
+    switch (cfg) {
+        SG_GEMM3(5, 1, 1)
+        SG_GEMM3(6, 2, 1)
+        SG_GEMM3(7, 1, 2)
+        SG_GEMM3(8, 2, 2)
+        default: break;
+    }
+#undef SG_GEMM3
+}
+
 static int dispatch_gemm(int precision, int cfg, const GemmTask& g, const GemmTask* d_tasks, const int* d_start,
                          int ntask, int total, hipStream_t st) {
     if (cfg < 0 || cfg >= SG_GEMM_NCFG) return fail(SG_EINVAL, "unknown GEMM tile configuration");
+    if (cfg >= SG_GEMM_NCFG_REAL) {
+        if (precision != SG_PREC_F64) return fail(SG_EINVAL, "the 3M tile shapes are FP64 only");
+        launch_gemm3m_cfg(cfg, g, d_tasks, d_start, ntask, total, st);
+        SG_HIP(hipGetLastError());
+        return SG_OK;
+    }
     switch (precision) {
         case SG_PREC_F64: launch_gemm_cfg<MODE_F64>(cfg, g, d_tasks, d_start, ntask, total, st); break;
         case SG_PREC_F32: launch_gemm_cfg<MODE_F32>(cfg, g, d_tasks, d_start, ntask, total, st); break;
@@ -638,9 +848,11 @@ static int dispatch_gemm(int precision, int cfg, const GemmTask& g, const GemmTa
 static int launch_gemm(int precision, const double* A, const DenseB& B, int N, double* C, int M, hipStream_t st) {
     // tile shape from the autotuner table when this (n, Q, precision) was tuned
     int cfg = tune_get(N, M / N, precision);
-    if (cfg < 0 || cfg >= SG_GEMM_NCFG) cfg = 0;
+    if (cfg < 0 || cfg >= SG_GEMM_NCFG || (cfg >= SG_GEMM_NCFG_REAL && precision != SG_PREC_F64)) cfg = 0;
     const GemmTask g = make_gemm_task(precision, A, B, N, C, M, cfg);
-    KScope ks(SG_K_GEMM, 2.0 * M * (double)g.Nc * (double)g.Kc, st);
+    // algorithmic flops: 8 real flops per complex multiply-add, 6 with the 3M form
+    const double cmacs = (double)M * N * N;
+    KScope ks(SG_K_GEMM, (cfg >= SG_GEMM_NCFG_REAL ? 6.0 : 8.0) * cmacs, st);
     return dispatch_gemm(precision, cfg, g, nullptr, nullptr, 0, 0, st);
 }
 

@@ -428,6 +428,8 @@ Ctx::~Ctx() {
     (void)hipFree(inv.f32);
     (void)hipFree(inv.bf_hi);
     (void)hipFree(inv.bf_lo);
+    (void)hipFree(fwd.p3);
+    (void)hipFree(inv.p3);
     for (auto& t : tri) free_tri(t);
     (void)hipFree(ws.V);
     (void)hipFree(ws.Z);

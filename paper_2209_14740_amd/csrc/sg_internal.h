@@ -62,6 +62,7 @@ struct DenseB {
     float* f32 = nullptr;      // [2N][2N]
     uint16_t* bf_hi = nullptr; // [2N][2N] bf16 bits, packed for the MFMA B operand
     uint16_t* bf_lo = nullptr;
+    double* p3 = nullptr;      // 3M planes of B (n-major [n][k], ld = bexp_ld(N)): Re, Im, Re+Im
 };
 
 // One dense problem C[M][Nc] = A[M][Kc] · B of the preconditioner transforms, Bt[Nc][Kc]
@@ -70,11 +71,15 @@ struct GemmTask {
     const double* A;
     const void* Bt0;
     const void* Bt1;
+    const void* Bt2;
     double* C;
     long long lda, ldb, ldc;
     int M, Nc, Kc, tiles_m, tiles_n;
 };
-enum { SG_GEMM_NCFG = 5 };   // tile shapes 128×128, 64×128, 64×64, 64×32, 32×64
+// GEMM tile shapes: 0..4 the expanded real form (BM × BN real columns) 128×128, 64×128,
+// 64×64, 64×32, 32×64 for every precision; 5..8 the 3M complex form (FP64 only, BM × BN
+// complex columns) 32×32, 64×32, 32×64, 64×64.
+enum { SG_GEMM_NCFG = 9, SG_GEMM_NCFG_REAL = 5 };
 
 // One set of tridiagonal solves: element i of system (q, a) is X[q*sq + a*sa + i*se],
 // the factors of system a are at column a*fa of f.

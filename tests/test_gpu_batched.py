@@ -86,7 +86,8 @@ def test_batched_iterations_match_single(small_ops):
         assert d <= 1e-9
 
 
-@pytest.mark.parametrize("tile", ["128x128", "64x128", "64x64", "64x32", "32x64"])
+@pytest.mark.parametrize("tile", ["128x128", "64x128", "64x64", "64x32", "32x64", "3m32x32", "3m64x32", "3m32x64",
+                                  "3m64x64"])
 def test_batched_tile_shapes(small_ops, tile):
     for op in small_ops:
         if op.dim == 2:
@@ -135,7 +136,7 @@ def test_autotune_fills_table(small_ops):
     assert ms > 0
     for op in small_ops:
         if op.dim == 2:
-            assert sg.tune_get(op.n, op.Q, "bf16x3") in range(5)
+            assert sg.tune_get(op.n, op.Q, "bf16x3") in range(5)      # 3M shapes are FP64 only
 
 
 def test_batched_config4_sample_full_size():

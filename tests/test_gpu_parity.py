@@ -310,3 +310,24 @@ def test_setup_kbar_with_close_eigenvalues():
     zz = to_host(z)
     assert np.all(np.isfinite(zz)) and np.linalg.norm(zz) > 0
     op.close()
+
+
+@pytest.mark.parametrize("tile", ["3m32x32", "3m64x32", "3m32x64", "3m64x64", "32x64"])
+@pytest.mark.parametrize("key", ["2d_n150_s3_r3", "2d_n37_s2_r4"])
+def test_precond_f64_tile_shapes(key, tile):
+    """Every FP64 transform tile shape, including the 3M complex form (three real products
+    per complex multiply-add), against the oracle's sparse-LU block solve (1e-9)."""
+    inst = SMALL[key]()
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    sg.tune_set(op.n, op.Q, "f64", tile)
+    try:
+        r = rand_vec(S.A.shape[0], 21)
+        ref = precond.mean_value(S)(r)
+        z = to_host(op.precond(to_dev(r), pc="mean", precision="f64"))
+        err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+        assert err <= 1e-9, err
+    finally:
+        sg.tune_set(op.n, op.Q, "f64", "128x128")
+    with pytest.raises(sg.SGError):
+        sg.tune_set(op.n, op.Q, "f32", "3m32x32")
