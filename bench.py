@@ -282,6 +282,43 @@ def learned_config5(n_pairs, n_eval, log):
     return out
 
 
+def mixed_config3(log):
+    """Mixed-precision forms on their own workload (config 3: 511x511, Q=84, 21.9M
+    unknowns): plain FP64 GMRES(50) against FGMRES(50) with FP32 and BF16x3 transforms, all
+    to the FP64 true relative residual 1e-8 (one warm-up and two timed solves each)."""
+    import torch
+    from paper_2209_14740_amd import sg
+    from workloads import config3
+    inst = config3()
+    t0 = time.perf_counter()
+    op = sg.SG.from_instance(inst)
+    for prec in ("f64", "f32", "bf16x3"):
+        sg.autotune([op], prec, reps=3)
+    setup_s = time.perf_counter() - t0
+    b = op.rhs(inst.f)
+    x = op.empty()
+    out = {"workload": "2D 511x511 nodes, kbar=40, sigma=4, s=6 sine modes, degree 3 (Q=84), 21,934,164 unknowns; "
+                       "mean-value preconditioner, restart 50, true relres 1e-8 from x=0",
+           "setup_s": setup_s, "gemm_tiles": {p_: sg.tune_get(op.n, op.Q, p_) for p_ in ("f64", "f32", "bf16x3")}}
+    x_plain = None
+    for name, fn, prec in (("plain_f64_gmres", op.gmres, "f64"), ("mixed_f32_fgmres", op.fgmres, "f32"),
+                           ("mixed_bf16x3_fgmres", op.fgmres, "bf16x3")):
+        t, info = time_solve(op, b, x, 2, 1, name != "plain_f64_gmres", pc="mean", precision=prec, restart=50,
+                             maxit=1000, tol=1e-8)
+        rec = {"s": t, "iters": info["iters"], "relres_true": info["relres_true"]}
+        if x_plain is None:
+            x_plain = x.clone()
+        else:
+            rec["max_rel_diff_vs_plain"] = float((x - x_plain).abs().max() / x_plain.abs().max())
+            rec["speedup_vs_plain"] = out["plain_f64_gmres"]["s"] / t
+        out[name] = rec
+        log("config 3 %s: %.1f ms, %d iterations" % (name, t * 1e3, info["iters"]))
+    op.close()
+    del x, x_plain, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def paper_context():
     """The paper's own timed 1D experiment (Section 6: k̄ = 50, θ = 0.1, degree 3, point
     source, A_0 as right preconditioner, full GMRES to 1e-12), for context only."""
@@ -347,6 +384,9 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched leg (for profiling); prints its JSON object")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-mixed3", action="store_true")
+    ap.add_argument("--mixed3-only", action="store_true",
+                    help="run only the config-3 mixed-precision leg; prints its JSON object")
     ap.add_argument("--matvec-only", action="store_true",
                     help="run only the SG-operator bandwidth leg; prints its JSON object")
     ap.add_argument("--calib-copy", action="store_true",
@@ -358,8 +398,9 @@ def main():
                     help="run only the learned leg; prints its JSON object")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this solver runs on one GPU; a run on %d GPUs is not part of this build "
-              "(see DESIGN.md for how the path would shard)" % args.gpus, file=sys.stderr)
+        print("bench.py: this solver runs on one GPU; a run on %d GPUs is not supported (one large "
+              "solve would shard into y-slabs with halo exchanges and all-to-all transposes of the "
+              "preconditioner, the batched workload by instances)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -374,6 +415,9 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
         del src, dst
+    if args.mixed3_only:
+        print(json.dumps({"mixed_config3": mixed_config3(log)}))
+        return
     if args.matvec_only:
         print(json.dumps({"matvec": matvec_bandwidth(config3(), 20)}))
         return
@@ -466,6 +510,9 @@ def main():
     if not args.no_matvec:
         log("matvec bandwidth on config 3")
         out["matvec"] = matvec_bandwidth(config3(), 20)
+    if not args.no_mixed3:
+        log("mixed-precision forms on config 3")
+        out["mixed_config3"] = mixed_config3(log)
     log("paper context (Section 6, 1D)")
     out["paper_context"] = paper_context()
     if not args.no_batched:

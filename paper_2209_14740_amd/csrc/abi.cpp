@@ -270,8 +270,7 @@ int sg_tune_get(int n, int Q, int precision) {
 int sg_tune_set(int n, int Q, int precision, int tile) {
     SG_TRY({
         if (tile < 0 || tile >= sgi::SG_GEMM_NCFG) return fail(SG_EINVAL, "unknown tile shape");
-        if (tile >= sgi::SG_GEMM_NCFG_REAL && precision != SG_PREC_F64)
-            return fail(SG_EINVAL, "the 3M tile shapes are FP64 only");
+        if (!sgi::gemm_cfg_valid(tile, precision)) return fail(SG_EINVAL, "tile shape not available in this precision");
         if (n < 1 || Q < 1 || precision < SG_PREC_F64 || precision > SG_PREC_BF16X3)
             return fail(SG_EINVAL, "invalid table key");
         sgi::tune_set(n, Q, precision, tile);

@@ -397,13 +397,13 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                 g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
             } else {
                 int cfg = tune_get(c->n, c->Q, prec);
-                if (cfg < 0 || cfg >= SG_GEMM_NCFG || (cfg >= SG_GEMM_NCFG_REAL && prec != SG_PREC_F64)) cfg = 0;
+                if (!gemm_cfg_valid(cfg, prec)) cfg = 0;
                 const int M = c->Q * c->n;
                 GemmTask gf = make_gemm_task(prec, reinterpret_cast<const double*>(pi.second), c->fwd, c->n,
                                              reinterpret_cast<double*>(c->d_tmp_pc), M, cfg);
                 GemmTask gi = make_gemm_task(prec, reinterpret_cast<const double*>(c->d_tmp_pc), c->inv, c->n,
                                              reinterpret_cast<double*>(s.zt), M, cfg);
-                const double fl = (cfg >= SG_GEMM_NCFG_REAL ? 6.0 : 8.0) * M * (double)c->n * c->n;
+                const double fl = (gemm_cfg_3m(cfg) ? 6.0 : 8.0) * M * (double)c->n * c->n;
                 g_fwd[cfg].add(gf, gf.tiles_m * gf.tiles_n, fl);
                 g_inv[cfg].add(gi, gi.tiles_m * gi.tiles_n, fl);
                 TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->Q, 2);
@@ -735,8 +735,8 @@ int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out
         } ft{d_tasks};
         double best = 1e300;
         int best_cfg = 0;
-        const int ncfg = precision == SG_PREC_F64 ? SG_GEMM_NCFG : SG_GEMM_NCFG_REAL;
-        for (int cfg = 0; cfg < ncfg; ++cfg) {
+        for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg) {
+            if (!gemm_cfg_valid(cfg, precision)) continue;
             std::vector<GemmTask> tasks(G);
             std::vector<int> start(G + 1, 0);
             for (int g = 0; g < G; ++g) {

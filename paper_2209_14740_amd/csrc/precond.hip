@@ -752,12 +752,12 @@ int upload_dense_b(Ctx* c, hipStream_t) {
 
 // Tile shapes (see SG_GEMM_NCFG): BM = 32·WM rows; BN = 32·WN real columns for the
 // expanded real form (cfg < 5), 32·WN complex columns for the 3M form (cfg >= 5).
-static const int kGemmWM[SG_GEMM_NCFG] = {4, 2, 2, 2, 1, 1, 2, 1, 2};
-static const int kGemmWN[SG_GEMM_NCFG] = {4, 4, 2, 1, 2, 1, 1, 2, 2};
+static const int kGemmWM[SG_GEMM_NCFG] = {4, 2, 2, 2, 1, 1, 2, 1, 2, 2, 4};
+static const int kGemmWN[SG_GEMM_NCFG] = {4, 4, 2, 1, 2, 1, 1, 2, 2, 8, 8};
 
 void gemm_tiles(int cfg, int M, int Nc, int* tiles_m, int* tiles_n) {
     const int bm = 32 * kGemmWM[cfg], bn = 32 * kGemmWN[cfg];
-    const int cols = cfg >= SG_GEMM_NCFG_REAL ? Nc / 2 : Nc;   // 3M tiles count complex columns
+    const int cols = gemm_cfg_3m(cfg) ? Nc / 2 : Nc;   // 3M tiles count complex columns
     *tiles_m = (M + bm - 1) / bm;
     *tiles_n = (cols + bn - 1) / bn;
 }
@@ -770,7 +770,7 @@ GemmTask make_gemm_task(int precision, const double* A, const DenseB& B, int N, 
           : precision == SG_PREC_F32 ? (const void*)B.f32 : (const void*)B.bf_hi;
     g.Bt1 = precision == SG_PREC_BF16X3 ? (const void*)B.bf_lo : nullptr;
     g.Bt2 = nullptr;
-    if (cfg >= SG_GEMM_NCFG_REAL) {   // 3M planes, FP64
+    if (gemm_cfg_3m(cfg)) {   // 3M planes, FP64
         const size_t plane = (size_t)N * bexp_ld(N);
         g.Bt0 = B.p3;
         g.Bt1 = B.p3 + plane;
@@ -804,6 +804,13 @@ static void launch_gemm_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks,
         SG_GEMM_CFG(4, 1, 2)
         default: break;
     }
+    if constexpr (MODE != MODE_F64) {   // wide tiles (the FP64 accumulators would not fit)
+        switch (cfg) {
+            SG_GEMM_CFG(9, 2, 8)
+            SG_GEMM_CFG(10, 4, 8)
+            default: break;
+        }
+    }
 #undef SG_GEMM_CFG
 }
 
@@ -828,9 +835,8 @@ static void launch_gemm3m_cfg(int cfg, const GemmTask& g, const GemmTask* d_task
 
 static int dispatch_gemm(int precision, int cfg, const GemmTask& g, const GemmTask* d_tasks, const int* d_start,
                          int ntask, int total, hipStream_t st) {
-    if (cfg < 0 || cfg >= SG_GEMM_NCFG) return fail(SG_EINVAL, "unknown GEMM tile configuration");
-    if (cfg >= SG_GEMM_NCFG_REAL) {
-        if (precision != SG_PREC_F64) return fail(SG_EINVAL, "the 3M tile shapes are FP64 only");
+    if (!gemm_cfg_valid(cfg, precision)) return fail(SG_EINVAL, "GEMM tile configuration not available in this precision");
+    if (gemm_cfg_3m(cfg)) {
         launch_gemm3m_cfg(cfg, g, d_tasks, d_start, ntask, total, st);
         SG_HIP(hipGetLastError());
         return SG_OK;
@@ -848,11 +854,11 @@ static int dispatch_gemm(int precision, int cfg, const GemmTask& g, const GemmTa
 static int launch_gemm(int precision, const double* A, const DenseB& B, int N, double* C, int M, hipStream_t st) {
     // tile shape from the autotuner table when this (n, Q, precision) was tuned
     int cfg = tune_get(N, M / N, precision);
-    if (cfg < 0 || cfg >= SG_GEMM_NCFG || (cfg >= SG_GEMM_NCFG_REAL && precision != SG_PREC_F64)) cfg = 0;
+    if (!gemm_cfg_valid(cfg, precision)) cfg = 0;
     const GemmTask g = make_gemm_task(precision, A, B, N, C, M, cfg);
     // algorithmic flops: 8 real flops per complex multiply-add, 6 with the 3M form
     const double cmacs = (double)M * N * N;
-    KScope ks(SG_K_GEMM, (cfg >= SG_GEMM_NCFG_REAL ? 6.0 : 8.0) * cmacs, st);
+    KScope ks(SG_K_GEMM, (gemm_cfg_3m(cfg) ? 6.0 : 8.0) * cmacs, st);
     return dispatch_gemm(precision, cfg, g, nullptr, nullptr, 0, 0, st);
 }
 

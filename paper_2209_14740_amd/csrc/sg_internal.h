@@ -76,10 +76,18 @@ struct GemmTask {
     long long lda, ldb, ldc;
     int M, Nc, Kc, tiles_m, tiles_n;
 };
-// GEMM tile shapes: 0..4 the expanded real form (BM × BN real columns) 128×128, 64×128,
-// 64×64, 64×32, 32×64 for every precision; 5..8 the 3M complex form (FP64 only, BM × BN
-// complex columns) 32×32, 64×32, 32×64, 64×64.
-enum { SG_GEMM_NCFG = 9, SG_GEMM_NCFG_REAL = 5 };
+// GEMM tile shapes: the expanded real form (BM × BN real columns, every precision) 0:
+// 128×128, 1: 64×128, 2: 64×64, 3: 64×32, 4: 32×64, 9: 64×256, 10: 128×256 (FP32 / BF16x3);
+// the 3M complex form (BM × BN complex columns, FP64 only) 5: 32×32, 6: 64×32, 7: 32×64,
+// 8: 64×64.
+enum { SG_GEMM_NCFG = 11 };
+inline bool gemm_cfg_3m(int cfg) { return cfg >= 5 && cfg <= 8; }
+inline bool gemm_cfg_valid(int cfg, int precision) {
+    if (cfg < 0 || cfg >= SG_GEMM_NCFG) return false;
+    if (gemm_cfg_3m(cfg)) return precision == SG_PREC_F64;
+    if (cfg >= 9) return precision != SG_PREC_F64;
+    return true;
+}
 
 // One set of tridiagonal solves: element i of system (q, a) is X[q*sq + a*sa + i*se],
 // the factors of system a are at column a*fa of f.

@@ -266,7 +266,7 @@ def _wrap_device(ptr, n):
 
 
 TILES = {"128x128": 0, "64x128": 1, "64x64": 2, "64x32": 3, "32x64": 4, "3m32x32": 5, "3m64x32": 6, "3m32x64": 7,
-         "3m64x64": 8}
+         "3m64x64": 8, "64x256": 9, "128x256": 10}
 
 
 def gmres_batched(ops, bs, xs=None, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8, stream=None):

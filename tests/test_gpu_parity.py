@@ -154,6 +154,29 @@ def test_precond_parity_mixed(key, precision, tol):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("tile", ["64x256", "128x256"])
+@pytest.mark.parametrize("precision,tol", [("f32", 2e-4), ("bf16x3", 2e-3)])
+@pytest.mark.parametrize("key", ["2d_n150_s3_r3", "2d_n37_s2_r4"])
+def test_precond_mixed_wide_tiles(key, precision, tol, tile):
+    """The 256-column transform tiles of the reduced-precision forms (several column tiles
+    and a ragged tail at n = 150, one partial tile at n = 37) against the oracle's block
+    solve; FP64 rejects them (their accumulators would not fit)."""
+    inst = SMALL[key]()
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    sg.tune_set(op.n, op.Q, precision, tile)
+    try:
+        r = rand_vec(S.A.shape[0], 22)
+        ref = precond.mean_value(S)(r)
+        z = to_host(op.precond(to_dev(r), pc="mean", precision=precision))
+        err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+        assert err <= tol, err
+    finally:
+        sg.tune_set(op.n, op.Q, precision, "128x128")
+    with pytest.raises(sg.SGError):
+        sg.tune_set(op.n, op.Q, "f64", tile)
+
+
 def test_precond_in_place_alias():
     inst = SMALL["2d_n37_s2_r4"]()
     op = sg.SG.from_instance(inst)
@@ -331,3 +354,36 @@ def test_precond_f64_tile_shapes(key, tile):
         sg.tune_set(op.n, op.Q, "f64", "128x128")
     with pytest.raises(sg.SGError):
         sg.tune_set(op.n, op.Q, "f32", "3m32x32")
+
+
+def test_config3_forms_full_size():
+    """The mixed-precision workload at full size (511², Q = 84): plain FP64 GMRES(50) and
+    BF16x3 FGMRES(50) both reach the FP64 true relative residual 1e-8, agree with each other
+    to 1e-6 (both are within 1e-8 of the exact solution in the residual norm of a system with
+    κ ≈ 1e2 after preconditioning), and the oracle's pointwise rows of A reproduce the GPU
+    residual at sampled points."""
+    inst = config3()
+    op = sg.SG.from_instance(inst)
+    try:
+        b = op.rhs(inst.f)
+        x64, i64 = op.gmres(b, restart=50, maxit=400, pc="mean", precision="f64", tol=1e-8)
+        xbf, ibf = op.fgmres(b, restart=50, maxit=400, pc="mean", precision="bf16x3", tol=1e-8)
+        print("config 3: f64 %d its %.2e, bf16x3 %d its %.2e" % (i64["iters"], i64["relres_true"], ibf["iters"],
+                                                                   ibf["relres_true"]), flush=True)
+        assert i64["converged"] == 1 and ibf["converged"] == 1
+        d = float((x64 - xbf).abs().max() / x64.abs().max())
+        assert d <= 1e-6, d
+        r = b - op.apply(xbf)
+        rel = sg.norm(r) / sg.norm(b)
+        assert rel <= 1.05e-8
+        rng = np.random.default_rng(5)
+        n, P = inst.n, inst.points
+        pts = np.unique(np.concatenate([rng.integers(0, P, 40), [0, n - 1, P - n, P - 1, (n // 2) * n + n // 2]]))
+        xh, rh, bh = to_host(xbf), to_host(r), to_host(b)
+        ax = assemble.apply_at_points(inst, xh, pts)
+        idx = (np.arange(op.Q)[:, None] * P + pts[None, :]).ravel()
+        kmax = np.max(np.abs(inst.k_fields).sum(axis=0))
+        rowsum = (8.0 / inst.h ** 2 + 4.0 * kmax ** 2 + 2.0 * kmax / inst.h) * np.max(np.abs(xh))
+        assert np.max(np.abs(bh[idx] - ax.ravel() - rh[idx])) <= 64 * 2.2e-16 * rowsum
+    finally:
+        op.close()
