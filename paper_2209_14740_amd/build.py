@@ -28,6 +28,8 @@ FLAGS = [
     "-O3", "-std=c++20", "-fPIC", "--offload-arch=" + ARCH,
     # never let the compiler form packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep MFMA accumulators in ordinary VGPRs (no AGPR copies around every K step)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-fconstexpr-steps=400000000", "-Wno-unused-result", "-I" + INCLUDE, "-I" + CSRC,
 ]
 

@@ -393,20 +393,20 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
             if (pc == SG_PC_NONE) continue;
             const TriFactors& f = c->tri[pc == SG_PC_MEAN ? 0 : 1];
             if (c->dim == 1) {
-                TriTask tt = make_tri_task(f, s.zt, c->n, c->Q, 1);
+                TriTask tt = make_tri_task(f, s.zt, c->n, c->n, c->Q, 1);
                 g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
             } else {
                 int cfg = tune_get(c->n, c->Q, prec);
                 if (!gemm_cfg_valid(cfg, prec)) cfg = 0;
                 const int M = c->Q * c->n;
-                GemmTask gf = make_gemm_task(prec, reinterpret_cast<const double*>(pi.second), c->fwd, c->n,
-                                             reinterpret_cast<double*>(c->d_tmp_pc), M, cfg);
-                GemmTask gi = make_gemm_task(prec, reinterpret_cast<const double*>(c->d_tmp_pc), c->inv, c->n,
-                                             reinterpret_cast<double*>(s.zt), M, cfg);
+                GemmTask gf = make_gemm_task(prec, reinterpret_cast<const double*>(pi.second), c->n, c->fwd, c->n,
+                                             reinterpret_cast<double*>(c->d_tmp_pc), c->tld, M, cfg);
+                GemmTask gi = make_gemm_task(prec, reinterpret_cast<const double*>(c->d_tmp_pc), c->tld, c->inv, c->n,
+                                             reinterpret_cast<double*>(s.zt), c->n, M, cfg);
                 const double fl = (gemm_cfg_3m(cfg) ? 6.0 : 8.0) * M * (double)c->n * c->n;
                 g_fwd[cfg].add(gf, gf.tiles_m * gf.tiles_n, fl);
                 g_inv[cfg].add(gi, gi.tiles_m * gi.tiles_n, fl);
-                TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->Q, 2);
+                TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->tld, c->Q, 2);
                 g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
             }
         }
@@ -720,15 +720,17 @@ int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out
             ~FB() { (void)hipFree(p); }
         } fb{buf};
         SG_HIP(hipMemsetAsync(buf, 0, (size_t)G * nv * sizeof(double2), stream));
-        // tasks: input = the zeroed scratch of task g, output = the handle's own intermediate
+        // tasks: the forward transform (zeroed scratch of task g -> the handle's own
+        // intermediate) and the inverse one (intermediate -> scratch), the two layouts of a
+        // preconditioner application, in two launches per repetition
         int* d_start = nullptr;
         GemmTask* d_tasks = nullptr;
-        SG_HIP(hipMalloc(&d_start, (G + 1) * sizeof(int)));
+        SG_HIP(hipMalloc(&d_start, 2 * (G + 1) * sizeof(int)));
         struct FS {
             void* p;
             ~FS() { (void)hipFree(p); }
         } fs{d_start};
-        SG_HIP(hipMalloc(&d_tasks, G * sizeof(GemmTask)));
+        SG_HIP(hipMalloc(&d_tasks, 2 * G * sizeof(GemmTask)));
         struct FT {
             void* p;
             ~FT() { (void)hipFree(p); }
@@ -737,20 +739,29 @@ int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out
         int best_cfg = 0;
         for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg) {
             if (!gemm_cfg_valid(cfg, precision)) continue;
-            std::vector<GemmTask> tasks(G);
-            std::vector<int> start(G + 1, 0);
+            std::vector<GemmTask> tasks(2 * G);
+            std::vector<int> start(2 * (G + 1), 0);
             for (int g = 0; g < G; ++g) {
-                tasks[g] = make_gemm_task(precision, reinterpret_cast<const double*>(buf + (size_t)g * nv), hs[g]->fwd, n,
-                                          reinterpret_cast<double*>(hs[g]->d_tmp_pc), Q * n, cfg);
+                double* io = reinterpret_cast<double*>(buf + (size_t)g * nv);
+                double* tmp = reinterpret_cast<double*>(hs[g]->d_tmp_pc);
+                tasks[g] = make_gemm_task(precision, io, n, hs[g]->fwd, n, tmp, hs[g]->tld, Q * n, cfg);
+                tasks[G + g] = make_gemm_task(precision, tmp, hs[g]->tld, hs[g]->inv, n, io, n, Q * n, cfg);
                 start[g + 1] = start[g] + tasks[g].tiles_m * tasks[g].tiles_n;
+                start[G + 1 + g + 1] = start[G + 1 + g] + tasks[G + g].tiles_m * tasks[G + g].tiles_n;
             }
-            SG_HIP(hipMemcpyAsync(d_tasks, tasks.data(), G * sizeof(GemmTask), hipMemcpyHostToDevice, stream));
-            SG_HIP(hipMemcpyAsync(d_start, start.data(), (G + 1) * sizeof(int), hipMemcpyHostToDevice, stream));
-            int rc = launch_gemm_grouped(precision, cfg, d_tasks, d_start, G, start[G], 0.0, stream);
+            SG_HIP(hipMemcpyAsync(d_tasks, tasks.data(), 2 * G * sizeof(GemmTask), hipMemcpyHostToDevice, stream));
+            SG_HIP(hipMemcpyAsync(d_start, start.data(), 2 * (G + 1) * sizeof(int), hipMemcpyHostToDevice, stream));
+            auto both = [&]() {
+                int rc = launch_gemm_grouped(precision, cfg, d_tasks, d_start, G, start[G], 0.0, stream);
+                if (rc) return rc;
+                return launch_gemm_grouped(precision, cfg, d_tasks + G, d_start + G + 1, G, start[2 * G + 1], 0.0,
+                                           stream);
+            };
+            int rc = both();
             if (rc) return rc;
             SG_HIP(hipEventRecord(e0, stream));
             for (int r = 0; r < reps; ++r)
-                if ((rc = launch_gemm_grouped(precision, cfg, d_tasks, d_start, G, start[G], 0.0, stream))) return rc;
+                if ((rc = both())) return rc;
             SG_HIP(hipEventRecord(e1, stream));
             SG_HIP(hipEventSynchronize(e1));
             float ms = 0;

@@ -266,18 +266,19 @@ __device__ __forceinline__ void gemm_tile(const GemmTask& g, int tile, Lds<MODE,
 }
 
 // 3M complex product, FP64: C = A·B with complex A [M][K] (interleaved), B [K][N] given as
-// three real n-major planes Br, Bi, Bs = Br + Bi.  Per 16×16 complex output block and K step:
-// P1 += Ar·Br, P2 += Ai·Bi, P3 += (Ar+Ai)·Bs on v_mfma_f64_16x16x4f64; then Re = P1 − P2,
-// Im = P3 − P1 − P2.  Three real products per complex multiply-add instead of the four of
-// the expanded real form.  BM = 32·WM complex rows, BN = 32·WN complex columns, BK3 complex
-// k per LDS stage; the A planes are formed while staging.
+// two real n-major planes Br, Bi.  Per 16×16 complex output block and K step:
+// P1 += Ar·Br, P2 += Ai·Bi, P3 += (Ar+Ai)·(Br+Bi) on v_mfma_f64_16x16x4f64; then
+// Re = P1 − P2, Im = P3 − P1 − P2.  Three real products per complex multiply-add instead of
+// the four of the expanded real form.  BM = 32·WM complex rows, BN = 32·WN complex columns,
+// BK3 complex k per LDS stage; LDS holds the real and imaginary planes only, the sums are
+// formed in registers after the LDS reads (a third less LDS traffic than staging them).
 constexpr int BK3 = 16;
 
 template <int BM, int BN>
 struct Lds3 {
     static constexpr int PAD = BK3 + 1;
-    double ar[BM * PAD], ai[BM * PAD], as[BM * PAD];
-    double br[BN * PAD], bi[BN * PAD], bs[BN * PAD];
+    double ar[BM * PAD], ai[BM * PAD];
+    double br[BN * PAD], bi[BN * PAD];
 };
 
 template <int WM, int WN>
@@ -293,7 +294,6 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
     const double* __restrict__ A = g.A;
     const double* __restrict__ Br = reinterpret_cast<const double*>(g.Bt0);
     const double* __restrict__ Bi = reinterpret_cast<const double*>(g.Bt1);
-    const double* __restrict__ Bs = reinterpret_cast<const double*>(g.Bt2);
     const long long lda = g.lda, ldb = g.ldb;
 
     d4 p1[WM][WN], p2[WM][WN], p3[WM][WN];
@@ -306,7 +306,7 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
     // BN × BK3 doubles each, loaded as double2 pairs along k (8·BN pairs, BN/32 per thread)
     constexpr int PA = BM / 16, PB = BN / 32;
     double2 ra[PA];
-    double2 rbr[PB], rbi[PB], rbs[PB];
+    double2 rbr[PB], rbi[PB];
     auto load_tiles = [&](int k0) {
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
@@ -324,7 +324,6 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
             const long long off = (long long)gn * ldb + gk;
             rbr[p] = ok ? *reinterpret_cast<const double2*>(Br + off) : make_double2(0.0, 0.0);
             rbi[p] = ok ? *reinterpret_cast<const double2*>(Bi + off) : make_double2(0.0, 0.0);
-            rbs[p] = ok ? *reinterpret_cast<const double2*>(Bs + off) : make_double2(0.0, 0.0);
         }
     };
     auto store_tiles = [&]() {
@@ -333,7 +332,6 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
             const int idx = p * 256 + tid, row = idx >> 4, k = idx & 15;
             sm.ar[row * PAD + k] = ra[p].x;
             sm.ai[row * PAD + k] = ra[p].y;
-            sm.as[row * PAD + k] = ra[p].x + ra[p].y;
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
@@ -342,8 +340,6 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
             sm.br[row * PAD + k + 1] = rbr[p].y;
             sm.bi[row * PAD + k] = rbi[p].x;
             sm.bi[row * PAD + k + 1] = rbi[p].y;
-            sm.bs[row * PAD + k] = rbs[p].x;
-            sm.bs[row * PAD + k + 1] = rbs[p].y;
         }
     };
 
@@ -362,14 +358,14 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
                 const int r = (wm * (16 * WM) + i * 16 + l16) * PAD + kk + lq;
                 xr[i] = sm.ar[r];
                 xi[i] = sm.ai[r];
-                xs[i] = sm.as[r];
+                xs[i] = xr[i] + xi[i];
             }
 #pragma unroll
             for (int j = 0; j < WN; ++j) {
                 const int c = (wn * (16 * WN) + j * 16 + l16) * PAD + kk + lq;
                 yr[j] = sm.br[c];
                 yi[j] = sm.bi[c];
-                ys[j] = sm.bs[c];
+                ys[j] = yr[j] + yi[j];
             }
 #pragma unroll
             for (int i = 0; i < WM; ++i)
@@ -538,106 +534,168 @@ __global__ __launch_bounds__(64) void k_tri(double2* __restrict__ X, TriFactors 
 
 // Segmented pivoted tridiagonal solve (same arithmetic as k_tri, in parallel over row
 // segments).  Thread (k, system) owns rows [k·L, k·L+L) (L <= SEGL) of one system and
-// keeps them in registers.  Forward: run the segment with a zero entering value (segment 0 starts from
-// b_0), exchange the end values through LDS, form the exact entering value from the
-// previous segments with the forward propagators, rerun and keep y_i/u_ii.  Backward: the
-// same with the 2-vector state (x_{i}, x_{i+1}) and the 2x2 propagators, from the last
-// segment upwards.  Data is read once and written once.
+// keeps them in registers.  Forward: run the segment with a zero entering value (segment 0
+// starts from b_0); a log2(K)-round scan in LDS over the segments' affine maps (forward
+// propagator, local end value) gives every segment its exact entering value; rerun and
+// keep y_i/u_ii.  Backward: the same with the 2-vector state (x_{i}, x_{i+1}) and the 2x2
+// propagators, as a suffix scan.  Data is read once and written once.
+// Componentwise select (a ternary on the vector struct can end up as a select of
+// addresses of stack copies).
+__device__ __forceinline__ double2 csel(bool c, double2 a, double2 b) {
+    return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
 __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {   // a*b + c
     return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+
+// LDS of the segment joins: ping-pong buffers of one scan round (the forward scan uses
+// the first two planes, the backward one all six).
+struct TriLds {
+    double2 p[2][6][256];
+};
+
+// Block → (systems, right-hand side).  With at least SYS systems per right-hand side a
+// block takes SYS consecutive systems a of one right-hand side q, and consecutive blocks
+// step through q first: the blocks that share a set of factor rows run together and
+// find them in L2.  Otherwise (one system, 1D) a block takes SYS consecutive (a, q).
+__host__ __device__ inline long long tri_blocks(int na, int nq, int K) {
+    const int SYS = 256 / K;
+    if (na >= SYS) return (long long)((na + SYS - 1) / SYS) * nq;
+    return ((long long)na * nq + SYS - 1) / SYS;
 }
 
 template <int SEGL>
 __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const TriFactors& f, int len, int na,
                                               int nq, long long se, long long sa, long long sq, int fa, int blk,
-                                              double2 (&tf_)[256], double2 (&tb_)[256][2]) {
+                                              TriLds& sm) {
     const int K = f.K, L = f.L, SYS = 256 / K;
     const int tid = threadIdx.x, k = tid / SYS, sl = tid - k * SYS;
-    const long long sysg = (long long)blk * SYS + sl;
-    const bool valid = sysg < (long long)na * nq;
-    const int a = valid ? (int)(sysg % na) : 0, q = valid ? (int)(sysg / na) : 0;
+    int a, q;
+    bool valid;
+    if (na >= SYS) {
+        q = blk % nq;
+        a = (blk / nq) * SYS + sl;
+        valid = a < na;
+    } else {
+        const long long sysg = (long long)blk * SYS + sl;
+        valid = sysg < (long long)na * nq;
+        a = (int)(sysg % na);
+        q = (int)(sysg / na);
+    }
+    if (!valid) a = q = 0;   // in-range reads; nothing is stored
     double2* x = X + (long long)q * sq + (long long)a * sa;
-    const int fs = f.nsys, fo = a * fa;
+    const int fs = f.nsys;
+    // factor row i of this system: ptr[i * fs]
+    const double2* __restrict__ dl = f.dl + a * fa;
+    const double2* __restrict__ dinv = f.dinv + a * fa;
+    const double2* __restrict__ u1p = f.u1p + a * fa;
+    const double2* __restrict__ u2p = f.u2p + a * fa;
     const int s0 = k * L, e0 = min(s0 + L, len);
+    const double2 zero = make_double2(0.0, 0.0);
+    const double2 ph = f.phi[(long long)k * fs + a * fa];
+    const uint32_t pm = f.pivm[(long long)k * fs + a * fa];
     double2 b[SEGL + 1];
 #pragma unroll
     for (int u = 0; u <= SEGL; ++u) {
         const int i = s0 + u;
-        b[u] = (valid && u <= L && i < len) ? x[(long long)i * se] : make_double2(0.0, 0.0);
+        b[u] = zero;
+        if (valid && u <= L && i < len) b[u] = x[(long long)i * se];
     }
-    // forward, local run
-    double2 cur = (k == 0) ? b[0] : make_double2(0.0, 0.0);
+    // forward, local run (segment 0 starts from b_0, the others from zero)
+    double2 cur = csel(k == 0, b[0], zero);
 #pragma unroll
     for (int u = 0; u < SEGL; ++u) {
         const int i = s0 + u;
         if (i < e0 && i <= len - 2) {
-            const double2 l = f.dl[(long long)i * fs + fo];
+            const double2 l = dl[(long long)i * fs];
             const double2 nb = b[u + 1];
-            cur = f.piv[(long long)i * fs + fo] ? csub(cur, cmul(l, nb)) : csub(nb, cmul(l, cur));
+            const bool pv = (pm >> u) & 1u;
+            cur = csub(csel(pv, cur, nb), cmul(l, csel(pv, nb, cur)));
         }
     }
-    tf_[tid] = cur;
-    __syncthreads();
-    double2 S = b[0];
-    if (k > 0) {
-        S = tf_[sl];
-        for (int j = 1; j < k; ++j) S = cfma(f.phi[(long long)j * fs + fo], S, tf_[j * SYS + sl]);
+    // inclusive scan over the segments of the affine maps c -> φ_k c + t_k (segment 0's
+    // map is constant): afterwards T is the exact value leaving segment k
+    double2 P = csel(k == 0, zero, ph), T = cur;
+    int buf = 0;
+    for (int d = 1; d < K; d <<= 1, buf ^= 1) {
+        sm.p[buf][0][tid] = P;
+        sm.p[buf][1][tid] = T;
+        __syncthreads();
+        if (k >= d) {
+            const double2 Pp = sm.p[buf][0][tid - d * SYS], Tp = sm.p[buf][1][tid - d * SYS];
+            T = cfma(P, Tp, T);
+            P = cmul(P, Pp);
+        }
     }
-    cur = S;
+    sm.p[buf][1][tid] = T;
+    __syncthreads();
+    cur = csel(k == 0, b[0], sm.p[buf][1][max(tid - SYS, 0)]);
+    buf ^= 1;
 #pragma unroll
     for (int u = 0; u < SEGL; ++u) {
         const int i = s0 + u;
         if (i < e0) {
-            const double2 di = f.dinv[(long long)i * fs + fo];
+            const double2 di = dinv[(long long)i * fs];
             if (i <= len - 2) {
-                const double2 l = f.dl[(long long)i * fs + fo];
+                const double2 l = dl[(long long)i * fs];
+                const bool pv = (pm >> u) & 1u;
                 const double2 nb = b[u + 1];
-                double2 out, nxt;
-                if (f.piv[(long long)i * fs + fo]) {
-                    out = nb;
-                    nxt = csub(cur, cmul(l, nb));
-                } else {
-                    out = cur;
-                    nxt = csub(nb, cmul(l, cur));
-                }
-                b[u] = cmul(out, di);
-                cur = nxt;
+                b[u] = cmul(csel(pv, nb, cur), di);
+                cur = csub(csel(pv, cur, nb), cmul(l, csel(pv, nb, cur)));
             } else {
                 b[u] = cmul(cur, di);
             }
         }
     }
     // backward, local run with a zero entering state
-    double2 x1 = make_double2(0.0, 0.0), x2 = make_double2(0.0, 0.0);
+    const double2* ps = f.psi + ((long long)k * fs + a * fa) * 4;
+    double2 M00 = ps[0], M01 = ps[1], M10 = ps[2], M11 = ps[3];
+    double2 x1 = zero, x2 = zero;
 #pragma unroll
     for (int u = SEGL - 1; u >= 0; --u) {
         const int i = s0 + u;
         if (i < e0) {
-            const double2 xi = csub(csub(b[u], cmul(f.u1p[(long long)i * fs + fo], x1)),
-                                    cmul(f.u2p[(long long)i * fs + fo], x2));
+            const long long r = (long long)i * fs;
+            const double2 xi = csub(csub(b[u], cmul(u1p[r], x1)), cmul(u2p[r], x2));
             x2 = x1;
             x1 = xi;
         }
     }
-    tb_[tid][0] = x1;
-    tb_[tid][1] = x2;
-    __syncthreads();
-    double2 E0 = make_double2(0.0, 0.0), E1 = make_double2(0.0, 0.0);
-    for (int j = K - 1; j > k; --j) {
-        const double2* ps = f.psi + ((long long)j * fs + fo) * 4;
-        const double2 n0 = cfma(ps[0], E0, cfma(ps[1], E1, tb_[j * SYS + sl][0]));
-        const double2 n1 = cfma(ps[2], E0, cfma(ps[3], E1, tb_[j * SYS + sl][1]));
-        E0 = n0;
-        E1 = n1;
+    // suffix scan of the affine maps G -> Ψ_k G + g_k (the last segment's map is
+    // constant): afterwards (V0, V1) is the exact state at the start of segment k
+    if (k == K - 1) M00 = M01 = M10 = M11 = zero;
+    double2 V0 = x1, V1 = x2;
+    for (int d = 1; d < K; d <<= 1, buf ^= 1) {
+        sm.p[buf][0][tid] = M00;
+        sm.p[buf][1][tid] = M01;
+        sm.p[buf][2][tid] = M10;
+        sm.p[buf][3][tid] = M11;
+        sm.p[buf][4][tid] = V0;
+        sm.p[buf][5][tid] = V1;
+        __syncthreads();
+        if (k + d < K) {
+            const int o = tid + d * SYS;
+            const double2 N00 = sm.p[buf][0][o], N01 = sm.p[buf][1][o], N10 = sm.p[buf][2][o],
+                          N11 = sm.p[buf][3][o], W0 = sm.p[buf][4][o], W1 = sm.p[buf][5][o];
+            V0 = cfma(M00, W0, cfma(M01, W1, V0));
+            V1 = cfma(M10, W0, cfma(M11, W1, V1));
+            const double2 R00 = cfma(M00, N00, cmul(M01, N10)), R01 = cfma(M00, N01, cmul(M01, N11));
+            const double2 R10 = cfma(M10, N00, cmul(M11, N10)), R11 = cfma(M10, N01, cmul(M11, N11));
+            M00 = R00; M01 = R01; M10 = R10; M11 = R11;
+        }
     }
-    x1 = E0;
-    x2 = E1;
+    sm.p[buf][4][tid] = V0;
+    sm.p[buf][5][tid] = V1;
+    __syncthreads();
+    const int nxt_seg = min(tid + SYS, 255);
+    x1 = csel(k == K - 1, zero, sm.p[buf][4][nxt_seg]);
+    x2 = csel(k == K - 1, zero, sm.p[buf][5][nxt_seg]);
 #pragma unroll
     for (int u = SEGL - 1; u >= 0; --u) {
         const int i = s0 + u;
         if (i < e0) {
-            const double2 xi = csub(csub(b[u], cmul(f.u1p[(long long)i * fs + fo], x1)),
-                                    cmul(f.u2p[(long long)i * fs + fo], x2));
+            const long long r = (long long)i * fs;
+            const double2 xi = csub(csub(b[u], cmul(u1p[r], x1)), cmul(u2p[r], x2));
             if (valid) x[(long long)i * se] = xi;
             x2 = x1;
             x1 = xi;
@@ -645,24 +703,28 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     }
 }
 
+// One block of 256 threads per SYS systems; the XCD remap keeps consecutive virtual blocks
+// (the right-hand sides of one set of systems) on one XCD.
 template <int SEGL>
 __global__ __launch_bounds__(256) void k_tri_seg(double2* __restrict__ X, TriFactors f, int len, int na, int nq,
-                                                 long long se, long long sa, long long sq, int fa) {
-    __shared__ double2 tf_[256];
-    __shared__ double2 tb_[256][2];
-    tri_seg_block<SEGL>(X, f, len, na, nq, se, sa, sq, fa, blockIdx.x, tf_, tb_);
+                                                 long long se, long long sa, long long sq, int fa, int total) {
+    __shared__ TriLds sm;
+    const int per = gridDim.x / 8;
+    const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (v >= total) return;
+    tri_seg_block<SEGL>(X, f, len, na, nq, se, sa, sq, fa, v, sm);
 }
 
 template <int SEGL>
 __global__ __launch_bounds__(256) void k_tri_seg_grouped(const TriTask* __restrict__ tasks,
                                                          const int* __restrict__ start, int ntask, int total) {
-    __shared__ double2 tf_[256];
-    __shared__ double2 tb_[256][2];
-    const int v = blockIdx.x;
+    __shared__ TriLds sm;
+    const int per = gridDim.x / 8;
+    const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (v >= total) return;
     const int t = find_task(start, ntask, v);
     const TriTask& g = tasks[t];
-    tri_seg_block<SEGL>(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], tf_, tb_);
+    tri_seg_block<SEGL>(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], sm);
 }
 
 static inline uint16_t host_bf16(float f) {
@@ -696,16 +758,15 @@ static void expand_bt(int N, const std::vector<cplx>& B /* [k][n] */, std::vecto
 }
 
 // 3M planes of the complex N×N matrix B[k][n]: n-major [n][k] rows of ld doubles (zero
-// padded), Re, Im and Re+Im one after the other.
+// padded), Re and Im one after the other.
 static int upload_planes(DenseB& d, int N, const std::vector<cplx>& B, int ld) {
     const size_t plane = (size_t)N * ld;
-    std::vector<double> h(3 * plane, 0.0);
+    std::vector<double> h(2 * plane, 0.0);
     for (int k = 0; k < N; ++k)
         for (int n = 0; n < N; ++n) {
             const cplx b = B[(size_t)k * N + n];
             h[(size_t)n * ld + k] = b.real();
             h[plane + (size_t)n * ld + k] = b.imag();
-            h[2 * plane + (size_t)n * ld + k] = b.real() + b.imag();
         }
     SG_HIP(hipMalloc(&d.p3, h.size() * sizeof(double)));
     SG_HIP(hipMemcpy(d.p3, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -762,22 +823,21 @@ void gemm_tiles(int cfg, int M, int Nc, int* tiles_m, int* tiles_n) {
     *tiles_n = (cols + bn - 1) / bn;
 }
 
-GemmTask make_gemm_task(int precision, const double* A, const DenseB& B, int N, double* C, int M, int cfg) {
+GemmTask make_gemm_task(int precision, const double* A, long long lda, const DenseB& B, int N, double* C,
+                        long long ldc, int M, int cfg) {
     GemmTask g{};
     g.A = A;
     g.C = C;
     g.Bt0 = precision == SG_PREC_F64 ? (const void*)B.f64
           : precision == SG_PREC_F32 ? (const void*)B.f32 : (const void*)B.bf_hi;
     g.Bt1 = precision == SG_PREC_BF16X3 ? (const void*)B.bf_lo : nullptr;
-    g.Bt2 = nullptr;
     if (gemm_cfg_3m(cfg)) {   // 3M planes, FP64
         const size_t plane = (size_t)N * bexp_ld(N);
         g.Bt0 = B.p3;
         g.Bt1 = B.p3 + plane;
-        g.Bt2 = B.p3 + 2 * plane;
     }
-    g.lda = 2LL * N;
-    g.ldc = 2LL * N;
+    g.lda = 2 * lda;
+    g.ldc = 2 * ldc;
     g.ldb = bexp_ld(N);
     g.M = M;
     g.Nc = 2 * N;
@@ -851,11 +911,12 @@ static int dispatch_gemm(int precision, int cfg, const GemmTask& g, const GemmTa
     return SG_OK;
 }
 
-static int launch_gemm(int precision, const double* A, const DenseB& B, int N, double* C, int M, hipStream_t st) {
+static int launch_gemm(int precision, const double* A, long long lda, const DenseB& B, int N, double* C,
+                       long long ldc, int M, hipStream_t st) {
     // tile shape from the autotuner table when this (n, Q, precision) was tuned
     int cfg = tune_get(N, M / N, precision);
     if (!gemm_cfg_valid(cfg, precision)) cfg = 0;
-    const GemmTask g = make_gemm_task(precision, A, B, N, C, M, cfg);
+    const GemmTask g = make_gemm_task(precision, A, lda, B, N, C, ldc, M, cfg);
     // algorithmic flops: 8 real flops per complex multiply-add, 6 with the 3M form
     const double cmacs = (double)M * N * N;
     KScope ks(SG_K_GEMM, (gemm_cfg_3m(cfg) ? 6.0 : 8.0) * cmacs, st);
@@ -869,19 +930,17 @@ int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const i
     return dispatch_gemm(precision, cfg, GemmTask{}, d_tasks, d_start, ntask, total, st);
 }
 
-TriTask make_tri_task(const TriFactors& f, double2* X, int n, int Q, int dim) {
+TriTask make_tri_task(const TriFactors& f, double2* X, int n, int ld, int Q, int dim) {
     TriTask t{};
     t.X = X;
     t.f = f;
     t.len = n;
     if (dim == 2) {
-        t.na = n; t.nq = Q; t.se = n; t.sa = 1; t.sq = (long long)n * n; t.fa = 1;
+        t.na = n; t.nq = Q; t.se = ld; t.sa = 1; t.sq = (long long)n * ld; t.fa = 1;
     } else {
         t.na = 1; t.nq = Q; t.se = 1; t.sa = 0; t.sq = n; t.fa = 0;
     }
-    const long long nth = (long long)t.na * t.nq;
-    const int sys = f.K >= 1 ? 256 / f.K : 256;
-    t.nblocks = (int)((nth + sys - 1) / sys);
+    t.nblocks = (int)tri_blocks(t.na, t.nq, f.K >= 1 ? f.K : 1);
     return t;
 }
 
@@ -890,17 +949,18 @@ int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, in
     if (ntask <= 0 || total <= 0) return SG_OK;
     if (max_seg > 32) return fail(SG_EINVAL, "grid too large for the grouped tridiagonal sweep");
     KScope ks(SG_K_TRI, bytes, st);
-    if (max_seg <= 16) hipLaunchKernelGGL(k_tri_seg_grouped<16>, dim3(total), dim3(256), 0, st, d_tasks, d_start, ntask, total);
-    else hipLaunchKernelGGL(k_tri_seg_grouped<32>, dim3(total), dim3(256), 0, st, d_tasks, d_start, ntask, total);
+    const dim3 grid((unsigned)((total + 7) / 8 * 8));
+    if (max_seg <= 16) hipLaunchKernelGGL(k_tri_seg_grouped<16>, grid, dim3(256), 0, st, d_tasks, d_start, ntask, total);
+    else hipLaunchKernelGGL(k_tri_seg_grouped<32>, grid, dim3(256), 0, st, d_tasks, d_start, ntask, total);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
 
-static int launch_tri(const TriFactors& f, double2* X, int n, int Q, int dim, hipStream_t st) {
+static int launch_tri(const TriFactors& f, double2* X, int n, int ld, int Q, int dim, hipStream_t st) {
     int na, nq, fa;
     long long se, sa, sq;
     if (dim == 2) {
-        na = n; nq = Q; se = n; sa = 1; sq = (long long)n * n; fa = 1;
+        na = n; nq = Q; se = ld; sa = 1; sq = (long long)n * ld; fa = 1;
     } else {
         na = 1; nq = Q; se = 1; sa = 0; sq = n; fa = 0;
     }
@@ -909,10 +969,13 @@ static int launch_tri(const TriFactors& f, double2* X, int n, int Q, int dim, hi
     // algorithmic: every element read and written once, factors read once
     KScope ks(SG_K_TRI, 32.0 * na * (double)nq * n + 65.0 * f.nsys * (double)n, st);
     if (f.L <= 32 && f.K >= 1) {
-        const int SYS = 256 / f.K;
-        const dim3 grid((unsigned)((nth + SYS - 1) / SYS));
-        if (f.L <= 16) hipLaunchKernelGGL(k_tri_seg<16>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa);
-        else hipLaunchKernelGGL(k_tri_seg<32>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa);
+        const long long total = tri_blocks(na, nq, f.K);
+        if (total > INT32_MAX - 8) return fail(SG_EINVAL, "grid too large for the tridiagonal sweep");
+        const dim3 grid((unsigned)((total + 7) / 8 * 8));
+        if (f.L <= 16)
+            hipLaunchKernelGGL(k_tri_seg<16>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total);
+        else
+            hipLaunchKernelGGL(k_tri_seg<32>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total);
         SG_HIP(hipGetLastError());
         return SG_OK;
     }
@@ -933,15 +996,17 @@ int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, 
     const int n = c->n;
     if (c->dim == 1) {
         if (r != z) SG_HIP(hipMemcpyAsync(z, r, (size_t)c->nvec * sizeof(double2), hipMemcpyDeviceToDevice, st));
-        return launch_tri(f, z, n, c->Q, 1, st);
+        return launch_tri(f, z, n, n, c->Q, 1, st);
     }
     const int M = c->Q * n;
     double2* t = c->d_tmp_pc;
-    int rc = launch_gemm(precision, reinterpret_cast<const double*>(r), c->fwd, n, reinterpret_cast<double*>(t), M, st);
+    int rc = launch_gemm(precision, reinterpret_cast<const double*>(r), n, c->fwd, n, reinterpret_cast<double*>(t),
+                         c->tld, M, st);
     if (rc) return rc;
-    rc = launch_tri(f, t, n, c->Q, 2, st);
+    rc = launch_tri(f, t, n, c->tld, c->Q, 2, st);
     if (rc) return rc;
-    return launch_gemm(precision, reinterpret_cast<const double*>(t), c->inv, n, reinterpret_cast<double*>(z), M, st);
+    return launch_gemm(precision, reinterpret_cast<const double*>(t), c->tld, c->inv, n, reinterpret_cast<double*>(z),
+                       n, M, st);
 }
 
 }  // namespace sgi

@@ -345,6 +345,7 @@ static int build_tri(int n, double h, double kbar, const std::vector<cplx>& sig,
     tf.L = L;
     std::vector<double2> hu1p((size_t)n * nsys, make_double2(0, 0)), hu2p((size_t)n * nsys, make_double2(0, 0));
     std::vector<double2> hphi((size_t)K * nsys), hpsi((size_t)K * nsys * 4);
+    std::vector<uint32_t> hpm((size_t)K * nsys, 0u);
     for (int a = 0; a < nsys; ++a) {
         auto C = [&](const std::vector<double2>& v, size_t idx) { return cplx(v[idx].x, v[idx].y); };
         for (int i = 0; i < n; ++i) {
@@ -364,6 +365,10 @@ static int build_tri(int n, double h, double kbar, const std::vector<cplx>& sig,
             for (int i = s0; i < e0 && i <= n - 2; ++i)
                 ph *= hp[(size_t)i * nsys + a] ? cplx(1.0) : -C(hdl, (size_t)i * nsys + a);
             hphi[(size_t)k * nsys + a] = make_double2(ph.real(), ph.imag());
+            uint32_t bits = 0;
+            for (int i = s0; i < e0 && i <= n - 2; ++i)
+                if (hp[(size_t)i * nsys + a]) bits |= 1u << (i - s0);
+            hpm[(size_t)k * nsys + a] = bits;
             cplx m00 = 1.0, m01 = 0.0, m10 = 0.0, m11 = 1.0;   // product M_s ... M_{e-1}
             for (int i = e0 - 1; i >= s0; --i) {
                 const cplx u1 = C(hu1p, (size_t)i * nsys + a), u2 = C(hu2p, (size_t)i * nsys + a);
@@ -387,6 +392,8 @@ static int build_tri(int n, double h, double kbar, const std::vector<cplx>& sig,
     SG_HIP(hipMemcpy(tf.u2p, hu2p.data(), hu2p.size() * sizeof(double2), hipMemcpyHostToDevice));
     SG_HIP(hipMemcpy(tf.phi, hphi.data(), hphi.size() * sizeof(double2), hipMemcpyHostToDevice));
     SG_HIP(hipMemcpy(tf.psi, hpsi.data(), hpsi.size() * sizeof(double2), hipMemcpyHostToDevice));
+    SG_HIP(hipMalloc(&tf.pivm, hpm.size() * sizeof(uint32_t)));
+    SG_HIP(hipMemcpy(tf.pivm, hpm.data(), hpm.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     SG_HIP(hipMalloc(&tf.dl, hdl.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.dinv, hdi.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.du1, hu1.size() * sizeof(double2)));
@@ -410,6 +417,7 @@ static void free_tri(TriFactors& t) {
     (void)hipFree(t.u2p);
     (void)hipFree(t.phi);
     (void)hipFree(t.psi);
+    (void)hipFree(t.pivm);
     t = TriFactors{};
 }
 
@@ -582,7 +590,10 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
         rc = upload_dense_b(c.get(), stream);
         if (rc) return rc;
     }
-    SG_HIP(hipMalloc(&c->d_tmp_pc, (size_t)c->nvec * sizeof(double2)));
+    // rows of the intermediate start on 128-byte boundaries, so that the sweep's and the
+    // transforms' row pieces are whole cache lines
+    c->tld = c->dim == 2 ? (n + 7) / 8 * 8 : n;
+    SG_HIP(hipMalloc(&c->d_tmp_pc, (c->dim == 2 ? (size_t)c->Q * n * c->tld : (size_t)c->nvec) * sizeof(double2)));
     SG_HIP(hipDeviceSynchronize());
     c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = c.release();

@@ -53,6 +53,7 @@ struct TriFactors {
     double2* u2p = nullptr;   // u_{i,i+2} / u_ii
     double2* phi = nullptr;   // forward propagator of segment k: [k][sys]
     double2* psi = nullptr;   // backward 2x2 propagator of segment k: [k][sys][4]
+    uint32_t* pivm = nullptr; // row-exchange flags of segment k as bits u = i - k·L: [k][sys]
 };
 
 // Expanded real form of a complex N×N matrix for the GEMM C = A·B, where A rows are
@@ -62,7 +63,7 @@ struct DenseB {
     float* f32 = nullptr;      // [2N][2N]
     uint16_t* bf_hi = nullptr; // [2N][2N] bf16 bits, packed for the MFMA B operand
     uint16_t* bf_lo = nullptr;
-    double* p3 = nullptr;      // 3M planes of B (n-major [n][k], ld = bexp_ld(N)): Re, Im, Re+Im
+    double* p3 = nullptr;      // 3M planes of B (n-major [n][k], ld = bexp_ld(N)): Re, Im
 };
 
 // One dense problem C[M][Nc] = A[M][Kc] · B of the preconditioner transforms, Bt[Nc][Kc]
@@ -71,7 +72,6 @@ struct GemmTask {
     const double* A;
     const void* Bt0;
     const void* Bt1;
-    const void* Bt2;
     double* C;
     long long lda, ldb, ldc;
     int M, Nc, Kc, tiles_m, tiles_n;
@@ -197,7 +197,8 @@ struct Ctx {
     Workspace ws;
     Prof prof;
     bool use_spec_apply = true;        // compile-time-specialised operator when available
-    double2* d_tmp_pc = nullptr;       // preconditioner intermediate (nvec complex)
+    double2* d_tmp_pc = nullptr;       // preconditioner intermediate: Q·n rows of tld complex (2D)
+    int tld = 0;                       // its row length, n rounded up to 8 (128-byte aligned rows)
     Net* net = nullptr;                // attached correction network (not owned)
     double t_setup_ms = 0;
 
@@ -218,10 +219,13 @@ void tune_set(int n, int Q, int precision, int cfg);
 int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, hipStream_t st);
 int upload_dense_b(Ctx* c, hipStream_t st);
 void gemm_tiles(int cfg, int M, int Nc, int* tiles_m, int* tiles_n);
-GemmTask make_gemm_task(int precision, const double* A, const DenseB& B, int N, double* C, int M, int cfg);
+// lda, ldc: row lengths of A and C in complex elements
+GemmTask make_gemm_task(int precision, const double* A, long long lda, const DenseB& B, int N, double* C,
+                        long long ldc, int M, int cfg);
 int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const int* d_start, int ntask, int total,
                         double flops, hipStream_t st);
-TriTask make_tri_task(const TriFactors& f, double2* X, int n, int Q, int dim);
+// ld: row length of X in complex elements (2D; the 1D layout is contiguous)
+TriTask make_tri_task(const TriFactors& f, double2* X, int n, int ld, int Q, int dim);
 int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, int max_seg, double bytes,
                        hipStream_t st);
 

@@ -71,6 +71,8 @@ SMALL = {
     "2d_n3_min": lambda: small_2d(n=3, kbar=2.0, sigma=0.2, s=1, degree=1),
     "2d_n66_s1_r0": lambda: small_2d(n=66, kbar=9.0, sigma=0.9, s=1, degree=0),
     "2d_n41_s5_r2": lambda: small_2d(n=41, kbar=6.0, sigma=0.6, s=5, degree=2),   # generic kernel
+    # 32 sweep segments of 10 rows: the last two segments are empty
+    "2d_n300_s1_r1": lambda: small_2d(n=300, kbar=16.0, sigma=0.8, s=1, degree=1),
 }
 
 
@@ -125,7 +127,7 @@ def test_apply_parity_full_size_sampled(which):
     assert np.max(np.abs(y[:, pts] - ref)) <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("key", ["c1_1d", "2d_n150_s3_r3", "2d_n37_s2_r4", "2d_n3_min"])
+@pytest.mark.parametrize("key", ["c1_1d", "2d_n150_s3_r3", "2d_n37_s2_r4", "2d_n3_min", "2d_n300_s1_r1"])
 @pytest.mark.parametrize("pc", ["mean", "csl"])
 def test_precond_parity_f64(key, pc):
     inst = SMALL[key]()
