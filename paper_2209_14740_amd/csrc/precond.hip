@@ -302,22 +302,22 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
 #pragma unroll
         for (int j = 0; j < WN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = d4{0, 0, 0, 0};
 
-    // staging: A tile BM × BK3 complex = 16·BM double2 (BM/16 per thread); B planes
-    // BN × BK3 doubles each, loaded as double2 pairs along k (8·BN pairs, BN/32 per thread)
-    constexpr int PA = BM / 16, PB = BN / 32;
+    // staging: A tile BM × BK3 complex (BM·BK3/256 double2 per thread); B planes BN × BK3
+    // doubles each, loaded as double2 pairs along k (BN·BK3/512 pairs per thread)
+    constexpr int PA = BM * BK3 / 256, PB = BN * BK3 / 512, HK = BK3 / 2;
     double2 ra[PA];
     double2 rbr[PB], rbi[PB];
     auto load_tiles = [&](int k0) {
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
-            const int idx = p * 256 + tid, row = idx >> 4, k = idx & 15;
+            const int idx = p * 256 + tid, row = idx / BK3, k = idx % BK3;
             const int gm = m0 + row, gk = k0 + k;
             ra[p] = (gm < M && gk < K) ? *reinterpret_cast<const double2*>(A + (long long)gm * lda + 2 * gk)
                                        : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
-            const int idx = p * 256 + tid, row = idx >> 3, k = (idx & 7) * 2;
+            const int idx = p * 256 + tid, row = idx / HK, k = (idx % HK) * 2;
             const int gn = n0 + row, gk = k0 + k;
             // K is padded to an even ld with zero columns: a pair is inside or fully zero
             const bool ok = gn < N && gk < K;
@@ -329,13 +329,13 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
     auto store_tiles = [&]() {
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
-            const int idx = p * 256 + tid, row = idx >> 4, k = idx & 15;
+            const int idx = p * 256 + tid, row = idx / BK3, k = idx % BK3;
             sm.ar[row * PAD + k] = ra[p].x;
             sm.ai[row * PAD + k] = ra[p].y;
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
-            const int idx = p * 256 + tid, row = idx >> 3, k = (idx & 7) * 2;
+            const int idx = p * 256 + tid, row = idx / HK, k = (idx % HK) * 2;
             sm.br[row * PAD + k] = rbr[p].x;
             sm.br[row * PAD + k + 1] = rbr[p].y;
             sm.bi[row * PAD + k] = rbi[p].x;
@@ -548,10 +548,10 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {   // 
     return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
 
-// LDS of the segment joins: ping-pong buffers of one scan round (the forward scan uses
-// the first two planes, the backward one all six).
+// LDS of the segment joins, one scan round at a time (the forward scan uses the first two
+// planes, the backward one all six).
 struct TriLds {
-    double2 p[2][6][256];
+    double2 p[6][256];
 };
 
 // Block → (systems, right-hand side).  With at least SYS systems per right-hand side a
@@ -616,21 +616,20 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     // inclusive scan over the segments of the affine maps c -> φ_k c + t_k (segment 0's
     // map is constant): afterwards T is the exact value leaving segment k
     double2 P = csel(k == 0, zero, ph), T = cur;
-    int buf = 0;
-    for (int d = 1; d < K; d <<= 1, buf ^= 1) {
-        sm.p[buf][0][tid] = P;
-        sm.p[buf][1][tid] = T;
+    for (int d = 1; d < K; d <<= 1) {
+        sm.p[0][tid] = P;
+        sm.p[1][tid] = T;
         __syncthreads();
         if (k >= d) {
-            const double2 Pp = sm.p[buf][0][tid - d * SYS], Tp = sm.p[buf][1][tid - d * SYS];
+            const double2 Pp = sm.p[0][tid - d * SYS], Tp = sm.p[1][tid - d * SYS];
             T = cfma(P, Tp, T);
             P = cmul(P, Pp);
         }
+        __syncthreads();
     }
-    sm.p[buf][1][tid] = T;
+    sm.p[1][tid] = T;
     __syncthreads();
-    cur = csel(k == 0, b[0], sm.p[buf][1][max(tid - SYS, 0)]);
-    buf ^= 1;
+    cur = csel(k == 0, b[0], sm.p[1][max(tid - SYS, 0)]);
 #pragma unroll
     for (int u = 0; u < SEGL; ++u) {
         const int i = s0 + u;
@@ -665,31 +664,33 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     // constant): afterwards (V0, V1) is the exact state at the start of segment k
     if (k == K - 1) M00 = M01 = M10 = M11 = zero;
     double2 V0 = x1, V1 = x2;
-    for (int d = 1; d < K; d <<= 1, buf ^= 1) {
-        sm.p[buf][0][tid] = M00;
-        sm.p[buf][1][tid] = M01;
-        sm.p[buf][2][tid] = M10;
-        sm.p[buf][3][tid] = M11;
-        sm.p[buf][4][tid] = V0;
-        sm.p[buf][5][tid] = V1;
+    __syncthreads();   // every thread has read the forward entering values
+    for (int d = 1; d < K; d <<= 1) {
+        sm.p[0][tid] = M00;
+        sm.p[1][tid] = M01;
+        sm.p[2][tid] = M10;
+        sm.p[3][tid] = M11;
+        sm.p[4][tid] = V0;
+        sm.p[5][tid] = V1;
         __syncthreads();
         if (k + d < K) {
             const int o = tid + d * SYS;
-            const double2 N00 = sm.p[buf][0][o], N01 = sm.p[buf][1][o], N10 = sm.p[buf][2][o],
-                          N11 = sm.p[buf][3][o], W0 = sm.p[buf][4][o], W1 = sm.p[buf][5][o];
+            const double2 N00 = sm.p[0][o], N01 = sm.p[1][o], N10 = sm.p[2][o],
+                          N11 = sm.p[3][o], W0 = sm.p[4][o], W1 = sm.p[5][o];
             V0 = cfma(M00, W0, cfma(M01, W1, V0));
             V1 = cfma(M10, W0, cfma(M11, W1, V1));
             const double2 R00 = cfma(M00, N00, cmul(M01, N10)), R01 = cfma(M00, N01, cmul(M01, N11));
             const double2 R10 = cfma(M10, N00, cmul(M11, N10)), R11 = cfma(M10, N01, cmul(M11, N11));
             M00 = R00; M01 = R01; M10 = R10; M11 = R11;
         }
+        __syncthreads();
     }
-    sm.p[buf][4][tid] = V0;
-    sm.p[buf][5][tid] = V1;
+    sm.p[4][tid] = V0;
+    sm.p[5][tid] = V1;
     __syncthreads();
     const int nxt_seg = min(tid + SYS, 255);
-    x1 = csel(k == K - 1, zero, sm.p[buf][4][nxt_seg]);
-    x2 = csel(k == K - 1, zero, sm.p[buf][5][nxt_seg]);
+    x1 = csel(k == K - 1, zero, sm.p[4][nxt_seg]);
+    x2 = csel(k == K - 1, zero, sm.p[5][nxt_seg]);
 #pragma unroll
     for (int u = SEGL - 1; u >= 0; --u) {
         const int i = s0 + u;
@@ -950,7 +951,8 @@ int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, in
     if (max_seg > 32) return fail(SG_EINVAL, "grid too large for the grouped tridiagonal sweep");
     KScope ks(SG_K_TRI, bytes, st);
     const dim3 grid((unsigned)((total + 7) / 8 * 8));
-    if (max_seg <= 16) hipLaunchKernelGGL(k_tri_seg_grouped<16>, grid, dim3(256), 0, st, d_tasks, d_start, ntask, total);
+    if (max_seg <= 8) hipLaunchKernelGGL(k_tri_seg_grouped<8>, grid, dim3(256), 0, st, d_tasks, d_start, ntask, total);
+    else if (max_seg <= 16) hipLaunchKernelGGL(k_tri_seg_grouped<16>, grid, dim3(256), 0, st, d_tasks, d_start, ntask, total);
     else hipLaunchKernelGGL(k_tri_seg_grouped<32>, grid, dim3(256), 0, st, d_tasks, d_start, ntask, total);
     SG_HIP(hipGetLastError());
     return SG_OK;
@@ -972,7 +974,9 @@ static int launch_tri(const TriFactors& f, double2* X, int n, int ld, int Q, int
         const long long total = tri_blocks(na, nq, f.K);
         if (total > INT32_MAX - 8) return fail(SG_EINVAL, "grid too large for the tridiagonal sweep");
         const dim3 grid((unsigned)((total + 7) / 8 * 8));
-        if (f.L <= 16)
+        if (f.L <= 8)
+            hipLaunchKernelGGL(k_tri_seg<8>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total);
+        else if (f.L <= 16)
             hipLaunchKernelGGL(k_tri_seg<16>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total);
         else
             hipLaunchKernelGGL(k_tri_seg<32>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total);

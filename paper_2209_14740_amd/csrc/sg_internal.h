@@ -47,7 +47,7 @@ struct TriFactors {
     double2* du1 = nullptr;   // u_{i,i+1}
     double2* du2 = nullptr;   // u_{i,i+2}
     uint8_t* piv = nullptr;   // 1 if rows i and i+1 were swapped at step i
-    // segmented form (rows split into K segments of L rows, L <= 16 up to n = 512, see precond.hip)
+    // segmented form (rows split into K <= 32 segments of L <= 16 rows up to n = 512, see precond.hip)
     int K = 0, L = 0;
     double2* u1p = nullptr;   // u_{i,i+1} / u_ii   (len rows, zero past the end)
     double2* u2p = nullptr;   // u_{i,i+2} / u_ii

@@ -73,6 +73,8 @@ SMALL = {
     "2d_n41_s5_r2": lambda: small_2d(n=41, kbar=6.0, sigma=0.6, s=5, degree=2),   # generic kernel
     # 32 sweep segments of 10 rows: the last two segments are empty
     "2d_n300_s1_r1": lambda: small_2d(n=300, kbar=16.0, sigma=0.8, s=1, degree=1),
+    # n a multiple of 8: the preconditioner intermediate has no row padding
+    "2d_n48_s2_r2": lambda: small_2d(n=48, kbar=8.0, sigma=0.8, s=2, degree=2),
 }
 
 
@@ -127,7 +129,8 @@ def test_apply_parity_full_size_sampled(which):
     assert np.max(np.abs(y[:, pts] - ref)) <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("key", ["c1_1d", "2d_n150_s3_r3", "2d_n37_s2_r4", "2d_n3_min", "2d_n300_s1_r1"])
+@pytest.mark.parametrize("key", ["c1_1d", "2d_n150_s3_r3", "2d_n37_s2_r4", "2d_n3_min", "2d_n300_s1_r1",
+                                 "2d_n48_s2_r2"])
 @pytest.mark.parametrize("pc", ["mean", "csl"])
 def test_precond_parity_f64(key, pc):
     inst = SMALL[key]()
