@@ -96,7 +96,11 @@ typedef struct {
     int fallback;             /* 1 if the learned correction was switched off               */
     double relres_true;       /* final ||b-Ax||_2/||b||_2 recomputed in FP64                */
     double relres_est;        /* final Arnoldi estimate |g_{j+1}|/||b||                     */
-    double t_setup, t_precond, t_matvec, t_orth, t_total;   /* milliseconds              */
+    double t_setup;           /* milliseconds                                               */
+    double t_precond, t_matvec, t_orth;  /* GPU milliseconds per phase, measured only while
+                                 profiling of every kind is on (sg_set_profiling), else 0:
+                                 the events between the phases idle the GPU briefly    */
+    double t_total;           /* milliseconds                                               */
 } sg_solve_stats;
 
 /* Build the operator for one problem: basis, triple-product tables, coefficient

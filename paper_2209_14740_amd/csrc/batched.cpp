@@ -254,6 +254,12 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         double2* p;
         ~FreeH() { (void)hipHostFree(p); }
     } free_hcoef{h_coef};
+    hipEvent_t step_done = nullptr;   // the host polls it at the end of every lockstep step
+    SG_HIP(hipEventCreateWithFlags(&step_done, hipEventDisableTiming));
+    struct FreeE {
+        hipEvent_t e;
+        ~FreeE() { (void)hipEventDestroy(e); }
+    } free_ev{step_done};
     Staging stg;
 
     std::vector<int> active;
@@ -553,7 +559,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         if ((rc = launch_reduce_grouped(stg.dtasks(g_redn), stg.dstart(g_redn), g_redn.n(), g_redn.total(), 1, stream)))
             return rc;
         SG_HIP(hipMemcpyAsync(h_coef, d_coef, (size_t)S * CW * sizeof(double2), hipMemcpyDeviceToHost, stream));
-        SG_HIP(hipStreamSynchronize(stream));
+        if ((rc = wait_stream(stream, step_done))) return rc;
 
         // host part of every active instance
         std::vector<int> still;

@@ -23,7 +23,6 @@
 
 namespace sgi {
 
-int launch_reduce_norm(int nblocks, const double2* partial, double2* out, hipStream_t st);
 
 int ensure_workspace(Ctx* c, int m, bool flexible) {
     Workspace& w = c->ws;
@@ -35,6 +34,7 @@ int ensure_workspace(Ctx* c, int m, bool flexible) {
     (void)hipFree(w.coef);
     (void)hipFree(w.partial);
     if (w.host_pinned) (void)hipHostFree(w.host_pinned);
+    if (w.done) (void)hipEventDestroy(w.done);
     w = Workspace{};
     const size_t nv = (size_t)c->nvec;
     w.m = m;
@@ -48,14 +48,34 @@ int ensure_workspace(Ctx* c, int m, bool flexible) {
     SG_HIP(hipMalloc(&w.coef, (size_t)3 * (m + 2) * sizeof(double2)));
     SG_HIP(hipMalloc(&w.partial, (size_t)w.npartial_blocks * (m + 2) * sizeof(double2)));
     SG_HIP(hipHostMalloc(&w.host_pinned, (size_t)3 * (m + 2) * sizeof(double2), hipHostMallocDefault));
+    SG_HIP(hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
+    return SG_OK;
+}
+
+// Wait until the work queued on st has finished.  With an event the host polls it (the
+// waits of the Arnoldi loop are a few hundred microseconds apart, and a blocking wait
+// adds tens of microseconds of wake-up latency to each); without one, a blocking wait.
+int wait_stream(hipStream_t st, hipEvent_t ev) {
+    if (!ev) {
+        SG_HIP(hipStreamSynchronize(st));
+        return SG_OK;
+    }
+    SG_HIP(hipEventRecord(ev, st));
+    hipError_t e;
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+    SG_HIP(e);
     return SG_OK;
 }
 
 // Two passes of classical Gram-Schmidt of w against v_k = s_k V_k (k < nv), then ||w||.
 // On return h_pinned[0..nv) = pass-1 coefficients, [nv..2nv) = pass-2 coefficients,
-// h_pinned[2nv].x = ||w|| after both passes; the stream is synchronised.
+// h_pinned[2nv].x = ||w|| after both passes; the stream is synchronised.  The reciprocal
+// norm, the lazy scale of the next basis vector, is also left in d_next_scale on the
+// device, so that the next step needs no host-to-device copy.
 int cgs2_step(long long n, int nv, const double2* V, long long ldv, const double* d_scale, double2* w,
-              double2* partial, int nblocks, double2* d_coef, double2* h_pinned, hipStream_t st) {
+              double2* partial, int nblocks, double2* d_coef, double2* h_pinned, hipStream_t st,
+              double* d_next_scale, hipEvent_t done) {
     int rc;
     // pass 1 projection
     if ((rc = launch_multidot(n, nv, V, ldv, d_scale, w, partial, nblocks, st))) return rc;
@@ -73,33 +93,45 @@ int cgs2_step(long long n, int nv, const double2* V, long long ldv, const double
         if ((rc = launch_axpy_dot(n, nv, V, ldv, d_scale, d_coef + nv, w, nullptr, 0, false, st))) return rc;
         if ((rc = launch_norm2(n, w, partial, nblocks, st))) return rc;
     }
-    if ((rc = launch_reduce_norm(nblocks, partial, d_coef + 2 * nv, st))) return rc;
+    if ((rc = launch_reduce_norm(nblocks, partial, d_coef + 2 * nv, st, d_next_scale))) return rc;
     SG_HIP(hipMemcpyAsync(h_pinned, d_coef, (size_t)(2 * nv + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
-    SG_HIP(hipStreamSynchronize(st));
-    return SG_OK;
+    return wait_stream(st, done);
 }
 
-static int norm_sync(Ctx* c, const double2* x, double* out, hipStream_t st) {
+// ||x|| to the host; d_inv (device, may be null) also receives 1/||x||.
+static int norm_sync(Ctx* c, const double2* x, double* out, hipStream_t st, double* d_inv = nullptr) {
     Workspace& w = c->ws;
     int rc = launch_norm2(c->nvec, x, w.partial, w.npartial_blocks, st);
     if (rc) return rc;
-    if ((rc = launch_reduce_norm(w.npartial_blocks, w.partial, w.coef, st))) return rc;
+    if ((rc = launch_reduce_norm(w.npartial_blocks, w.partial, w.coef, st, d_inv))) return rc;
     SG_HIP(hipMemcpyAsync(w.host_pinned, w.coef, sizeof(double2), hipMemcpyDeviceToHost, st));
-    SG_HIP(hipStreamSynchronize(st));
+    if ((rc = wait_stream(st, w.done))) return rc;
     *out = w.host_pinned[0].x;
     return SG_OK;
 }
 
 namespace {
+// Per-phase timing of the solve statistics, recorded only while the handle's profiler is
+// on: an event between two kernels leaves the GPU idle for a few microseconds.
 struct Timer {
-    hipEvent_t e[4];
+    hipEvent_t e[4] = {};
     bool ok = false;
-    Timer() { ok = hipEventCreate(&e[0]) == hipSuccess && hipEventCreate(&e[1]) == hipSuccess &&
-                   hipEventCreate(&e[2]) == hipSuccess && hipEventCreate(&e[3]) == hipSuccess; }
-    ~Timer() { for (auto& x : e) (void)hipEventDestroy(x); }
+    explicit Timer(bool on) {
+        if (!on) return;
+        ok = true;
+        for (auto& x : e) ok = ok && hipEventCreateWithFlags(&x, hipEventDisableSystemFence) == hipSuccess;
+    }
+    ~Timer() {
+        for (auto& x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    void record(int i, hipStream_t st) {
+        if (ok && hipEventRecord(e[i], st) != hipSuccess) ok = false;
+    }
     float between(int a, int b) {
         float ms = 0;
-        if (ok && hipEventElapsedTime(&ms, e[a], e[b]) == hipSuccess) return ms;
+        if (ok && hipEventSynchronize(e[b]) == hipSuccess && hipEventElapsedTime(&ms, e[a], e[b]) == hipSuccess)
+            return ms;
         return 0.f;
     }
 };
@@ -124,7 +156,7 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
     const long long n = c->nvec;
     const long long ldv = n;
     sg_solve_stats s{};
-    Timer tm;
+    Timer tm(c->prof.on && c->prof.mask == ~0u);   // phase times only under full profiling
 
     auto precond = [&](const double2* in, double2* out) -> int {
         if (cb) {
@@ -149,7 +181,7 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
     double2* Vb = W.V;
     double2* zt = W.tmp;            // z_j (non-flexible) / update scratch
     double2* ut = W.tmp + n;
-    std::vector<double> hscale(m + 2, 1.0), zscale(m + 1, 1.0);
+    std::vector<double> hscale(m + 2, 1.0);
     std::vector<cd> H((size_t)(m + 1) * m), R((size_t)(m + 1) * m), g(m + 1), sn(m);
     std::vector<double> cs(m);
     bool first = true;
@@ -160,21 +192,20 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
         if (first && o->x0_zero) {
             SG_HIP(hipMemcpyAsync(Vb, b, (size_t)n * sizeof(double2), hipMemcpyDeviceToDevice, stream));
         } else {
-            SG_HIP(hipEventRecord(tm.e[0], stream));
+            tm.record(0, stream);
             if ((rc = launch_apply(c, x, ut, stream))) return rc;
-            SG_HIP(hipEventRecord(tm.e[1], stream));
+            tm.record(1, stream);
             if ((rc = launch_axpby(n, make_double2(1, 0), b, make_double2(-1, 0), ut, Vb, stream))) return rc;
         }
         double beta = 0;
-        if ((rc = norm_sync(c, Vb, &beta, stream))) return rc;
+        if ((rc = norm_sync(c, Vb, &beta, stream, W.scale))) return rc;   // W.scale[0] = 1/beta
         if (!(first && o->x0_zero)) s.t_matvec += tm.between(0, 1);
         first = false;
         if (!std::isfinite(beta)) return fail(SG_ENONFINITE, "non-finite residual");
         s.relres_true = beta / bnorm;
         if (s.relres_true <= o->tol) { result = SG_OK; s.converged = 1; break; }
         if (s.iters >= o->maxit) break;
-        hscale[0] = 1.0 / beta;
-        SG_HIP(hipMemcpyAsync(W.scale, hscale.data(), sizeof(double), hipMemcpyHostToDevice, stream));
+        hscale[0] = 1.0 / beta;   // the same value the device stored in W.scale[0]
         std::fill(g.begin(), g.end(), cd(0));
         g[0] = beta;
         int k = 0;
@@ -183,17 +214,15 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             const double2* vj = Vb + (long long)j * ldv;
             double2* zj = flexible ? W.Z + (long long)j * ldv : zt;
             double2* wv = Vb + (long long)(j + 1) * ldv;
-            SG_HIP(hipEventRecord(tm.e[0], stream));
+            tm.record(0, stream);
             if ((rc = precond(vj, zj))) return rc;
-            SG_HIP(hipEventRecord(tm.e[1], stream));
+            tm.record(1, stream);
             if ((rc = launch_apply(c, zj, wv, stream))) return rc;        // w = A P^{-1} V_j (unscaled)
-            SG_HIP(hipEventRecord(tm.e[2], stream));
-            zscale[j] = hscale[j];
+            tm.record(2, stream);
             if ((rc = cgs2_step(n, j + 1, Vb, ldv, W.scale, wv, W.partial, W.npartial_blocks, W.coef,
-                                W.host_pinned, stream)))
+                                W.host_pinned, stream, W.scale + j + 1, W.done)))
                 return rc;
-            SG_HIP(hipEventRecord(tm.e[3], stream));
-            SG_HIP(hipEventSynchronize(tm.e[3]));
+            tm.record(3, stream);
             s.t_precond += tm.between(0, 1);
             s.t_matvec += tm.between(1, 2);
             s.t_orth += tm.between(2, 3);
@@ -242,8 +271,7 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             s.relres_est = std::abs(g[j + 1]) / bnorm;
             if (o->hist && s.iters - 1 < o->hist_cap) o->hist[s.iters - 1] = s.relres_est;
             if (!(nrm > 1e-14 * colnorm / (sj > 0 ? sj : 1.0)) || hnext <= 1e-14 * colnorm) { breakdown = true; break; }
-            hscale[j + 1] = 1.0 / nrm;
-            SG_HIP(hipMemcpyAsync(W.scale + j + 1, &hscale[j + 1], sizeof(double), hipMemcpyHostToDevice, stream));
+            hscale[j + 1] = 1.0 / nrm;   // the same value cgs2_step left in W.scale[j + 1]
             if (s.relres_est <= o->tol || s.iters >= o->maxit) break;
         }
         // y = R^{-1} g (upper triangular k×k)
@@ -258,7 +286,8 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
         for (int i = 0; i < k; ++i) W.host_pinned[i] = make_double2(y[i].real(), y[i].imag());
         SG_HIP(hipMemcpyAsync(W.coef, W.host_pinned, (size_t)k * sizeof(double2), hipMemcpyHostToDevice, stream));
         if (flexible) {
-            SG_HIP(hipMemcpyAsync(W.scale, zscale.data(), (size_t)k * sizeof(double), hipMemcpyHostToDevice, stream));
+            // z_j = P^{-1}(s_j V_j) was formed from the unscaled V_j: the same lazy scales
+            // W.scale[0..k) apply to Z
             if ((rc = launch_lincomb(n, k, W.Z, ldv, W.scale, W.coef, x, stream))) return rc;
         } else {
             SG_HIP(hipMemsetAsync(ut, 0, (size_t)n * sizeof(double2), stream));
@@ -266,11 +295,11 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             if ((rc = precond(ut, zt))) return rc;
             if ((rc = launch_axpby(n, make_double2(1, 0), x, make_double2(1, 0), zt, x, stream))) return rc;
         }
-        SG_HIP(hipStreamSynchronize(stream));   // host vectors above must outlive the copies
+        if ((rc = wait_stream(stream, W.done))) return rc;   // host vectors above must outlive the copies
         ++s.restarts;
         if (breakdown) {
             // the Krylov space is invariant: the update is the solution of this space
-            SG_HIP(hipEventRecord(tm.e[0], stream));
+            tm.record(0, stream);
             if ((rc = launch_apply(c, x, ut, stream))) return rc;
             if ((rc = launch_axpby(n, make_double2(1, 0), b, make_double2(-1, 0), ut, ut, stream))) return rc;
             double rn = 0;

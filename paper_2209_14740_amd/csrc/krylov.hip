@@ -94,9 +94,11 @@ __global__ __launch_bounds__(RB) void k_norm2(long long n, const double2* __rest
     }
 }
 
-// One block per output coefficient k; mode 0: scaled complex sum, mode 1: sqrt of real sum.
+// One block per output coefficient k; mode 0: scaled complex sum, mode 1: sqrt of real sum
+// (and, when inv is given, its reciprocal: the lazy scale of the next basis vector).
 __global__ __launch_bounds__(RB) void k_reduce(int nblocks, int nv, const double2* __restrict__ partial,
-                                               const double* __restrict__ scale, double2* __restrict__ out, int mode) {
+                                               const double* __restrict__ scale, double2* __restrict__ out, int mode,
+                                               double* __restrict__ inv) {
     __shared__ double2 red[RB / 64];
     const int k = blockIdx.x;
     double sx = 0.0, sy = 0.0;
@@ -116,7 +118,9 @@ __global__ __launch_bounds__(RB) void k_reduce(int nblocks, int nv, const double
             ty += red[w].y;
         }
         if (mode == 1) {
-            out[k] = make_double2(sqrt(tx), 0.0);
+            const double nrm = sqrt(tx);
+            out[k] = make_double2(nrm, 0.0);
+            if (inv) *inv = 1.0 / nrm;
         } else {
             const double s = scale ? scale[k] : 1.0;
             out[k] = make_double2(s * tx, s * ty);
@@ -413,14 +417,14 @@ int launch_multidot(long long n, int nv, const double2* V, long long ldv, const 
 
 int launch_reduce(int nblocks, int nv, const double2* partial, const double* scale, double2* out, hipStream_t st) {
     KScope ks(SG_K_NORM, 16.0 * nblocks * (double)nv, st);
-    hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(RB), 0, st, nblocks, nv, partial, scale, out, 0);
+    hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(RB), 0, st, nblocks, nv, partial, scale, out, 0, (double*)nullptr);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
 
-int launch_reduce_norm(int nblocks, const double2* partial, double2* out, hipStream_t st) {
+int launch_reduce_norm(int nblocks, const double2* partial, double2* out, hipStream_t st, double* inv) {
     KScope ks(SG_K_NORM, 16.0 * nblocks, st);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RB), 0, st, nblocks, 1, partial, (const double*)nullptr, out, 1);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RB), 0, st, nblocks, 1, partial, (const double*)nullptr, out, 1, inv);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }

@@ -13,8 +13,10 @@ hipEvent_t Prof::get() {
         pool.pop_back();
         return e;
     }
+    // timing only: no system-scope release at the event, which would write back and
+    // invalidate caches between the kernels it separates
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 

@@ -446,6 +446,7 @@ Ctx::~Ctx() {
     (void)hipFree(ws.coef);
     (void)hipFree(ws.partial);
     if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
+    if (ws.done) (void)hipEventDestroy(ws.done);
     (void)hipFree(d_tmp_pc);
 }
 

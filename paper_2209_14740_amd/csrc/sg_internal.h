@@ -128,6 +128,7 @@ struct Workspace {
     double2* partial = nullptr;// reduction partials
     int npartial_blocks = 0;
     double2* host_pinned = nullptr; // pinned host mirror of coef
+    hipEvent_t done = nullptr; // host waits of the Arnoldi loop poll this event
 };
 
 // Optional per-kernel-class event timing (sg_set_profiling / sg_kernel_times).
@@ -241,7 +242,8 @@ int launch_axpy_dot(long long n, int nv, const double2* V, long long ldv, const 
 int launch_norm2(long long n, const double2* x, double2* partial, int nblocks, hipStream_t st);
 int launch_upd(long long n, int nv, const double2* V, long long ldv, const double* scale, const double2* coef,
                double2* w, double2* partial, int nblocks, bool dot, hipStream_t st);
-int launch_reduce_norm(int nblocks, const double2* partial, double2* out, hipStream_t st);
+// out[0] = (||.||, 0); inv (device, may be null) receives 1/||.||
+int launch_reduce_norm(int nblocks, const double2* partial, double2* out, hipStream_t st, double* inv = nullptr);
 int launch_lincomb(long long n, int nv, const double2* V, long long ldv, const double* scale,
                    const double2* coef, double2* x, hipStream_t st);
 int launch_axpby(long long n, double2 a, const double2* x, double2 b, const double2* y, double2* out,
@@ -271,10 +273,14 @@ void tune_set(int n, int Q, int precision, int cfg);
 int net_precond(Net* n, Ctx* c, int precision, const double2* v, double2* z, hipStream_t st);
 
 // gmres.cpp
+// wait for the work queued on st: poll ev (recorded here) when given, else block
+int wait_stream(hipStream_t st, hipEvent_t ev);
 int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_precond_cb cb,
               void* user, bool flexible, sg_solve_stats* st, hipStream_t stream);
+// d_next_scale (device, may be null) receives 1/||w|| after the two passes; the host waits
+// for the coefficients by polling `done` (null: a blocking stream synchronisation)
 int cgs2_step(long long n, int nv, const double2* V, long long ldv, const double* d_scale,
               double2* w, double2* partial, int nblocks, double2* d_coef, double2* h_pinned,
-              hipStream_t st);
+              hipStream_t st, double* d_next_scale = nullptr, hipEvent_t done = nullptr);
 
 }  // namespace sgi
