@@ -55,12 +55,7 @@ int ensure_workspace(Ctx* c, int m, bool flexible) {
 // Wait until the work queued on st has finished.  With an event the host polls it (the
 // waits of the Arnoldi loop are a few hundred microseconds apart, and a blocking wait
 // adds tens of microseconds of wake-up latency to each); without one, a blocking wait.
-int wait_stream(hipStream_t st, hipEvent_t ev) {
-    if (!ev) {
-        SG_HIP(hipStreamSynchronize(st));
-        return SG_OK;
-    }
-    SG_HIP(hipEventRecord(ev, st));
+static int poll_event(hipEvent_t ev) {
     hipError_t e;
     while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
     }
@@ -68,14 +63,24 @@ int wait_stream(hipStream_t st, hipEvent_t ev) {
     return SG_OK;
 }
 
+int wait_stream(hipStream_t st, hipEvent_t ev) {
+    if (!ev) {
+        SG_HIP(hipStreamSynchronize(st));
+        return SG_OK;
+    }
+    SG_HIP(hipEventRecord(ev, st));
+    return poll_event(ev);
+}
+
 // Two passes of classical Gram-Schmidt of w against v_k = s_k V_k (k < nv), then ||w||.
 // On return h_pinned[0..nv) = pass-1 coefficients, [nv..2nv) = pass-2 coefficients,
-// h_pinned[2nv].x = ||w|| after both passes; the stream is synchronised.  The reciprocal
-// norm, the lazy scale of the next basis vector, is also left in d_next_scale on the
-// device, so that the next step needs no host-to-device copy.
+// h_pinned[2nv].x = ||w|| after both passes; the stream is synchronised (or, with
+// wait = false, `done` is recorded after the copy and the caller polls it).  The
+// reciprocal norm, the lazy scale of the next basis vector, is also left in d_next_scale on
+// the device, so that the next step needs no host-to-device copy.
 int cgs2_step(long long n, int nv, const double2* V, long long ldv, const double* d_scale, double2* w,
               double2* partial, int nblocks, double2* d_coef, double2* h_pinned, hipStream_t st,
-              double* d_next_scale, hipEvent_t done) {
+              double* d_next_scale, hipEvent_t done, bool wait) {
     int rc;
     // pass 1 projection
     if ((rc = launch_multidot(n, nv, V, ldv, d_scale, w, partial, nblocks, st))) return rc;
@@ -95,6 +100,10 @@ int cgs2_step(long long n, int nv, const double2* V, long long ldv, const double
     }
     if ((rc = launch_reduce_norm(nblocks, partial, d_coef + 2 * nv, st, d_next_scale))) return rc;
     SG_HIP(hipMemcpyAsync(h_pinned, d_coef, (size_t)(2 * nv + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
+    if (!wait && done) {
+        SG_HIP(hipEventRecord(done, st));
+        return SG_OK;
+    }
     return wait_stream(st, done);
 }
 
@@ -168,7 +177,8 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
     };
 
     double bnorm = 0;
-    if ((rc = norm_sync(c, b, &bnorm, stream))) return rc;
+    // from x = 0 the first residual is b itself: its norm and lazy scale serve the first cycle
+    if ((rc = norm_sync(c, b, &bnorm, stream, o->x0_zero ? W.scale : nullptr))) return rc;
     if (!std::isfinite(bnorm)) return fail(SG_ENONFINITE, "non-finite right-hand side");
     if (o->x0_zero) SG_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double2), stream));
     if (bnorm == 0.0) {
@@ -178,6 +188,14 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
         if (st) *st = s;
         return SG_OK;
     }
+    // The preconditioner and operator of Arnoldi step j+1 need no host result (the lazy
+    // scale of v_{j+1} is formed on the device), so with the built-in preconditioners they
+    // are queued before the host waits for step j's coefficients, hiding the host's turn
+    // (wait, least-squares update, launches).  It is done while the estimate is above
+    // 30·tol, so the work rarely goes unused; unused, it only writes buffers that the
+    // cycle's update does not read.  Not under full profiling, whose phase times need the
+    // phases apart.
+    const bool can_ahead = !cb && o->precond != SG_PC_MEAN_NET && !tm.ok;
     double2* Vb = W.V;
     double2* zt = W.tmp;            // z_j (non-flexible) / update scratch
     double2* ut = W.tmp + n;
@@ -197,8 +215,9 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             tm.record(1, stream);
             if ((rc = launch_axpby(n, make_double2(1, 0), b, make_double2(-1, 0), ut, Vb, stream))) return rc;
         }
-        double beta = 0;
-        if ((rc = norm_sync(c, Vb, &beta, stream, W.scale))) return rc;   // W.scale[0] = 1/beta
+        double beta = bnorm;
+        if (!(first && o->x0_zero) && (rc = norm_sync(c, Vb, &beta, stream, W.scale)))   // W.scale[0] = 1/beta
+            return rc;
         if (!(first && o->x0_zero)) s.t_matvec += tm.between(0, 1);
         first = false;
         if (!std::isfinite(beta)) return fail(SG_ENONFINITE, "non-finite residual");
@@ -210,18 +229,29 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
         g[0] = beta;
         int k = 0;
         bool breakdown = false;
+        bool queued = false;                 // step j's preconditioner and operator already queued
+        double est_prev = s.relres_true;     // latest residual estimate
+        auto queue_pa = [&](int jj) -> int {   // w_{jj+1} = A P^{-1} V_jj (unscaled)
+            double2* zz = flexible ? W.Z + (long long)jj * ldv : zt;
+            int r2 = precond(Vb + (long long)jj * ldv, zz);
+            if (r2) return r2;
+            tm.record(1, stream);
+            return launch_apply(c, zz, Vb + (long long)(jj + 1) * ldv, stream);
+        };
         for (int j = 0; j < m; ++j) {
-            const double2* vj = Vb + (long long)j * ldv;
-            double2* zj = flexible ? W.Z + (long long)j * ldv : zt;
             double2* wv = Vb + (long long)(j + 1) * ldv;
             tm.record(0, stream);
-            if ((rc = precond(vj, zj))) return rc;
-            tm.record(1, stream);
-            if ((rc = launch_apply(c, zj, wv, stream))) return rc;        // w = A P^{-1} V_j (unscaled)
+            if (!queued && (rc = queue_pa(j))) return rc;
             tm.record(2, stream);
+            const bool ahead = can_ahead && j + 1 < m && s.iters + 1 < o->maxit && est_prev > 30.0 * o->tol;
             if ((rc = cgs2_step(n, j + 1, Vb, ldv, W.scale, wv, W.partial, W.npartial_blocks, W.coef,
-                                W.host_pinned, stream, W.scale + j + 1, W.done)))
+                                W.host_pinned, stream, W.scale + j + 1, W.done, !ahead)))
                 return rc;
+            if (ahead) {
+                if ((rc = queue_pa(j + 1))) return rc;
+                if ((rc = poll_event(W.done))) return rc;
+            }
+            queued = ahead;
             tm.record(3, stream);
             s.t_precond += tm.between(0, 1);
             s.t_matvec += tm.between(1, 2);
@@ -269,6 +299,7 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             ++s.iters;
             k = j + 1;
             s.relres_est = std::abs(g[j + 1]) / bnorm;
+            est_prev = s.relres_est;
             if (o->hist && s.iters - 1 < o->hist_cap) o->hist[s.iters - 1] = s.relres_est;
             if (!(nrm > 1e-14 * colnorm / (sj > 0 ? sj : 1.0)) || hnext <= 1e-14 * colnorm) { breakdown = true; break; }
             hscale[j + 1] = 1.0 / nrm;   // the same value cgs2_step left in W.scale[j + 1]
@@ -295,7 +326,8 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             if ((rc = precond(ut, zt))) return rc;
             if ((rc = launch_axpby(n, make_double2(1, 0), x, make_double2(1, 0), zt, x, stream))) return rc;
         }
-        if ((rc = wait_stream(stream, W.done))) return rc;   // host vectors above must outlive the copies
+        // (the coefficients went up from pinned memory, which the host does not touch again
+        // before the next wait, so no wait is needed here)
         ++s.restarts;
         if (breakdown) {
             // the Krylov space is invariant: the update is the solution of this space

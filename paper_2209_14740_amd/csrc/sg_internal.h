@@ -278,9 +278,10 @@ int wait_stream(hipStream_t st, hipEvent_t ev);
 int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_precond_cb cb,
               void* user, bool flexible, sg_solve_stats* st, hipStream_t stream);
 // d_next_scale (device, may be null) receives 1/||w|| after the two passes; the host waits
-// for the coefficients by polling `done` (null: a blocking stream synchronisation)
+// for the coefficients by polling `done` (null: a blocking stream synchronisation); with
+// wait = false (and done given) it only records `done` after the copy
 int cgs2_step(long long n, int nv, const double2* V, long long ldv, const double* d_scale,
               double2* w, double2* partial, int nblocks, double2* d_coef, double2* h_pinned,
-              hipStream_t st, double* d_next_scale = nullptr, hipEvent_t done = nullptr);
+              hipStream_t st, double* d_next_scale = nullptr, hipEvent_t done = nullptr, bool wait = true);
 
 }  // namespace sgi
