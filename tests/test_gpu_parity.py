@@ -302,6 +302,32 @@ def test_sigma_zero_one_step():
     _check_solution(S, to_host(x), 1e-10, precond.direct_solve(S))
 
 
+def test_lookahead_matches_profiled_solve():
+    """Without profiling the host loop queues step j+1's preconditioner and operator before
+    it waits for step j's coefficients; under full profiling it runs the phases apart with
+    events between them.  The device arithmetic is the same, so both give the same iterates
+    bit for bit (several restart cycles, plain and flexible); the phase times are reported
+    only by the profiled solve."""
+    key = "2d_n150_s3_r3"
+    inst = SMALL[key]()
+    op = sg.SG.from_instance(inst)
+    b = op.rhs(inst.f)
+    for flexible, precision in ((False, "f64"), (True, "bf16x3")):
+        fn = op.fgmres if flexible else op.gmres
+        x1, i1 = fn(b, restart=10, maxit=2000, pc="mean", precision=precision, tol=1e-10, hist=True)
+        sg.check(sg.lib().sg_set_profiling(op._h, 1), "sg_set_profiling")
+        try:
+            x2, i2 = fn(b, restart=10, maxit=2000, pc="mean", precision=precision, tol=1e-10, hist=True)
+        finally:
+            sg.check(sg.lib().sg_set_profiling(op._h, 0), "sg_set_profiling")
+        print("look-ahead", precision, i1["iters"], i1["restarts"], flush=True)
+        assert i1["converged"] == 1 and i1["restarts"] >= 2
+        assert (i1["iters"], i1["restarts"]) == (i2["iters"], i2["restarts"])
+        assert i1["hist"] == i2["hist"]
+        assert torch.equal(x1, x2)
+        assert i1["t_precond"] == 0.0 and i2["t_precond"] > 0.0 and i2["t_orth"] > 0.0
+
+
 def test_maxit_returns_not_converged():
     inst = config1()
     op = sg.SG.from_instance(inst)
