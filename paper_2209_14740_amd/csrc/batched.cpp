@@ -254,6 +254,12 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         double2* p;
         ~FreeH() { (void)hipHostFree(p); }
     } free_hcoef{h_coef};
+    // sweep layout of every grouped launch: two right-hand sides per thread when all
+    // instances allow it
+    int tri_nr = 2;
+    if (pc == SG_PC_NONE) tri_nr = 1;
+    for (int i = 0; i < count && tri_nr == 2; ++i)
+        if (!tri_nr_ok(ctx[i]->tri[pc == SG_PC_MEAN ? 0 : 1], ctx[i]->n, ctx[i]->Q, ctx[i]->dim)) tri_nr = 1;
     hipEvent_t step_done = nullptr;   // the host polls it at the end of every lockstep step
     SG_HIP(hipEventCreateWithFlags(&step_done, hipEventDisableTiming));
     struct FreeE {
@@ -399,7 +405,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
             if (pc == SG_PC_NONE) continue;
             const TriFactors& f = c->tri[pc == SG_PC_MEAN ? 0 : 1];
             if (c->dim == 1) {
-                TriTask tt = make_tri_task(f, s.zt, c->n, c->n, c->Q, 1);
+                TriTask tt = make_tri_task(f, s.zt, c->n, c->n, c->Q, 1, tri_nr);
                 g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
             } else {
                 int cfg = tune_get(c->n, c->Q, prec);
@@ -412,7 +418,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                 const double fl = (gemm_cfg_3m(cfg) ? 6.0 : 8.0) * M * (double)c->n * c->n;
                 g_fwd[cfg].add(gf, gf.tiles_m * gf.tiles_n, fl);
                 g_inv[cfg].add(gi, gi.tiles_m * gi.tiles_n, fl);
-                TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->tld, c->Q, 2);
+                TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->tld, c->Q, 2, tri_nr);
                 g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
             }
         }
@@ -519,8 +525,8 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                 return rc;
         int max_seg = 0;
         for (const TriTask& tt : g_tri.tasks) max_seg = std::max(max_seg, tt.f.L);
-        if ((rc = launch_tri_grouped(stg.dtasks(g_tri), stg.dstart(g_tri), g_tri.n(), g_tri.total(), max_seg, g_tri.work,
-                                     stream)))
+        if ((rc = launch_tri_grouped(stg.dtasks(g_tri), stg.dstart(g_tri), g_tri.n(), g_tri.total(), max_seg, tri_nr,
+                                     g_tri.work, stream)))
             return rc;
         for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg)
             if ((rc = launch_gemm_grouped(prec, cfg, stg.dtasks(g_inv[cfg]), stg.dstart(g_inv[cfg]), g_inv[cfg].n(),

@@ -548,42 +548,53 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {   // 
     return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
 
-// LDS of the segment joins, one scan round at a time (the forward scan uses the first two
-// planes, the backward one all six).
+// LDS of the segment joins, one scan round at a time.  The propagators depend on the system
+// only, the carried values also on the right-hand side: the forward scan uses planes 0
+// (propagator) and 1..NR (values), the backward one planes 0..3 (2×2 propagator) and
+// 4..4+2NR-1 (2-vector values).
+template <int NR>
 struct TriLds {
-    double2 p[6][256];
+    double2 p[4 + 2 * NR][256];
 };
 
-// Block → (systems, right-hand side).  With at least SYS systems per right-hand side a
-// block takes SYS consecutive systems a of one right-hand side q, and consecutive blocks
-// step through q first: the blocks that share a set of factor rows run together and
-// find them in L2.  Otherwise (one system, 1D) a block takes SYS consecutive (a, q).
-__host__ __device__ inline long long tri_blocks(int na, int nq, int K) {
+// Block → (systems, right-hand sides).  With at least SYS systems per right-hand side a
+// block takes SYS consecutive systems a and NR consecutive right-hand sides q (each
+// thread solves its segment for all NR, sharing the factor loads), and consecutive blocks
+// step through q first: the blocks that share a set of factor rows run together and find
+// them in L2.  Otherwise (one system, 1D; NR = 1) a block takes SYS consecutive (a, q).
+__host__ __device__ inline long long tri_blocks(int na, int nq, int K, int NR) {
     const int SYS = 256 / K;
-    if (na >= SYS) return (long long)((na + SYS - 1) / SYS) * nq;
+    if (na >= SYS) return (long long)((na + SYS - 1) / SYS) * ((nq + NR - 1) / NR);
     return ((long long)na * nq + SYS - 1) / SYS;
 }
 
-template <int SEGL>
+template <int SEGL, int NR>
 __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const TriFactors& f, int len, int na,
                                               int nq, long long se, long long sa, long long sq, int fa, int blk,
-                                              TriLds& sm) {
+                                              TriLds<NR>& sm) {
     const int K = f.K, L = f.L, SYS = 256 / K;
     const int tid = threadIdx.x, k = tid / SYS, sl = tid - k * SYS;
-    int a, q;
+    int a, q0;
     bool valid;
     if (na >= SYS) {
-        q = blk % nq;
-        a = (blk / nq) * SYS + sl;
+        const int nqb = (nq + NR - 1) / NR;
+        q0 = (blk % nqb) * NR;
+        a = (blk / nqb) * SYS + sl;
         valid = a < na;
-    } else {
+    } else {   // NR == 1
         const long long sysg = (long long)blk * SYS + sl;
         valid = sysg < (long long)na * nq;
         a = (int)(sysg % na);
-        q = (int)(sysg / na);
+        q0 = (int)(sysg / na);
     }
-    if (!valid) a = q = 0;   // in-range reads; nothing is stored
-    double2* x = X + (long long)q * sq + (long long)a * sa;
+    if (!valid) a = q0 = 0;   // in-range reads; nothing is stored
+    bool qok[NR];
+    double2* x[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        qok[r] = valid && q0 + r < nq;
+        x[r] = X + (long long)(qok[r] ? q0 + r : q0) * sq + (long long)a * sa;
+    }
     const int fs = f.nsys;
     // factor row i of this system: ptr[i * fs]
     const double2* __restrict__ dl = f.dl + a * fa;
@@ -594,42 +605,56 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     const double2 zero = make_double2(0.0, 0.0);
     const double2 ph = f.phi[(long long)k * fs + a * fa];
     const uint32_t pm = f.pivm[(long long)k * fs + a * fa];
-    double2 b[SEGL + 1];
+    double2 b[NR][SEGL + 1];
 #pragma unroll
     for (int u = 0; u <= SEGL; ++u) {
         const int i = s0 + u;
-        b[u] = zero;
-        if (valid && u <= L && i < len) b[u] = x[(long long)i * se];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            b[r][u] = zero;
+            if (qok[r] && u <= L && i < len) b[r][u] = x[r][(long long)i * se];
+        }
     }
     // forward, local run (segment 0 starts from b_0, the others from zero)
-    double2 cur = csel(k == 0, b[0], zero);
+    double2 cur[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) cur[r] = csel(k == 0, b[r][0], zero);
 #pragma unroll
     for (int u = 0; u < SEGL; ++u) {
         const int i = s0 + u;
         if (i < e0 && i <= len - 2) {
             const double2 l = dl[(long long)i * fs];
-            const double2 nb = b[u + 1];
             const bool pv = (pm >> u) & 1u;
-            cur = csub(csel(pv, cur, nb), cmul(l, csel(pv, nb, cur)));
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const double2 nb = b[r][u + 1];
+                cur[r] = csub(csel(pv, cur[r], nb), cmul(l, csel(pv, nb, cur[r])));
+            }
         }
     }
     // inclusive scan over the segments of the affine maps c -> φ_k c + t_k (segment 0's
     // map is constant): afterwards T is the exact value leaving segment k
-    double2 P = csel(k == 0, zero, ph), T = cur;
+    double2 P = csel(k == 0, zero, ph), T[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) T[r] = cur[r];
     for (int d = 1; d < K; d <<= 1) {
         sm.p[0][tid] = P;
-        sm.p[1][tid] = T;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) sm.p[1 + r][tid] = T[r];
         __syncthreads();
         if (k >= d) {
-            const double2 Pp = sm.p[0][tid - d * SYS], Tp = sm.p[1][tid - d * SYS];
-            T = cfma(P, Tp, T);
+            const double2 Pp = sm.p[0][tid - d * SYS];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) T[r] = cfma(P, sm.p[1 + r][tid - d * SYS], T[r]);
             P = cmul(P, Pp);
         }
         __syncthreads();
     }
-    sm.p[1][tid] = T;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) sm.p[1 + r][tid] = T[r];
     __syncthreads();
-    cur = csel(k == 0, b[0], sm.p[1][max(tid - SYS, 0)]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) cur[r] = csel(k == 0, b[r][0], sm.p[1 + r][max(tid - SYS, 0)]);
 #pragma unroll
     for (int u = 0; u < SEGL; ++u) {
         const int i = s0 + u;
@@ -638,94 +663,125 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
             if (i <= len - 2) {
                 const double2 l = dl[(long long)i * fs];
                 const bool pv = (pm >> u) & 1u;
-                const double2 nb = b[u + 1];
-                b[u] = cmul(csel(pv, nb, cur), di);
-                cur = csub(csel(pv, cur, nb), cmul(l, csel(pv, nb, cur)));
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const double2 nb = b[r][u + 1];
+                    b[r][u] = cmul(csel(pv, nb, cur[r]), di);
+                    cur[r] = csub(csel(pv, cur[r], nb), cmul(l, csel(pv, nb, cur[r])));
+                }
             } else {
-                b[u] = cmul(cur, di);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) b[r][u] = cmul(cur[r], di);
             }
         }
     }
     // backward, local run with a zero entering state
     const double2* ps = f.psi + ((long long)k * fs + a * fa) * 4;
     double2 M00 = ps[0], M01 = ps[1], M10 = ps[2], M11 = ps[3];
-    double2 x1 = zero, x2 = zero;
+    double2 x1[NR], x2[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) x1[r] = x2[r] = zero;
 #pragma unroll
     for (int u = SEGL - 1; u >= 0; --u) {
         const int i = s0 + u;
         if (i < e0) {
-            const long long r = (long long)i * fs;
-            const double2 xi = csub(csub(b[u], cmul(u1p[r], x1)), cmul(u2p[r], x2));
-            x2 = x1;
-            x1 = xi;
+            const long long ro = (long long)i * fs;
+            const double2 w1 = u1p[ro], w2 = u2p[ro];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const double2 xi = csub(csub(b[r][u], cmul(w1, x1[r])), cmul(w2, x2[r]));
+                x2[r] = x1[r];
+                x1[r] = xi;
+            }
         }
     }
     // suffix scan of the affine maps G -> Ψ_k G + g_k (the last segment's map is
     // constant): afterwards (V0, V1) is the exact state at the start of segment k
     if (k == K - 1) M00 = M01 = M10 = M11 = zero;
-    double2 V0 = x1, V1 = x2;
+    double2 V0[NR], V1[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        V0[r] = x1[r];
+        V1[r] = x2[r];
+    }
     __syncthreads();   // every thread has read the forward entering values
     for (int d = 1; d < K; d <<= 1) {
         sm.p[0][tid] = M00;
         sm.p[1][tid] = M01;
         sm.p[2][tid] = M10;
         sm.p[3][tid] = M11;
-        sm.p[4][tid] = V0;
-        sm.p[5][tid] = V1;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            sm.p[4 + 2 * r][tid] = V0[r];
+            sm.p[5 + 2 * r][tid] = V1[r];
+        }
         __syncthreads();
         if (k + d < K) {
             const int o = tid + d * SYS;
-            const double2 N00 = sm.p[0][o], N01 = sm.p[1][o], N10 = sm.p[2][o],
-                          N11 = sm.p[3][o], W0 = sm.p[4][o], W1 = sm.p[5][o];
-            V0 = cfma(M00, W0, cfma(M01, W1, V0));
-            V1 = cfma(M10, W0, cfma(M11, W1, V1));
+            const double2 N00 = sm.p[0][o], N01 = sm.p[1][o], N10 = sm.p[2][o], N11 = sm.p[3][o];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const double2 W0 = sm.p[4 + 2 * r][o], W1 = sm.p[5 + 2 * r][o];
+                V0[r] = cfma(M00, W0, cfma(M01, W1, V0[r]));
+                V1[r] = cfma(M10, W0, cfma(M11, W1, V1[r]));
+            }
             const double2 R00 = cfma(M00, N00, cmul(M01, N10)), R01 = cfma(M00, N01, cmul(M01, N11));
             const double2 R10 = cfma(M10, N00, cmul(M11, N10)), R11 = cfma(M10, N01, cmul(M11, N11));
             M00 = R00; M01 = R01; M10 = R10; M11 = R11;
         }
         __syncthreads();
     }
-    sm.p[4][tid] = V0;
-    sm.p[5][tid] = V1;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        sm.p[4 + 2 * r][tid] = V0[r];
+        sm.p[5 + 2 * r][tid] = V1[r];
+    }
     __syncthreads();
     const int nxt_seg = min(tid + SYS, 255);
-    x1 = csel(k == K - 1, zero, sm.p[4][nxt_seg]);
-    x2 = csel(k == K - 1, zero, sm.p[5][nxt_seg]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        x1[r] = csel(k == K - 1, zero, sm.p[4 + 2 * r][nxt_seg]);
+        x2[r] = csel(k == K - 1, zero, sm.p[5 + 2 * r][nxt_seg]);
+    }
 #pragma unroll
     for (int u = SEGL - 1; u >= 0; --u) {
         const int i = s0 + u;
         if (i < e0) {
-            const long long r = (long long)i * fs;
-            const double2 xi = csub(csub(b[u], cmul(u1p[r], x1)), cmul(u2p[r], x2));
-            if (valid) x[(long long)i * se] = xi;
-            x2 = x1;
-            x1 = xi;
+            const long long ro = (long long)i * fs;
+            const double2 w1 = u1p[ro], w2 = u2p[ro];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const double2 xi = csub(csub(b[r][u], cmul(w1, x1[r])), cmul(w2, x2[r]));
+                if (qok[r]) x[r][(long long)i * se] = xi;
+                x2[r] = x1[r];
+                x1[r] = xi;
+            }
         }
     }
 }
 
-// One block of 256 threads per SYS systems; the XCD remap keeps consecutive virtual blocks
-// (the right-hand sides of one set of systems) on one XCD.
-template <int SEGL>
+// One block of 256 threads per SYS systems (× NR right-hand sides); the XCD remap keeps
+// consecutive virtual blocks (the right-hand sides of one set of systems) on one XCD.
+template <int SEGL, int NR>
 __global__ __launch_bounds__(256) void k_tri_seg(double2* __restrict__ X, TriFactors f, int len, int na, int nq,
                                                  long long se, long long sa, long long sq, int fa, int total) {
-    __shared__ TriLds sm;
+    __shared__ TriLds<NR> sm;
     const int per = gridDim.x / 8;
     const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (v >= total) return;
-    tri_seg_block<SEGL>(X, f, len, na, nq, se, sa, sq, fa, v, sm);
+    tri_seg_block<SEGL, NR>(X, f, len, na, nq, se, sa, sq, fa, v, sm);
 }
 
-template <int SEGL>
+template <int SEGL, int NR>
 __global__ __launch_bounds__(256) void k_tri_seg_grouped(const TriTask* __restrict__ tasks,
                                                          const int* __restrict__ start, int ntask, int total) {
-    __shared__ TriLds sm;
+    __shared__ TriLds<NR> sm;
     const int per = gridDim.x / 8;
     const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (v >= total) return;
     const int t = find_task(start, ntask, v);
     const TriTask& g = tasks[t];
-    tri_seg_block<SEGL>(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], sm);
+    tri_seg_block<SEGL, NR>(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], sm);
 }
 
 static inline uint16_t host_bf16(float f) {
@@ -931,7 +987,13 @@ int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const i
     return dispatch_gemm(precision, cfg, GemmTask{}, d_tasks, d_start, ntask, total, st);
 }
 
-TriTask make_tri_task(const TriFactors& f, double2* X, int n, int ld, int Q, int dim) {
+// Two right-hand sides per thread need whole sets of systems per block (2D, n >= 256/K),
+// at least two right-hand sides and segments of at most 8 rows (both in registers).
+bool tri_nr_ok(const TriFactors& f, int n, int Q, int dim) {
+    return dim == 2 && f.K >= 1 && n >= 256 / f.K && Q >= 2 && f.L <= 8;
+}
+
+TriTask make_tri_task(const TriFactors& f, double2* X, int n, int ld, int Q, int dim, int nr) {
     TriTask t{};
     t.X = X;
     t.f = f;
@@ -941,19 +1003,24 @@ TriTask make_tri_task(const TriFactors& f, double2* X, int n, int ld, int Q, int
     } else {
         t.na = 1; t.nq = Q; t.se = 1; t.sa = 0; t.sq = n; t.fa = 0;
     }
-    t.nblocks = (int)tri_blocks(t.na, t.nq, f.K >= 1 ? f.K : 1);
+    t.nblocks = (int)tri_blocks(t.na, t.nq, f.K >= 1 ? f.K : 1, nr);
     return t;
 }
 
-int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, int max_seg, double bytes,
-                       hipStream_t st) {
+int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, int max_seg, int nr,
+                       double bytes, hipStream_t st) {
     if (ntask <= 0 || total <= 0) return SG_OK;
     if (max_seg > 32) return fail(SG_EINVAL, "grid too large for the grouped tridiagonal sweep");
+    if (nr == 2 && max_seg > 8) return fail(SG_EINVAL, "two right-hand sides per thread need segments of <= 8 rows");
     KScope ks(SG_K_TRI, bytes, st);
     const dim3 grid((unsigned)((total + 7) / 8 * 8));
-    if (max_seg <= 8) hipLaunchKernelGGL(k_tri_seg_grouped<8>, grid, dim3(256), 0, st, d_tasks, d_start, ntask, total);
-    else if (max_seg <= 16) hipLaunchKernelGGL(k_tri_seg_grouped<16>, grid, dim3(256), 0, st, d_tasks, d_start, ntask, total);
-    else hipLaunchKernelGGL(k_tri_seg_grouped<32>, grid, dim3(256), 0, st, d_tasks, d_start, ntask, total);
+#define SG_TRIG(SEGL_, NR_) \
+    hipLaunchKernelGGL((k_tri_seg_grouped<SEGL_, NR_>), grid, dim3(256), 0, st, d_tasks, d_start, ntask, total)
+    if (nr == 2) SG_TRIG(8, 2);
+    else if (max_seg <= 8) SG_TRIG(8, 1);
+    else if (max_seg <= 16) SG_TRIG(16, 1);
+    else SG_TRIG(32, 1);
+#undef SG_TRIG
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
@@ -971,15 +1038,23 @@ static int launch_tri(const TriFactors& f, double2* X, int n, int ld, int Q, int
     // algorithmic: every element read and written once, factors read once
     KScope ks(SG_K_TRI, 32.0 * na * (double)nq * n + 65.0 * f.nsys * (double)n, st);
     if (f.L <= 32 && f.K >= 1) {
-        const long long total = tri_blocks(na, nq, f.K);
+        // two right-hand sides per thread where the blocks hold whole sets of systems and the
+        // segments are short enough for both to stay in registers (8 rows: 166 registers;
+        // 16 rows would spill)
+        const int nr = tri_nr_ok(f, n, Q, dim) ? 2 : 1;
+        const long long total = tri_blocks(na, nq, f.K, nr);
         if (total > INT32_MAX - 8) return fail(SG_EINVAL, "grid too large for the tridiagonal sweep");
         const dim3 grid((unsigned)((total + 7) / 8 * 8));
-        if (f.L <= 8)
-            hipLaunchKernelGGL(k_tri_seg<8>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total);
-        else if (f.L <= 16)
-            hipLaunchKernelGGL(k_tri_seg<16>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total);
-        else
-            hipLaunchKernelGGL(k_tri_seg<32>, grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total);
+#define SG_TRI(SEGL_, NR_) \
+    hipLaunchKernelGGL((k_tri_seg<SEGL_, NR_>), grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total)
+        if (nr == 2) {
+            SG_TRI(8, 2);
+        } else {
+            if (f.L <= 8) SG_TRI(8, 1);
+            else if (f.L <= 16) SG_TRI(16, 1);
+            else SG_TRI(32, 1);
+        }
+#undef SG_TRI
         SG_HIP(hipGetLastError());
         return SG_OK;
     }

@@ -339,7 +339,7 @@ static int build_tri(int n, double h, double kbar, const std::vector<cplx>& sig,
     // M_i = [[-u_{i,i+1}/u_ii, -u_{i,i+2}/u_ii], [1, 0]]; the products of A_i and of M_i over
     // each segment are the propagators used to join independently computed segments.
     int K = 1;
-    while (K < 32 && (n + K - 1) / K > 16) K *= 2;
+    while (K < 32 && (n + K - 1) / K > 8) K *= 2;
     const int L = (n + K - 1) / K;
     tf.K = K;
     tf.L = L;
