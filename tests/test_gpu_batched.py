@@ -74,6 +74,27 @@ def test_batched_small_matches_oracle(small_ops, precision):
         assert err <= 1e-6
 
 
+@pytest.mark.parametrize("pc", ["mean", "csl"])
+def test_batched_2d_only_matches_oracle(small_ops, pc):
+    """A batch of 2D instances only (n = 33…65, segments of at most 8 rows): the grouped
+    sweep then carries two right-hand sides per thread (a batch with the 1D instance uses
+    one).  Every instance against the oracle's direct solve, and against the single-instance
+    solve (same iterations, solutions within 1e-9)."""
+    ops = small_ops[:5]
+    insts = SMALL[:5]
+    bs = [op.rhs(inst.f) for op, inst in zip(ops, insts)]
+    xs, rc, infos = sg.gmres_batched(ops, bs, restart=30, maxit=600, pc=pc, precision="f64", tol=1e-9)
+    assert rc == sg.SG_OK
+    for op, inst, b, x, info in zip(ops, insts, bs, xs, infos):
+        S, xref = ref(inst)
+        xh = to_host(x)
+        err = np.linalg.norm(xh - xref) / np.linalg.norm(xref)
+        assert info["converged"] == 1 and err <= 1e-6, (inst.name, err)
+        x1, i1 = op.gmres(b, restart=30, maxit=600, pc=pc, precision="f64", tol=1e-9)
+        assert abs(i1["iters"] - info["iters"]) <= 1
+        assert float((x - x1).abs().max() / x1.abs().max()) <= 1e-9
+
+
 def test_batched_iterations_match_single(small_ops):
     bs = [op.rhs(inst.f) for op, inst in zip(small_ops, SMALL)]
     xs, rc, infos = sg.gmres_batched(small_ops, bs, restart=20, maxit=600, pc="csl", precision="f64", tol=1e-9)
