@@ -314,8 +314,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
             s.hscale.assign(m + 2, 1.0);
             s.st.t_setup = s.c->t_setup_ms;
             s.t0 = std::chrono::steady_clock::now();
-            SG_HIP(hipMemsetAsync(s.x, 0, nv * sizeof(double2), stream));
-            active.push_back(sidx);
+            active.push_back(sidx);   // x is zeroed by the INIT step's grouped copy
         }
         return SG_OK;
     };
@@ -375,6 +374,10 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                 t.a = make_double2(1, 0);
                 t.w = s.V;
                 g_copy.add(t, s.nblk, 32.0 * n);
+                VecTask z = vt_base(s);   // x = 0 (no x, no y)
+                z.a = make_double2(1, 0);
+                z.w = s.x;
+                g_copy.add(z, s.nblk, 16.0 * n);
             } else if (s.phase == END) {
                 VecTask t = vt_base(s);
                 t.V = s.V;

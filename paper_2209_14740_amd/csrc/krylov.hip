@@ -343,7 +343,7 @@ __global__ __launch_bounds__(RB) void k_lincomb_g(const VecTask* __restrict__ ta
     }
 }
 
-// w = a x + b y (y may be null)
+// w = a x + b y (y may be null; a null x reads as zero, so that w = b y or w = 0)
 __global__ __launch_bounds__(RB) void k_axpby_g(const VecTask* __restrict__ tasks, const int* __restrict__ start,
                                                 int ntask) {
     const int t = task_of(start, ntask, blockIdx.x);
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(RB) void k_axpby_g(const VecTask* __restrict__ task
     const long long stride = (long long)g.nblocks * RB;
     const double2 a = g.a, b = g.b;
     for (long long i = (long long)lb * RB + threadIdx.x; i < g.n; i += stride) {
-        const double2 xv = g.x[i];
+        const double2 xv = g.x ? g.x[i] : make_double2(0.0, 0.0);   // no x: w = b·y, or 0
         double2 r = make_double2(a.x * xv.x - a.y * xv.y, a.x * xv.y + a.y * xv.x);
         if (g.y) {
             const double2 yv = g.y[i];
