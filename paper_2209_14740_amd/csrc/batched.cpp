@@ -342,6 +342,10 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         for (auto& gg : g_inv) gg.clear();
         stg.reset();
 
+        // slots in use are the lowest indices (admission takes the first free one): the
+        // per-slot tables below and the coefficient copy-back cover slots [0, nslot) only
+        int nslot = 0;
+        for (int sI : active) nslot = std::max(nslot, sI + 1);
         // scales and least-squares coefficients of this step (device copies in the staging)
         for (int sI : active) {
             const Slot& s = slots[sI];
@@ -349,8 +353,8 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
             if (s.phase == END)
                 for (int i = 0; i < s.k; ++i) y_tab[(size_t)sI * (m + 1) + i] = make_double2(s.y[i].real(), s.y[i].imag());
         }
-        const size_t off_scale = stg.put(hscale_tab.data(), hscale_tab.size() * sizeof(double));
-        const size_t off_y = stg.put(y_tab.data(), y_tab.size() * sizeof(double2));
+        const size_t off_scale = stg.put(hscale_tab.data(), (size_t)nslot * (m + 2) * sizeof(double));
+        const size_t off_y = stg.put(y_tab.data(), (size_t)nslot * (m + 1) * sizeof(double2));
         // device addresses are only known after ensure(); keep offsets and patch below
         auto dscale = [&](int sI) { return reinterpret_cast<const double*>(stg.dev + off_scale) + (size_t)sI * (m + 2); };
         auto dy = [&](int sI) { return reinterpret_cast<const double2*>(stg.dev + off_y) + (size_t)sI * (m + 1); };
@@ -567,7 +571,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
             return rc;
         if ((rc = launch_reduce_grouped(stg.dtasks(g_redn), stg.dstart(g_redn), g_redn.n(), g_redn.total(), 1, stream)))
             return rc;
-        SG_HIP(hipMemcpyAsync(h_coef, d_coef, (size_t)S * CW * sizeof(double2), hipMemcpyDeviceToHost, stream));
+        SG_HIP(hipMemcpyAsync(h_coef, d_coef, (size_t)nslot * CW * sizeof(double2), hipMemcpyDeviceToHost, stream));
         if ((rc = wait_stream(stream, step_done))) return rc;
 
         // host part of every active instance
