@@ -168,16 +168,16 @@ int  sg_gmres_batched(int count, const sg_handle* handles, const sg_c64* const* 
  * contents are overwritten) and a temporary device buffer.  *ms_total (may be NULL)
  * receives the measured GPU time. */
 /* Expanded real form (BM x BN real columns; the 256-wide tiles FP32 / BF16x3 only), and
- * the 3M complex form (FP64 only; BM x BN complex columns, three real products per complex
- * multiply-add). */
+ * the 3M complex form (FP64 and FP32; BM x BN complex columns, three real products per
+ * complex multiply-add). */
 enum { SG_GEMM_TILE_128x128 = 0, SG_GEMM_TILE_64x128 = 1, SG_GEMM_TILE_64x64 = 2, SG_GEMM_TILE_64x32 = 3,
        SG_GEMM_TILE_32x64 = 4, SG_GEMM_TILE_3M_32x32 = 5, SG_GEMM_TILE_3M_64x32 = 6, SG_GEMM_TILE_3M_32x64 = 7,
        SG_GEMM_TILE_3M_64x64 = 8, SG_GEMM_TILE_64x256 = 9, SG_GEMM_TILE_128x256 = 10 };
 int  sg_autotune(int count, const sg_handle* handles, int precision, int reps, double* ms_total,
                  hipStream_t stream);
 /* Read (-1 if absent) or set one entry of the autotuner table; sg_tune_set returns
- * SG_EINVAL for a shape not available in that precision (3M shapes: FP64 only; 64x256 and
- * 128x256: FP32 and BF16x3 only). */
+ * SG_EINVAL for a shape not available in that precision (3M shapes: FP64 and FP32; 64x256
+ * and 128x256: FP32 and BF16x3 only). */
 int  sg_tune_get(int n, int Q, int precision);
 int  sg_tune_set(int n, int Q, int precision, int tile);
 

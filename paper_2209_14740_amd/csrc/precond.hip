@@ -265,26 +265,31 @@ __device__ __forceinline__ void gemm_tile(const GemmTask& g, int tile, Lds<MODE,
         }
 }
 
-// 3M complex product, FP64: C = A·B with complex A [M][K] (interleaved), B [K][N] given as
-// two real n-major planes Br, Bi.  Per 16×16 complex output block and K step:
-// P1 += Ar·Br, P2 += Ai·Bi, P3 += (Ar+Ai)·(Br+Bi) on v_mfma_f64_16x16x4f64; then
-// Re = P1 − P2, Im = P3 − P1 − P2.  Three real products per complex multiply-add instead of
-// the four of the expanded real form.  BM = 32·WM complex rows, BN = 32·WN complex columns,
-// BK3 complex k per LDS stage; LDS holds the real and imaginary planes only, the sums are
-// formed in registers after the LDS reads (a third less LDS traffic than staging them).
+// 3M complex product, FP64 or FP32: C = A·B with complex A [M][K] (interleaved FP64), B
+// [K][N] given as two real n-major planes Br, Bi in the compute precision.  Per 16×16
+// complex output block and K step: P1 += Ar·Br, P2 += Ai·Bi, P3 += (Ar+Ai)·(Br+Bi) on
+// v_mfma_f64_16x16x4f64 (v_mfma_f32_16x16x4f32); then Re = P1 − P2, Im = P3 − P1 − P2, formed
+// in FP64.  Three real products per complex multiply-add instead of the four of the
+// expanded real form.  BM = 32·WM complex rows, BN = 32·WN complex columns, BK3 complex k
+// per LDS stage; LDS holds the real and imaginary planes only, the sums are formed in
+// registers after the LDS reads (a third less LDS traffic than staging them).
 constexpr int BK3 = 16;
 
-template <int BM, int BN>
+template <int MODE, int BM, int BN>
 struct Lds3 {
+    using e_t = typename std::conditional<MODE == MODE_F64, double, float>::type;
     static constexpr int PAD = BK3 + 1;
-    double ar[BM * PAD], ai[BM * PAD];
-    double br[BN * PAD], bi[BN * PAD];
+    e_t ar[BM * PAD], ai[BM * PAD];
+    e_t br[BN * PAD], bi[BN * PAD];
 };
 
-template <int WM, int WN>
-__device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32 * WM, 32 * WN>& sm) {
+template <int MODE, int WM, int WN>
+__device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<MODE, 32 * WM, 32 * WN>& sm) {
     constexpr int BM = 32 * WM, BN = 32 * WN;
-    constexpr int PAD = Lds3<BM, BN>::PAD;
+    constexpr int PAD = Lds3<MODE, BM, BN>::PAD;
+    using e_t = typename Lds3<MODE, BM, BN>::e_t;
+    using e2_t = typename std::conditional<MODE == MODE_F64, double2, float2>::type;
+    using acc_t = typename std::conditional<MODE == MODE_F64, d4, f4>::type;
     const int M = g.M, N = g.Nc / 2, K = g.Kc / 2;   // complex sizes
     const int tm = tile / g.tiles_n, tn = tile % g.tiles_n;
     const int m0 = tm * BM, n0 = tn * BN;
@@ -292,21 +297,21 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
     const int wm = wv >> 1, wn = wv & 1;
     const int l16 = lane & 15, lq = lane >> 4;
     const double* __restrict__ A = g.A;
-    const double* __restrict__ Br = reinterpret_cast<const double*>(g.Bt0);
-    const double* __restrict__ Bi = reinterpret_cast<const double*>(g.Bt1);
+    const e_t* __restrict__ Br = reinterpret_cast<const e_t*>(g.Bt0);
+    const e_t* __restrict__ Bi = reinterpret_cast<const e_t*>(g.Bt1);
     const long long lda = g.lda, ldb = g.ldb;
 
-    d4 p1[WM][WN], p2[WM][WN], p3[WM][WN];
+    acc_t p1[WM][WN], p2[WM][WN], p3[WM][WN];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = d4{0, 0, 0, 0};
+        for (int j = 0; j < WN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = acc_t{0, 0, 0, 0};
 
     // staging: A tile BM × BK3 complex (BM·BK3/256 double2 per thread); B planes BN × BK3
     // doubles each, loaded as double2 pairs along k (BN·BK3/512 pairs per thread)
     constexpr int PA = BM * BK3 / 256, PB = BN * BK3 / 512, HK = BK3 / 2;
     double2 ra[PA];
-    double2 rbr[PB], rbi[PB];
+    e2_t rbr[PB], rbi[PB];
     auto load_tiles = [&](int k0) {
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
@@ -322,16 +327,16 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
             // K is padded to an even ld with zero columns: a pair is inside or fully zero
             const bool ok = gn < N && gk < K;
             const long long off = (long long)gn * ldb + gk;
-            rbr[p] = ok ? *reinterpret_cast<const double2*>(Br + off) : make_double2(0.0, 0.0);
-            rbi[p] = ok ? *reinterpret_cast<const double2*>(Bi + off) : make_double2(0.0, 0.0);
+            rbr[p] = ok ? *reinterpret_cast<const e2_t*>(Br + off) : e2_t{0, 0};
+            rbi[p] = ok ? *reinterpret_cast<const e2_t*>(Bi + off) : e2_t{0, 0};
         }
     };
     auto store_tiles = [&]() {
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
             const int idx = p * 256 + tid, row = idx / BK3, k = idx % BK3;
-            sm.ar[row * PAD + k] = ra[p].x;
-            sm.ai[row * PAD + k] = ra[p].y;
+            sm.ar[row * PAD + k] = (e_t)ra[p].x;
+            sm.ai[row * PAD + k] = (e_t)ra[p].y;
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
@@ -352,7 +357,7 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
         if (kt + 1 < nk) load_tiles((kt + 1) * BK3);
 #pragma unroll
         for (int kk = 0; kk < BK3; kk += 4) {
-            double xr[WM], xi[WM], xs[WM], yr[WN], yi[WN], ys[WN];
+            e_t xr[WM], xi[WM], xs[WM], yr[WN], yi[WN], ys[WN];
 #pragma unroll
             for (int i = 0; i < WM; ++i) {
                 const int r = (wm * (16 * WM) + i * 16 + l16) * PAD + kk + lq;
@@ -371,13 +376,20 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
             for (int i = 0; i < WM; ++i)
 #pragma unroll
                 for (int j = 0; j < WN; ++j) {
-                    p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[i], yr[j], p1[i][j], 0, 0, 0);
-                    p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[i], yi[j], p2[i][j], 0, 0, 0);
-                    p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[i], ys[j], p3[i][j], 0, 0, 0);
+                    if constexpr (MODE == MODE_F64) {
+                        p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[i], yr[j], p1[i][j], 0, 0, 0);
+                        p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[i], yi[j], p2[i][j], 0, 0, 0);
+                        p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[i], ys[j], p3[i][j], 0, 0, 0);
+                    } else {
+                        p1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[i], yr[j], p1[i][j], 0, 0, 0);
+                        p2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[i], yi[j], p2[i][j], 0, 0, 0);
+                        p3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[i], ys[j], p3[i][j], 0, 0, 0);
+                    }
                 }
         }
     }
-    // the f64 MFMA leaves D[lq + 4v][l16] of each 16×16 block in lane (lq, l16)
+    // the f64 MFMA leaves D[lq + 4v][l16] of each 16×16 block in lane (lq, l16), the f32 one
+    // D[4lq + v][l16]
     double* __restrict__ C = g.C;
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -387,23 +399,25 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<32
             if (col >= N) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm * (16 * WM) + i * 16 + lq + 4 * v;
+                const int rl = (MODE == MODE_F64) ? (lq + 4 * v) : (4 * lq + v);
+                const int row = m0 + wm * (16 * WM) + i * 16 + rl;
                 if (row < M) {
-                    const double re = p1[i][j][v] - p2[i][j][v];
-                    const double im = p3[i][j][v] - p1[i][j][v] - p2[i][j][v];
+                    const double q1 = (double)p1[i][j][v], q2 = (double)p2[i][j][v], q3 = (double)p3[i][j][v];
+                    const double re = q1 - q2;
+                    const double im = q3 - q1 - q2;
                     *reinterpret_cast<double2*>(C + (long long)row * g.ldc + 2 * col) = make_double2(re, im);
                 }
             }
         }
 }
 
-template <int WM, int WN>
+template <int MODE, int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm3m(GemmTask g) {
-    __shared__ Lds3<32 * WM, 32 * WN> sm;
+    __shared__ Lds3<MODE, 32 * WM, 32 * WN> sm;
     const int per = gridDim.x / 8;
     const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= g.tiles_m * g.tiles_n) return;
-    gemm3m_tile<WM, WN>(g, tile, sm);
+    gemm3m_tile<MODE, WM, WN>(g, tile, sm);
 }
 
 // Single problem; blocks are dispatched round-robin over the 8 XCDs, so the tile index is
@@ -442,16 +456,16 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
     gemm_tile<MODE, WM, WN>(g, v - start[t], sm);
 }
 
-template <int WM, int WN>
+template <int MODE, int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm3m_grouped(const GemmTask* __restrict__ tasks,
                                                         const int* __restrict__ start, int ntask, int total) {
-    __shared__ Lds3<32 * WM, 32 * WN> sm;
+    __shared__ Lds3<MODE, 32 * WM, 32 * WN> sm;
     const int per = gridDim.x / 8;
     const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (v >= total) return;
     const int t = find_task(start, ntask, v);
     const GemmTask g = tasks[t];
-    gemm3m_tile<WM, WN>(g, v - start[t], sm);
+    gemm3m_tile<MODE, WM, WN>(g, v - start[t], sm);
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -814,8 +828,8 @@ static void expand_bt(int N, const std::vector<cplx>& B /* [k][n] */, std::vecto
         }
 }
 
-// 3M planes of the complex N×N matrix B[k][n]: n-major [n][k] rows of ld doubles (zero
-// padded), Re and Im one after the other.
+// 3M planes of the complex N×N matrix B[k][n]: n-major [n][k] rows of ld values (zero
+// padded), Re and Im one after the other, in FP64 and in FP32.
 static int upload_planes(DenseB& d, int N, const std::vector<cplx>& B, int ld) {
     const size_t plane = (size_t)N * ld;
     std::vector<double> h(2 * plane, 0.0);
@@ -825,8 +839,12 @@ static int upload_planes(DenseB& d, int N, const std::vector<cplx>& B, int ld) {
             h[(size_t)n * ld + k] = b.real();
             h[plane + (size_t)n * ld + k] = b.imag();
         }
+    std::vector<float> hf(h.size());
+    for (size_t i = 0; i < h.size(); ++i) hf[i] = (float)h[i];
     SG_HIP(hipMalloc(&d.p3, h.size() * sizeof(double)));
     SG_HIP(hipMemcpy(d.p3, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    SG_HIP(hipMalloc(&d.p3f, hf.size() * sizeof(float)));
+    SG_HIP(hipMemcpy(d.p3f, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
     return SG_OK;
 }
 
@@ -888,10 +906,10 @@ GemmTask make_gemm_task(int precision, const double* A, long long lda, const Den
     g.Bt0 = precision == SG_PREC_F64 ? (const void*)B.f64
           : precision == SG_PREC_F32 ? (const void*)B.f32 : (const void*)B.bf_hi;
     g.Bt1 = precision == SG_PREC_BF16X3 ? (const void*)B.bf_lo : nullptr;
-    if (gemm_cfg_3m(cfg)) {   // 3M planes, FP64
+    if (gemm_cfg_3m(cfg)) {   // 3M planes, FP64 or FP32
         const size_t plane = (size_t)N * bexp_ld(N);
-        g.Bt0 = B.p3;
-        g.Bt1 = B.p3 + plane;
+        g.Bt0 = precision == SG_PREC_F64 ? (const void*)B.p3 : (const void*)B.p3f;
+        g.Bt1 = precision == SG_PREC_F64 ? (const void*)(B.p3 + plane) : (const void*)(B.p3f + plane);
     }
     g.lda = 2 * lda;
     g.ldc = 2 * ldc;
@@ -931,14 +949,15 @@ static void launch_gemm_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks,
 #undef SG_GEMM_CFG
 }
 
+template <int MODE>
 static void launch_gemm3m_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks, const int* d_start, int ntask,
                               int total, hipStream_t st) {
     const int nt = d_tasks ? total : g.tiles_m * g.tiles_n;
     const dim3 grid(((nt + 7) / 8) * 8), blk(256);
 #define SG_GEMM3(C_, WM_, WN_)                                                                              \
     case C_:                                                                                                \
-        if (d_tasks) hipLaunchKernelGGL((k_gemm3m_grouped<WM_, WN_>), grid, blk, 0, st, d_tasks, d_start, ntask, total); \
-        else hipLaunchKernelGGL((k_gemm3m<WM_, WN_>), grid, blk, 0, st, g);                                    \
+        if (d_tasks) hipLaunchKernelGGL((k_gemm3m_grouped<MODE, WM_, WN_>), grid, blk, 0, st, d_tasks, d_start, ntask, total); \
+        else hipLaunchKernelGGL((k_gemm3m<MODE, WM_, WN_>), grid, blk, 0, st, g);                                    \
         break;
     switch (cfg) {
         SG_GEMM3(5, 1, 1)
@@ -954,7 +973,8 @@ static int dispatch_gemm(int precision, int cfg, const GemmTask& g, const GemmTa
                          int ntask, int total, hipStream_t st) {
     if (!gemm_cfg_valid(cfg, precision)) return fail(SG_EINVAL, "GEMM tile configuration not available in this precision");
     if (gemm_cfg_3m(cfg)) {
-        launch_gemm3m_cfg(cfg, g, d_tasks, d_start, ntask, total, st);
+        if (precision == SG_PREC_F64) launch_gemm3m_cfg<MODE_F64>(cfg, g, d_tasks, d_start, ntask, total, st);
+        else launch_gemm3m_cfg<MODE_F32>(cfg, g, d_tasks, d_start, ntask, total, st);
         SG_HIP(hipGetLastError());
         return SG_OK;
     }

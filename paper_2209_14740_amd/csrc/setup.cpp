@@ -438,6 +438,8 @@ Ctx::~Ctx() {
     (void)hipFree(inv.bf_lo);
     (void)hipFree(fwd.p3);
     (void)hipFree(inv.p3);
+    (void)hipFree(fwd.p3f);
+    (void)hipFree(inv.p3f);
     for (auto& t : tri) free_tri(t);
     (void)hipFree(ws.V);
     (void)hipFree(ws.Z);

@@ -64,6 +64,7 @@ struct DenseB {
     uint16_t* bf_hi = nullptr; // [2N][2N] bf16 bits, packed for the MFMA B operand
     uint16_t* bf_lo = nullptr;
     double* p3 = nullptr;      // 3M planes of B (n-major [n][k], ld = bexp_ld(N)): Re, Im
+    float* p3f = nullptr;      // the same in FP32
 };
 
 // One dense problem C[M][Nc] = A[M][Kc] · B of the preconditioner transforms, Bt[Nc][Kc]
@@ -78,13 +79,13 @@ struct GemmTask {
 };
 // GEMM tile shapes: the expanded real form (BM × BN real columns, every precision) 0:
 // 128×128, 1: 64×128, 2: 64×64, 3: 64×32, 4: 32×64, 9: 64×256, 10: 128×256 (FP32 / BF16x3);
-// the 3M complex form (BM × BN complex columns, FP64 only) 5: 32×32, 6: 64×32, 7: 32×64,
+// the 3M complex form (BM × BN complex columns, FP64 and FP32) 5: 32×32, 6: 64×32, 7: 32×64,
 // 8: 64×64.
 enum { SG_GEMM_NCFG = 11 };
 inline bool gemm_cfg_3m(int cfg) { return cfg >= 5 && cfg <= 8; }
 inline bool gemm_cfg_valid(int cfg, int precision) {
     if (cfg < 0 || cfg >= SG_GEMM_NCFG) return false;
-    if (gemm_cfg_3m(cfg)) return precision == SG_PREC_F64;
+    if (gemm_cfg_3m(cfg)) return precision == SG_PREC_F64 || precision == SG_PREC_F32;
     if (cfg >= 9) return precision != SG_PREC_F64;
     return true;
 }

@@ -157,7 +157,7 @@ def test_autotune_fills_table(small_ops):
     assert ms > 0
     for op in small_ops:
         if op.dim == 2:
-            assert sg.tune_get(op.n, op.Q, "bf16x3") in (0, 1, 2, 3, 4, 9, 10)   # 3M shapes are FP64 only
+            assert sg.tune_get(op.n, op.Q, "bf16x3") in (0, 1, 2, 3, 4, 9, 10)   # 3M shapes: FP64 and FP32
 
 
 def test_batched_config4_sample_full_size():
