@@ -128,6 +128,28 @@ def test_batched_tile_shapes(small_ops, tile):
                 sg.tune_set(op.n, op.Q, "f64", "128x128")
 
 
+@pytest.mark.parametrize("tile", ["3m32x32", "3m64x64", "64x256"])
+def test_batched_f32_tile_shapes(small_ops, tile):
+    """The FP32 preconditioner of the batched solver in the 3M form and the wide real-form
+    tile (grouped launches over instances of several shapes) against the oracle."""
+    for op in small_ops:
+        if op.dim == 2:
+            sg.tune_set(op.n, op.Q, "f32", tile)
+    try:
+        bs = [op.rhs(inst.f) for op, inst in zip(small_ops, SMALL)]
+        xs, rc, infos = sg.gmres_batched(small_ops, bs, restart=30, maxit=600, pc="mean", precision="f32",
+                                         tol=1e-10)
+        assert rc == sg.SG_OK
+        for inst, x in zip(SMALL, xs):
+            _, xref = ref(inst)
+            xh = to_host(x)
+            assert np.linalg.norm(xh - xref) / np.linalg.norm(xref) <= 1e-8
+    finally:
+        for op in small_ops:
+            if op.dim == 2:
+                sg.tune_set(op.n, op.Q, "f32", "128x128")
+
+
 def test_batched_edge_cases(small_ops):
     ops = small_ops[:3]
     bs = [op.rhs(inst.f) for op, inst in zip(ops, SMALL[:3])]
