@@ -153,7 +153,8 @@ int  sg_fgmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opt
  * [1, 63]; opts->hist is ignored.  stats: host array of `count` entries or NULL
  * (t_precond / t_matvec / t_orth are 0; t_total is the wall time from admission to
  * completion).  The GEMM tile shape of each instance comes from the autotuner table
- * (sg_autotune / sg_tune_set), 128×128 when absent.  Returns SG_OK if every instance
+ * (sg_autotune / sg_tune_set), else a size-based default (3M 32×32 or 64×64 in FP64 and
+ * FP32, 64×128 or 64×256 in BF16x3).  Returns SG_OK if every instance
  * converged, SG_ENOTCONV if some did not (their stats say which: converged = 0, a
  * non-finite value gives relres_true = NaN), negative on invalid arguments or a HIP
  * failure.  Kernel timing, when enabled, is recorded in the profiler of handles[0]. */

@@ -415,8 +415,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                 TriTask tt = make_tri_task(f, s.zt, c->n, c->n, c->Q, 1, tri_nr);
                 g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
             } else {
-                int cfg = tune_get(c->n, c->Q, prec);
-                if (!gemm_cfg_valid(cfg, prec)) cfg = 0;
+                const int cfg = gemm_cfg_for(c->n, c->Q * c->n, prec);
                 const int M = c->Q * c->n;
                 GemmTask gf = make_gemm_task(prec, reinterpret_cast<const double*>(pi.second), c->n, c->fwd, c->n,
                                              reinterpret_cast<double*>(c->d_tmp_pc), c->tld, M, cfg);

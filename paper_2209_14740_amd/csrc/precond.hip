@@ -988,11 +988,24 @@ static int dispatch_gemm(int precision, int cfg, const GemmTask& g, const GemmTa
     return SG_OK;
 }
 
+// Tile shape of an untuned (n, Q, precision), from the autotuner's choices on the
+// configurations: the 3M form in FP64 and FP32 (32×32 complex tiles, 64×64 once there are
+// more than about eight rounds of 32×32 tiles over the chip), the 64×128 real-form tile in
+// BF16x3 (64×256 for n > 384).
+int gemm_default_cfg(int N, int M, int precision) {
+    if (precision == SG_PREC_BF16X3) return N > 384 ? 9 : 1;
+    const long long tiles32 = (long long)((M + 31) / 32) * ((N + 31) / 32);
+    return tiles32 > 10240 ? 8 : 5;
+}
+
+int gemm_cfg_for(int N, int M, int precision) {
+    const int cfg = tune_get(N, M / N, precision);   // the autotuner's choice when tuned
+    return gemm_cfg_valid(cfg, precision) ? cfg : gemm_default_cfg(N, M, precision);
+}
+
 static int launch_gemm(int precision, const double* A, long long lda, const DenseB& B, int N, double* C,
                        long long ldc, int M, hipStream_t st) {
-    // tile shape from the autotuner table when this (n, Q, precision) was tuned
-    int cfg = tune_get(N, M / N, precision);
-    if (!gemm_cfg_valid(cfg, precision)) cfg = 0;
+    const int cfg = gemm_cfg_for(N, M, precision);
     const GemmTask g = make_gemm_task(precision, A, lda, B, N, C, ldc, M, cfg);
     // algorithmic flops: 8 real flops per complex multiply-add, 6 with the 3M form
     const double cmacs = (double)M * N * N;

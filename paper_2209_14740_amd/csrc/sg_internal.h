@@ -221,6 +221,10 @@ void tune_set(int n, int Q, int precision, int cfg);
 int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, hipStream_t st);
 int upload_dense_b(Ctx* c, hipStream_t st);
 void gemm_tiles(int cfg, int M, int Nc, int* tiles_m, int* tiles_n);
+// tile shape of a transform with N×N operator and M rows: the autotuner's choice, else a
+// size-based default
+int gemm_default_cfg(int N, int M, int precision);
+int gemm_cfg_for(int N, int M, int precision);
 // lda, ldc: row lengths of A and C in complex elements
 GemmTask make_gemm_task(int precision, const double* A, long long lda, const DenseB& B, int N, double* C,
                         long long ldc, int M, int cfg);
