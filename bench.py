@@ -34,7 +34,7 @@ KIND = {0: "sg_apply", 1: "fd_gemm", 2: "tri_sweep", 3: "cgs2_multidot", 4: "cgs
 # HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a copy kernel of known size.  Valid only for the kernel
 # source it was measured on (sha256 of the file below); otherwise reported as null.
-TRAFFIC = {"fd_gemm": {"bytes": 82.79e6, "file": "precond.hip", "src": "7b2025568982665c"}}
+TRAFFIC = {"fd_gemm": {"bytes": 82.78e6, "file": "precond.hip", "src": "a01a935f80e55c0e"}}
 
 
 def _src_hash(name):
