@@ -68,15 +68,16 @@ def test_net_shapes_and_params_round_trip(small_net):
     np.testing.assert_array_equal(small_net.get_params(), th)
 
 
-@pytest.mark.parametrize("H", [16, 20])
+@pytest.mark.parametrize("H", [16, 20, 132, 256])
 def test_net_forward_matches_oracle(small_net, H):
     th = random_theta(1)
     small_net.set_params(th.astype(np.float32))
     rng = np.random.default_rng(2)
-    x = rng.standard_normal((3, H, H, CIN))
+    nb = 3 if H < 64 else 1   # larger sizes: blocks of pixels within one row (W = 256) and across rows
+    x = rng.standard_normal((nb, H, H, CIN))
     y = small_net.forward_nhwc(dev32(x)).cpu().numpy()
     th64 = th.astype(np.float32).astype(np.float64)
-    for b in range(3):
+    for b in range(nb):
         e_r = rel(y[b], unet.forward(th64, x[b], COUT, rnd=unet.bf16_round))
         e_x = rel(y[b], unet.forward(th64, x[b], COUT))
         print("forward H=%d sample %d rel err vs rounded %.3e, vs exact %.3e" % (H, b, e_r, e_x), flush=True)
