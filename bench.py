@@ -33,8 +33,9 @@ KIND = {0: "sg_apply", 1: "fd_gemm", 2: "tri_sweep", 3: "cgs2_multidot", 4: "cgs
 
 # HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a copy kernel of known size.  Valid only for the kernel
-# source it was measured on (sha256 of the file below); otherwise reported as null.
-TRAFFIC = {"fd_gemm": {"bytes": 82.78e6, "file": "precond.hip", "src": "a01a935f80e55c0e"}}
+# source it was measured on (sha256 of the file below) and the tile shape the autotuner
+# chose then; otherwise reported as null.
+TRAFFIC = {"fd_gemm": {"bytes": 82.78e6, "file": "precond.hip", "src": "a01a935f80e55c0e", "tile": 5}}
 
 
 def _src_hash(name):
@@ -73,7 +74,7 @@ def time_solve(op, b, x, steps, warmup, flexible, **kw):
     return (t1 - t0) / steps, infos[-1]
 
 
-def roofline_of(prof, precision="f64"):
+def roofline_of(prof, precision="f64", tile=None):
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]
     avg_ms = d["ms"] / d["launches"]
@@ -87,7 +88,8 @@ def roofline_of(prof, precision="f64"):
         r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     r["frac"] = r["achieved"] / r["peak"]
     t = TRAFFIC.get(dom)
-    r["traffic"] = t["bytes"] if t and t.get("src") == _src_hash(t["file"]) else None
+    ok = t and t.get("src") == _src_hash(t["file"]) and t.get("tile", tile) == tile
+    r["traffic"] = t["bytes"] if ok else None
     r["kernel"] = dom
     r["avg_launch_ms"] = avg_ms
     r["work_per_launch"] = per_launch
@@ -389,6 +391,9 @@ def main():
                     help="run only the config-3 mixed-precision leg; prints its JSON object")
     ap.add_argument("--matvec-only", action="store_true",
                     help="run only the SG-operator bandwidth leg; prints its JSON object")
+    ap.add_argument("--f64-tile", default=None,
+                    help="force this FP64 transform tile after autotuning (e.g. 3m32x32), so that "
+                         "profiler runs measure the same kernel as the timed run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one elementwise copy kernel of 1 GiB in and 1 GiB out first (HBM counter "
                          "calibration under rocprofv3 --pmc)")
@@ -438,6 +443,8 @@ def main():
     t0 = time.perf_counter()
     for prec in ("f64", "f32", "bf16x3"):
         sg.autotune([op], prec, reps=5)
+    if args.f64_tile:
+        sg.tune_set(op.n, op.Q, "f64", args.f64_tile)
     tune_s = time.perf_counter() - t0
     tiles = {p_: sg.tune_get(op.n, op.Q, p_) for p_ in ("f64", "f32", "bf16x3")}
 
@@ -481,7 +488,7 @@ def main():
         forms[name] = {"s": t, "iters": inf["iters"], "relres_true": inf["relres_true"],
                        "max_rel_diff_vs_plain": err, "speedup_vs_plain": t_plain / t}
 
-    roof = roofline_of(prof_dom)
+    roof = roofline_of(prof_dom, "f64", tiles["f64"])
     out = {
         "metric": METRIC,
         "value": t_plain,
