@@ -23,7 +23,6 @@
 
 namespace sgi {
 
-
 int ensure_workspace(Ctx* c, int m, bool flexible) {
     Workspace& w = c->ws;
     if (w.V && w.m >= m && (!flexible || w.Z)) return SG_OK;
@@ -52,9 +51,7 @@ int ensure_workspace(Ctx* c, int m, bool flexible) {
     return SG_OK;
 }
 
-// Wait until the work queued on st has finished.  With an event the host polls it (the
-// waits of the Arnoldi loop are a few hundred microseconds apart, and a blocking wait
-// adds tens of microseconds of wake-up latency to each); without one, a blocking wait.
+// Spin until ev has completed.
 static int poll_event(hipEvent_t ev) {
     hipError_t e;
     while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
@@ -63,6 +60,9 @@ static int poll_event(hipEvent_t ev) {
     return SG_OK;
 }
 
+// Wait until the work queued on st has finished.  With an event the host polls it (the
+// waits of the Arnoldi loop are a few hundred microseconds apart, and a blocking wait
+// adds tens of microseconds of wake-up latency to each); without one, a blocking wait.
 int wait_stream(hipStream_t st, hipEvent_t ev) {
     if (!ev) {
         SG_HIP(hipStreamSynchronize(st));
