@@ -180,7 +180,7 @@ def test_precond_f32_3m_tiles(key, tile):
         sg.tune_set(op.n, op.Q, "f32", "128x128")
 
 
-@pytest.mark.parametrize("tile", ["64x256", "128x256", "128x128", "64x64"])
+@pytest.mark.parametrize("tile", ["64x256", "128x256", "128x128", "64x64", "64x32", "32x64"])
 @pytest.mark.parametrize("precision,tol", [("f32", 2e-4), ("bf16x3", 2e-3)])
 @pytest.mark.parametrize("key", ["2d_n150_s3_r3", "2d_n37_s2_r4"])
 def test_precond_mixed_wide_tiles(key, precision, tol, tile):
