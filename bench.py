@@ -321,6 +321,38 @@ def mixed_config3(log):
     return out
 
 
+def degree_sweep(log, degrees=range(1, 9)):
+    """Constant-mean analogue of the paper's degree study (three random variables, 129² nodes,
+    point source): for each total degree, A_0- and M_0-preconditioned GMRES(200) to the true
+    relative residual 1e-8 from x=0 (one warm-up and two timed solves each) and the SG
+    operator's bandwidth at that Q."""
+    import torch
+    from paper_2209_14740_amd import sg
+    from workloads import degree_sweep_instance
+    rows = []
+    for r in degrees:
+        inst = degree_sweep_instance(r)
+        op = sg.SG.from_instance(inst)
+        b = op.rhs(inst.f)
+        x = op.empty()
+        rec = {"degree": r, "Q": op.Q, "unknowns": op.size}
+        for pc in ("mean", "csl"):
+            t, info = time_solve(op, b, x, 2, 1, False, pc=pc, precision="f64", restart=200, maxit=1000, tol=1e-8)
+            rec[pc] = {"s": t, "iters": info["iters"], "relres_true": info["relres_true"]}
+        op.close()
+        del x, b
+        mv = matvec_bandwidth(inst, 10)
+        rec["apply_us"] = mv["avg_launch_ms"] * 1e3
+        rec["apply_frac_hbm"] = mv["frac"]
+        rows.append(rec)
+        log("degree sweep r=%d Q=%d: A0 %d it %.2f ms, M0 %d it %.2f ms, operator %.1f us (%.0f %% HBM)"
+            % (r, op.Q, rec["mean"]["iters"], rec["mean"]["s"] * 1e3, rec["csl"]["iters"], rec["csl"]["s"] * 1e3,
+               rec["apply_us"], 100 * rec["apply_frac_hbm"]))
+    torch.cuda.empty_cache()
+    return {"workload": "2D 129x129 nodes, kbar=20, sigma=2, s=3 sine modes, point source at the centre, "
+                        "degree 1..8 (Q up to 165); GMRES(200) to true relres 1e-8 from x=0", "rows": rows}
+
+
 def paper_context():
     """The paper's own timed 1D experiment (Section 6: k̄ = 50, θ = 0.1, degree 3, point
     source, A_0 as right preconditioner, full GMRES to 1e-12), for context only."""
@@ -391,6 +423,9 @@ def main():
                     help="run only the config-3 mixed-precision leg; prints its JSON object")
     ap.add_argument("--matvec-only", action="store_true",
                     help="run only the SG-operator bandwidth leg; prints its JSON object")
+    ap.add_argument("--no-degree-sweep", action="store_true")
+    ap.add_argument("--degree-sweep-only", action="store_true",
+                    help="run only the degree sweep (s=3, 129x129, degree 1..8); prints its JSON object")
     ap.add_argument("--f64-tile", default=None,
                     help="force this FP64 transform tile after autotuning (e.g. 3m32x32), so that "
                          "profiler runs measure the same kernel as the timed run")
@@ -425,6 +460,9 @@ def main():
         return
     if args.matvec_only:
         print(json.dumps({"matvec": matvec_bandwidth(config3(), 20)}))
+        return
+    if args.degree_sweep_only:
+        print(json.dumps({"degree_sweep": degree_sweep(log)}))
         return
     if args.batched_only:
         print(json.dumps({"batched": batched_config4(args.batched_count, log)}))
@@ -520,6 +558,9 @@ def main():
     if not args.no_mixed3:
         log("mixed-precision forms on config 3")
         out["mixed_config3"] = mixed_config3(log)
+    if not args.no_degree_sweep:
+        log("degree sweep (s=3, 129x129, degree 1..8)")
+        out["degree_sweep"] = degree_sweep(log)
     log("paper context (Section 6, 1D)")
     out["paper_context"] = paper_context()
     if not args.no_batched:

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsg.so")
 
-SOURCES = ["apply_spec_g0.hip", "apply_spec_g1.hip", "apply_spec_g2.hip", "apply_spec_g3.hip", "setup.cpp",
+SOURCES = ["apply_spec_g0.hip", "apply_spec_g1.hip", "apply_spec_g2.hip", "apply_spec_g3.hip", "apply_spec_g4.hip",
+           "setup.cpp",
            "prof.cpp", "abi.cpp", "gmres.cpp", "batched.cpp", "net_host.cpp", "net.hip", "apply.hip", "precond.hip", "krylov.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

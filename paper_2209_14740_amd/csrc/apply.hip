@@ -219,7 +219,7 @@ int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st) {
         KScope ks(SG_K_APPLY, (double)c->P * (32.0 * c->Q + 8.0 * c->s), st);
         const int sv = c->s, rv = c->degree;
         if (dispatch_spec_g0(sv, rv, a, st) || dispatch_spec_g1(sv, rv, a, st) ||
-            dispatch_spec_g2(sv, rv, a, st) || dispatch_spec_g3(sv, rv, a, st)) {
+            dispatch_spec_g2(sv, rv, a, st) || dispatch_spec_g3(sv, rv, a, st) || dispatch_spec_g4(sv, rv, a, st)) {
             SG_HIP(hipGetLastError());
             return SG_OK;
         }

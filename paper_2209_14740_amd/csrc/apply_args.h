@@ -38,15 +38,18 @@ int dispatch_spec_g0(int s, int r, const ApplyArgs& a, hipStream_t st);
 int dispatch_spec_g1(int s, int r, const ApplyArgs& a, hipStream_t st);
 int dispatch_spec_g2(int s, int r, const ApplyArgs& a, hipStream_t st);
 int dispatch_spec_g3(int s, int r, const ApplyArgs& a, hipStream_t st);
+int dispatch_spec_g4(int s, int r, const ApplyArgs& a, hipStream_t st);
 // Grouped forms over tasks of one shape (2D); with d == nullptr only report availability.
 // Task t needs spec_row_blocks(n) blocks.
 int dispatch_spec_grouped_g0(int s, int r, const ApplyArgs* d, const int* ds, int nt, int tot, hipStream_t st);
 int dispatch_spec_grouped_g1(int s, int r, const ApplyArgs* d, const int* ds, int nt, int tot, hipStream_t st);
 int dispatch_spec_grouped_g2(int s, int r, const ApplyArgs* d, const int* ds, int nt, int tot, hipStream_t st);
 int dispatch_spec_grouped_g3(int s, int r, const ApplyArgs* d, const int* ds, int nt, int tot, hipStream_t st);
+int dispatch_spec_grouped_g4(int s, int r, const ApplyArgs* d, const int* ds, int nt, int tot, hipStream_t st);
 inline int dispatch_spec_grouped(int s, int r, const ApplyArgs* d, const int* ds, int nt, int tot, hipStream_t st) {
     return dispatch_spec_grouped_g0(s, r, d, ds, nt, tot, st) || dispatch_spec_grouped_g1(s, r, d, ds, nt, tot, st) ||
-           dispatch_spec_grouped_g2(s, r, d, ds, nt, tot, st) || dispatch_spec_grouped_g3(s, r, d, ds, nt, tot, st);
+           dispatch_spec_grouped_g2(s, r, d, ds, nt, tot, st) || dispatch_spec_grouped_g3(s, r, d, ds, nt, tot, st) ||
+           dispatch_spec_grouped_g4(s, r, d, ds, nt, tot, st);
 }
 inline int spec_row_blocks(int n) { return ((n + 31) / 32) * ((n + 3) / 4); }
 

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 from oracle import assemble, krylov, precond
-from workloads import config1, config2, config3, small_2d
+from workloads import config1, config2, config3, degree_sweep_instance, small_2d
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +75,44 @@ SMALL = {
     "2d_n300_s1_r1": lambda: small_2d(n=300, kbar=16.0, sigma=0.8, s=1, degree=1),
     # n a multiple of 8: the preconditioner intermediate has no row padding
     "2d_n48_s2_r2": lambda: small_2d(n=48, kbar=8.0, sigma=0.8, s=2, degree=2),
+    # high degree, three random variables (Q = 84 and 165)
+    "2d_n40_s3_r6": lambda: small_2d(n=40, kbar=10.0, sigma=1.0, s=3, degree=6),
+    "2d_n33_s3_r8": lambda: small_2d(n=33, kbar=10.0, sigma=1.0, s=3, degree=8),
 }
+
+
+@pytest.mark.parametrize("degree", [5, 8])
+def test_high_degree_gmres_matches_oracle(degree):
+    """Degree 5 and 8 with three random variables (Q = 56, 165): the GPU A_0-GMRES solution
+    against the oracle's A_0-GMRES solution to 1e-12, and its true residual recomputed with
+    the oracle's assembled matrix."""
+    key = "2d_n33_s3_r%d" % degree
+    inst = small_2d(n=33, kbar=10.0, sigma=1.0, s=3, degree=degree)
+    print("high degree", key, flush=True)
+    S = oracle_sys(key, inst)
+    xref, info_ref = krylov.gmres(lambda v: S.A @ v, S.b, precond.mean_value(S), restart=80, tol=1e-12, maxit=600)
+    assert info_ref.converged
+    op = sg.SG.from_instance(inst)
+    x, info = op.gmres(op.rhs(inst.f), restart=80, maxit=600, pc="mean", precision="f64", tol=1e-10)
+    xh = to_host(x)
+    rel = np.linalg.norm(S.b - S.A @ xh) / np.linalg.norm(S.b)
+    err = np.linalg.norm(xh - xref) / np.linalg.norm(xref)
+    print(key, info["iters"], rel, err, flush=True)
+    assert info["converged"] == 1 and rel <= 1e-10 * 1.05 and err <= 1e-6
+
+
+def test_degree_sweep_operator_sampled():
+    """The degree-8 instance of the degree sweep at its bench size (129², Q = 165): sampled
+    rows against the oracle's point-by-point evaluation."""
+    inst = degree_sweep_instance(8)
+    op = sg.SG.from_instance(inst)
+    P, n = inst.points, inst.n
+    x = rand_vec(op.size, 4)
+    y = to_host(op.apply(to_dev(x))).reshape(op.Q, P)
+    rng = np.random.default_rng(5)
+    pts = np.array(sorted({0, n - 1, P - n, P - 1, (n // 2) * n + n // 2, 31, 32, 33} | set(rng.integers(0, P, 60).tolist())))
+    ref = assemble.apply_at_points(inst, x, pts)
+    assert np.max(np.abs(y[:, pts] - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
 def test_basis_order_matches_oracle():

@@ -17,6 +17,7 @@ from .configs import (  # noqa: F401
     config4_instances,
     config5_instance,
     small_2d,
+    degree_sweep_instance,
     one_d_paper,
     wedge_instance,
     MODES,

@@ -154,6 +154,14 @@ def small_2d(n: int = 33, kbar: float = 8.0, sigma: float = 0.8, s: int = 2, deg
                     gaussian_source(n, 2, centre, width), restart=restart, tol=tol)
 
 
+def degree_sweep_instance(degree: int, n: int = 129, kbar: float = 20.0, sigma: float = 2.0) -> Instance:
+    """Constant-mean analogue of the Section 7 degree study (three random variables, 127
+    interior nodes per side, point source at the centre, degree 0..8, Q up to 165): sine
+    mode fields instead of the wedge, so that the mean block has constant k̄."""
+    return Instance("sweep_2d_n%d_s3_r%d" % (n, degree), 2, n, 3, degree, sine_mode_fields(n, kbar, sigma, 3), kbar,
+                    point_source(n, 2), restart=200, tol=1e-8)
+
+
 def config4_instances(count: int = 512, seed0: int = 0) -> list[Instance]:
     """Batched workload: per seed, N∈{63,127,255}, k̄~U[5,30], σ=0.1k̄, s∈{1..4},
     degree∈{2,3,4}, Gaussian (width 0.05) at a uniform point of [0.2,0.8]²."""
