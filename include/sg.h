@@ -24,7 +24,8 @@
  *
  * Threading and streams: one handle serves one stream at a time.  Every call
  * enqueues its work on the given stream; calls that return host results
- * (sg_gmres, sg_fgmres, sg_cgs2, sg_norm) synchronise that stream.
+ * (sg_gmres, sg_fgmres, sg_cgs2, sg_norm, sg_stationary with a history) synchronise
+ * that stream.
  */
 #ifndef SG_H
 #define SG_H
@@ -138,6 +139,20 @@ int  sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts
 typedef int (*sg_precond_cb)(void* user, const sg_c64* r, sg_c64* z, hipStream_t stream);
 int  sg_fgmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
                sg_precond_cb cb, void* user, sg_solve_stats* stats, hipStream_t stream);
+
+/* Stationary iteration with the mean-based block matrix B (eq. stationary_iteration,
+ * Section 5; B = A_0 for pc = SG_PC_MEAN, M_0 for SG_PC_CSL_MEAN):
+ *   x_0 = B^{-1} b,   x_{i+1} = x_i + B^{-1} (b - A x_i),   i = 0 .. iters-1,
+ * all in FP64 (no Krylov workspace beyond two scratch vectors).  It converges when the
+ * spectral radius of I - B^{-1} A is below one (Theorem 5.3 gives a sufficient bound) and
+ * diverges otherwise; the caller judges that from the history.
+ * b, x: device vectors of sg_size(), must not overlap; x is overwritten.
+ * hist: host, may be NULL, else iters+1 doubles: ||b - A x_i|| / ||b|| for i = 0..iters
+ * (each entry costs one stream synchronisation).  A zero b gives x = 0 and a zero
+ * history.  Returns SG_ENONFINITE if a history entry is not finite, SG_EINVAL for bad
+ * arguments (pc not one of the two, iters < 0). */
+int  sg_stationary(sg_handle h, const sg_c64* b, sg_c64* x, int pc, int iters, double* hist,
+                   hipStream_t stream);
 
 /* Batched right-preconditioned GMRES(m) over `count` independent problems of any
  * size (instances of a parametric study, each with its own handle).

@@ -128,6 +128,17 @@ int sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
     })
 }
 
+int sg_stationary(sg_handle h, const sg_c64* b, sg_c64* x, int pc, int iters, double* hist, hipStream_t stream) {
+    SG_TRY({
+        if (!h) return fail(SG_EINVAL, "null handle");
+        Ctx* c = ctx(h);
+        if (int rc = guard_device(c)) return rc;
+        ProfBind pb(c);
+        return sgi::run_stationary(c, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), pc, iters,
+                                   hist, stream);
+    })
+}
+
 int sg_fgmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts, sg_precond_cb cb, void* user,
               sg_solve_stats* stats, hipStream_t stream) {
     SG_TRY({

@@ -349,4 +349,45 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
     return result;
 }
 
+// Stationary iteration B x_{i+1} = b - (A - B) x_i from x_0 = B^{-1} b (eq.
+// stationary_iteration), written as the correction x_{i+1} = x_i + B^{-1}(b - A x_i).
+int run_stationary(Ctx* c, const double2* b, double2* x, int pc, int iters, double* hist, hipStream_t st) {
+    if (!b || !x) return fail(SG_EINVAL, "null argument");
+    if (b == x) return fail(SG_EINVAL, "sg_stationary: b and x must not alias");
+    if (pc != SG_PC_MEAN && pc != SG_PC_CSL_MEAN) return fail(SG_EINVAL, "sg_stationary: pc must be a mean-based block preconditioner");
+    if (iters < 0) return fail(SG_EINVAL, "sg_stationary: iters must be >= 0");
+    int rc = ensure_workspace(c, 1, false);
+    if (rc) return rc;
+    const long long n = c->nvec;
+    double2* r = c->ws.tmp;
+    double2* z = c->ws.tmp + n;
+    const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
+    double bnorm = 0.0;
+    if ((rc = norm_sync(c, b, &bnorm, st))) return rc;
+    if (bnorm == 0.0) {
+        if ((rc = launch_scale_copy(n, 0.0, b, x, st))) return rc;
+        if (hist)
+            for (int i = 0; i <= iters; ++i) hist[i] = 0.0;
+        return wait_stream(st, c->ws.done);
+    }
+    if ((rc = launch_precond(c, pc, SG_PREC_F64, b, x, st))) return rc;
+    for (int i = 0; i <= iters; ++i) {
+        const bool last = i == iters;
+        if (hist || !last) {
+            if ((rc = launch_apply(c, x, r, st))) return rc;
+            if ((rc = launch_axpby(n, one, b, mone, r, r, st))) return rc;   // r = b - A x_i
+        }
+        if (hist) {
+            double rn = 0.0;
+            if ((rc = norm_sync(c, r, &rn, st))) return rc;
+            hist[i] = rn / bnorm;
+            if (!std::isfinite(hist[i])) return fail(SG_ENONFINITE, "sg_stationary: the iteration diverged to a non-finite residual");
+        }
+        if (last) break;
+        if ((rc = launch_precond(c, pc, SG_PREC_F64, r, z, st))) return rc;
+        if ((rc = launch_axpby(n, one, x, one, z, x, st))) return rc;        // x_{i+1} = x_i + B^{-1} r
+    }
+    return SG_OK;
+}
+
 }  // namespace sgi

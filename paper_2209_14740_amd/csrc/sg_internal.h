@@ -284,6 +284,7 @@ int net_precond(Net* n, Ctx* c, int precision, const double2* v, double2* z, hip
 int wait_stream(hipStream_t st, hipEvent_t ev);
 int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_precond_cb cb,
               void* user, bool flexible, sg_solve_stats* st, hipStream_t stream);
+int run_stationary(Ctx* c, const double2* b, double2* x, int pc, int iters, double* hist, hipStream_t st);
 // d_next_scale (device, may be null) receives 1/||w|| after the two passes; the host waits
 // for the coefficients by polling `done` (null: a blocking stream synchronisation); with
 // wait = false (and done given) it only records `done` after the copy

@@ -72,6 +72,7 @@ def lib():
     L.sg_precond.argtypes = [vp, i, i, vp, vp, vp]
     L.sg_gmres.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
     L.sg_fgmres.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), PRECOND_CB, vp, C.POINTER(SolveStats), vp]
+    L.sg_stationary.argtypes = [vp, vp, vp, i, i, C.POINTER(d), vp]
     L.sg_cgs2.argtypes = [ll, i, vp, vp, vp, vp]
     L.sg_norm.argtypes = [ll, vp, C.POINTER(d), vp]
     L.sg_gmres_batched.argtypes = [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
@@ -101,7 +102,7 @@ def lib():
     L.sg_strerror.restype = C.c_char_p
     L.sg_last_error.argtypes = []
     L.sg_last_error.restype = C.c_char_p
-    for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
+    for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres", "sg_stationary",
                  "sg_cgs2", "sg_norm", "sg_set_profiling", "sg_kernel_times", "sg_gmres_batched", "sg_autotune",
                  "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
                  "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step", "sg_net_train_pairs", "sg_net_save",
@@ -200,6 +201,16 @@ class SG:
         check(lib().sg_precond(self._h, PC[pc], PREC[precision], C.c_void_p(_ptr(r)), C.c_void_p(_ptr(z)),
                                C.c_void_p(_stream(stream))), "sg_precond")
         return z
+
+    def stationary(self, b, iters, x=None, pc: str = "mean", hist: bool = True, stream=None):
+        """Stationary iteration x_{i+1} = x_i + B^{-1}(b - A x_i) from x_0 = B^{-1} b;
+        returns (x, relative residual history of length iters+1, or None)."""
+        x = self.empty() if x is None else x
+        harr = (C.c_double * (iters + 1))() if hist else None
+        check(lib().sg_stationary(self._h, C.c_void_p(_ptr(b)), C.c_void_p(_ptr(x)), PC[pc], iters,
+                                  C.cast(harr, C.POINTER(C.c_double)) if harr is not None else None,
+                                  C.c_void_p(_stream(stream))), "sg_stationary")
+        return x, (list(harr) if hist else None)
 
     def _opts(self, restart, maxit, pc, precision, tol, x0_zero, hist):
         harr = None
@@ -401,7 +412,7 @@ def norm(x, stream=None) -> float:
 
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
-            "sg_fgmres", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_cgs2", "sg_norm",
+            "sg_fgmres", "sg_stationary", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_cgs2", "sg_norm",
             "sg_set_profiling", "sg_profile_kinds", "sg_kernel_times", "sg_net_create", "sg_net_destroy", "sg_net_num_params",
             "sg_net_get_params", "sg_net_set_params", "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step",
             "sg_net_train_pairs", "sg_net_save", "sg_net_load", "sg_attach_net", "sg_strerror", "sg_last_error"]

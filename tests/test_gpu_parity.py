@@ -101,6 +101,38 @@ def test_high_degree_gmres_matches_oracle(degree):
     assert info["converged"] == 1 and rel <= 1e-10 * 1.05 and err <= 1e-6
 
 
+@pytest.mark.parametrize("sigma,converges", [(1.0, True), (6.0, False)])
+def test_stationary_matches_oracle(sigma, converges):
+    """Stationary iteration with B = A_0 (eq. stationary_iteration, Section 5): the GPU
+    iterate after 10 updates against the oracle's, the residual history against the
+    oracle's residuals of the same iterates, and the outcome the paper reports for small
+    and large perturbations (Section 7: it converges for θ = 0.1 and diverges for θ = 0.2):
+    here σ = 1 (10 % of k̄) converges and σ = 6 diverges."""
+    inst = small_2d(n=33, kbar=10.0, sigma=sigma, s=3, degree=2)
+    S = assemble.from_instance(inst)
+    Binv = precond.mean_value(S)
+    xs, _ = krylov.stationary(lambda v: S.A @ v, S.b, Binv, 10)
+    x0 = Binv(S.b)
+    op = sg.SG.from_instance(inst)
+    x, hist = op.stationary(op.rhs(inst.f), 10)
+    xh = to_host(x)
+    assert np.max(np.abs(xh - xs)) <= 1e-8 * np.max(np.abs(xs))
+    nb = np.linalg.norm(S.b)
+    assert abs(hist[0] - np.linalg.norm(S.b - S.A @ x0) / nb) <= 1e-8 * hist[0]
+    assert abs(hist[-1] - np.linalg.norm(S.b - S.A @ xs) / nb) <= 1e-6 * hist[-1]
+    if converges:
+        assert hist[-1] < 1e-4 * hist[0]
+    else:
+        assert hist[-1] > hist[0]
+    # zero right-hand side and invalid arguments
+    z, hz = op.stationary(op.empty().zero_(), 3)
+    assert float(z.abs().max()) == 0.0 and hz == [0.0] * 4
+    with pytest.raises(sg.SGError):
+        op.stationary(op.rhs(inst.f), 3, pc="none")
+    with pytest.raises(sg.SGError):
+        op.stationary(op.rhs(inst.f), -1)
+
+
 def test_degree_sweep_operator_sampled():
     """The degree-8 instance of the degree sweep at its bench size (129², Q = 165): sampled
     rows against the oracle's point-by-point evaluation."""
