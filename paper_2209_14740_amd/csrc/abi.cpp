@@ -99,6 +99,15 @@ int sg_apply(sg_handle h, const sg_c64* x, sg_c64* y, hipStream_t stream) {
     })
 }
 
+int sg_set_operator_shift(sg_handle h, double beta) {
+    SG_TRY({
+        if (!h) return fail(SG_EINVAL, "null handle");
+        if (!std::isfinite(beta)) return fail(SG_EINVAL, "sg_set_operator_shift: beta must be finite");
+        ctx(h)->op_csl_beta = beta;
+        return SG_OK;
+    })
+}
+
 int sg_precond(sg_handle h, int pc, int precision, const sg_c64* r, sg_c64* z, hipStream_t stream) {
     SG_TRY({
         if (!h || !r || !z) return fail(SG_EINVAL, "null argument");

@@ -104,6 +104,11 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs& a, int tile, double2
             lre += dx * ty.x;
             lim += dx * ty.y;
         }
+        if (a.csl_beta != 0.0) {   // (1 + iβ) K x
+            const double sre = re - a.csl_beta * im, sim = im + a.csl_beta * re;
+            re = sre;
+            im = sim;
+        }
         double ore = lre * a.ih2 - re, oim = lim * a.ih2 - im;
         if (bnd) {
             // - i Σ_j b_ij x_j
@@ -177,6 +182,7 @@ ApplyArgs make_apply_args(const Ctx* c, const double2* x, double2* y) {
     a.btf = c->bprog_termfield;
     a.kv = c->kvals_off;
     a.bv = c->bvals_off;
+    a.csl_beta = c->op_csl_beta;
     a.ntiles_x = (c->n + TILE - 1) / TILE;
     a.nrows = c->dim == 2 ? c->n : 1;
     a.KF = c->d_kf;

@@ -23,6 +23,7 @@ struct ApplyArgs {
     int ntiles_x, nrows;
     const double* KF;     // k_1..k_s at the nodes ([s][P]) for the shape-specialised kernels
     double k0, ih;        // constant mean k_0 and 1/h
+    double csl_beta;      // 0: the operator A; β: the shifted operator M(β) = A - iβK (k² block times 1+iβ)
 };
 
 ApplyArgs make_apply_args(const Ctx* c, const double2* x, double2* y);

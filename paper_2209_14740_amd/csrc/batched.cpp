@@ -432,7 +432,8 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         auto add_apply = [&](Ctx* c, const double2* xin, double2* yout) {
             const ApplyArgs aa = make_apply_args(c, xin, yout);
             const double abytes = (double)c->P * (32.0 * c->Q + 8.0 * c->K.nfield);
-            if (c->dim == 2 && c->use_spec_apply && (long long)c->n * c->n * 16 < (1ll << 32) &&
+            if (c->dim == 2 && c->use_spec_apply && c->op_csl_beta == 0.0 &&
+                (long long)c->n * c->n * 16 < (1ll << 32) &&
                 dispatch_spec_grouped(c->s, c->degree, nullptr, nullptr, 0, 0, nullptr)) {
                 g_spec[{c->s, c->degree}].add(aa, spec_row_blocks(c->n), abytes);
             } else {

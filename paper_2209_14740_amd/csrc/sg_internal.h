@@ -199,6 +199,7 @@ struct Ctx {
     Workspace ws;
     Prof prof;
     bool use_spec_apply = true;        // compile-time-specialised operator when available
+    double op_csl_beta = 0.0;          // operator of sg_apply and the solvers: A (0) or M(β) = A - iβK
     double2* d_tmp_pc = nullptr;       // preconditioner intermediate: Q·n rows of tld complex (2D)
     int tld = 0;                       // its row length, n rounded up to 8 (128-byte aligned rows)
     Net* net = nullptr;                // attached correction network (not owned)

@@ -73,6 +73,7 @@ def lib():
     L.sg_gmres.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
     L.sg_fgmres.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), PRECOND_CB, vp, C.POINTER(SolveStats), vp]
     L.sg_stationary.argtypes = [vp, vp, vp, i, i, C.POINTER(d), vp]
+    L.sg_set_operator_shift.argtypes = [vp, d]
     L.sg_cgs2.argtypes = [ll, i, vp, vp, vp, vp]
     L.sg_norm.argtypes = [ll, vp, C.POINTER(d), vp]
     L.sg_gmres_batched.argtypes = [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
@@ -102,9 +103,9 @@ def lib():
     L.sg_strerror.restype = C.c_char_p
     L.sg_last_error.argtypes = []
     L.sg_last_error.restype = C.c_char_p
-    for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres", "sg_stationary",
-                 "sg_cgs2", "sg_norm", "sg_set_profiling", "sg_kernel_times", "sg_gmres_batched", "sg_autotune",
-                 "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
+    for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
+                 "sg_stationary", "sg_set_operator_shift", "sg_cgs2", "sg_norm", "sg_set_profiling",
+                 "sg_kernel_times", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
                  "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step", "sg_net_train_pairs", "sg_net_save",
                  "sg_net_load", "sg_attach_net", "sg_profile_kinds"):
         getattr(L, name).restype = C.c_int
@@ -201,6 +202,10 @@ class SG:
         check(lib().sg_precond(self._h, PC[pc], PREC[precision], C.c_void_p(_ptr(r)), C.c_void_p(_ptr(z)),
                                C.c_void_p(_stream(stream))), "sg_precond")
         return z
+
+    def set_operator_shift(self, beta: float):
+        """Operator of this handle: A (beta = 0) or M(beta) = A - i beta K."""
+        check(lib().sg_set_operator_shift(self._h, float(beta)), "sg_set_operator_shift")
 
     def stationary(self, b, iters, x=None, pc: str = "mean", hist: bool = True, stream=None):
         """Stationary iteration x_{i+1} = x_i + B^{-1}(b - A x_i) from x_0 = B^{-1} b;
@@ -412,7 +417,8 @@ def norm(x, stream=None) -> float:
 
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
-            "sg_fgmres", "sg_stationary", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_cgs2", "sg_norm",
+            "sg_fgmres", "sg_stationary", "sg_set_operator_shift", "sg_gmres_batched", "sg_autotune", "sg_tune_get",
+            "sg_tune_set", "sg_cgs2", "sg_norm",
             "sg_set_profiling", "sg_profile_kinds", "sg_kernel_times", "sg_net_create", "sg_net_destroy", "sg_net_num_params",
             "sg_net_get_params", "sg_net_set_params", "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step",
             "sg_net_train_pairs", "sg_net_save", "sg_net_load", "sg_attach_net", "sg_strerror", "sg_last_error"]
