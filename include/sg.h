@@ -126,8 +126,8 @@ int  sg_apply(sg_handle h, const sg_c64* x, sg_c64* y, hipStream_t stream);
 /* Select the operator of the handle: beta = 0 gives A (the default); beta != 0 gives the
  * full complex shifted Laplace matrix M(beta) = L - iB - (1 + i beta) K = A - i beta K
  * (eq. M, Section 4: only the k² block K is shifted, the boundary block is not).  It applies
- * to sg_apply and to the matrix of sg_gmres, sg_fgmres and sg_stationary on this handle;
- * the preconditioners and sg_rhs are unchanged.  A second handle of the same problem with
+ * to sg_apply and to the matrix of sg_gmres, sg_fgmres, sg_stationary and
+ * sg_gmres_batched on this handle; the preconditioners and sg_rhs are unchanged.  A second handle of the same problem with
  * beta set solves with the full M, e.g. as the inner solve of a nested FGMRES whose outer
  * matrix is A.  Returns SG_EINVAL for a non-finite beta. */
 int  sg_set_operator_shift(sg_handle h, double beta);
