@@ -214,6 +214,13 @@ int  sg_cgs2(long long n, int nv, const sg_c64* V, sg_c64* w, sg_c64* h_host, hi
 /* ||x||_2 in FP64 (deterministic two-stage reduction). */
 int  sg_norm(long long n, const sg_c64* x, double* out_host, hipStream_t stream);
 
+/* out = alpha x + beta y over n complex entries (device vectors; out may alias x or y; y may
+ * be NULL when beta = 0): the vector update of the solvers (the residual b - A x and the
+ * iterate update, Section 6.3), exposed for callers that form residuals and errors on the
+ * device, e.g. the learned form's training pairs.  Asynchronous on the stream. */
+int  sg_axpby(long long n, sg_c64 alpha, const sg_c64* x, sg_c64 beta, const sg_c64* y, sg_c64* out,
+              hipStream_t stream);
+
 /* Per-kernel-class timing with HIP events recorded on the launch stream around every
  * kernel the handle issues (off by default).  Classes: */
 enum {

@@ -249,6 +249,17 @@ int sg_norm(long long n, const sg_c64* x, double* out_host, hipStream_t stream) 
     })
 }
 
+int sg_axpby(long long n, sg_c64 alpha, const sg_c64* x, sg_c64 beta, const sg_c64* y, sg_c64* out,
+             hipStream_t stream) {
+    SG_TRY({
+        if (n < 1 || !x || !out) return fail(SG_EINVAL, "invalid argument");
+        if (!y && (beta.re != 0.0 || beta.im != 0.0)) return fail(SG_EINVAL, "sg_axpby: y is NULL but beta is not 0");
+        return sgi::launch_axpby(n, make_double2(alpha.re, alpha.im), reinterpret_cast<const double2*>(x),
+                                 make_double2(beta.re, beta.im), reinterpret_cast<const double2*>(y),
+                                 reinterpret_cast<double2*>(out), stream);
+    })
+}
+
 int sg_gmres_batched(int count, const sg_handle* handles, const sg_c64* const* b, sg_c64* const* x,
                      const sg_solve_opts* opts, sg_solve_stats* stats, hipStream_t stream) {
     SG_TRY({

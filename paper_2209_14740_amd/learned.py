@@ -23,8 +23,8 @@ def solver_pairs(op, b, cycle=3, max_pairs=16, tol=1e-11):
     pairs = []
     for _ in range(max_pairs):
         op.gmres(b, x, restart=cycle, maxit=cycle, pc="mean", precision="f64", tol=1e-300, x0_zero=False)
-        r = b - op.apply(x)
-        e = xs - x
+        r = sg.axpby(1.0, b, -1.0, op.apply(x))
+        e = sg.axpby(1.0, xs, -1.0, x)
         if sg.norm(r) <= 1e-9 * sg.norm(b):
             break
         pairs.append((r, e))

@@ -27,6 +27,10 @@ class SGError(RuntimeError):
     pass
 
 
+class C64(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int), ("bc", C.c_int), ("s", C.c_int), ("degree", C.c_int),
                 ("k_fields", C.POINTER(C.c_double)), ("k_mean", C.c_double), ("csl_beta", C.c_double)]
@@ -76,6 +80,7 @@ def lib():
     L.sg_set_operator_shift.argtypes = [vp, d]
     L.sg_cgs2.argtypes = [ll, i, vp, vp, vp, vp]
     L.sg_norm.argtypes = [ll, vp, C.POINTER(d), vp]
+    L.sg_axpby.argtypes = [ll, C64, vp, C64, vp, vp, vp]
     L.sg_gmres_batched.argtypes = [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
                                    C.POINTER(SolveStats), vp]
     L.sg_autotune.argtypes = [i, C.POINTER(vp), i, i, C.POINTER(d), vp]
@@ -104,7 +109,7 @@ def lib():
     L.sg_last_error.argtypes = []
     L.sg_last_error.restype = C.c_char_p
     for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
-                 "sg_stationary", "sg_set_operator_shift", "sg_cgs2", "sg_norm", "sg_set_profiling",
+                 "sg_stationary", "sg_set_operator_shift", "sg_cgs2", "sg_norm", "sg_axpby", "sg_set_profiling",
                  "sg_kernel_times", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
                  "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step", "sg_net_train_pairs", "sg_net_save",
                  "sg_net_load", "sg_attach_net", "sg_profile_kinds"):
@@ -410,6 +415,17 @@ def cgs2(V, w, stream=None):
     return a[0::2] + 1j * a[1::2]
 
 
+def axpby(alpha, x, beta=0.0, y=None, out=None, stream=None):
+    """out = alpha x + beta y on the device (sg_axpby); out defaults to a new vector."""
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    a, bb = complex(alpha), complex(beta)
+    check(lib().sg_axpby(x.numel(), C64(a.real, a.imag), C.c_void_p(_ptr(x)), C64(bb.real, bb.imag),
+                         C.c_void_p(_ptr(y)) if y is not None else None, C.c_void_p(_ptr(out)),
+                         C.c_void_p(_stream(stream))), "sg_axpby")
+    return out
+
+
 def norm(x, stream=None) -> float:
     out = C.c_double()
     check(lib().sg_norm(x.numel(), C.c_void_p(_ptr(x)), C.byref(out), C.c_void_p(_stream(stream))), "sg_norm")
@@ -418,7 +434,7 @@ def norm(x, stream=None) -> float:
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
             "sg_fgmres", "sg_stationary", "sg_set_operator_shift", "sg_gmres_batched", "sg_autotune", "sg_tune_get",
-            "sg_tune_set", "sg_cgs2", "sg_norm",
+            "sg_tune_set", "sg_cgs2", "sg_norm", "sg_axpby",
             "sg_set_profiling", "sg_profile_kinds", "sg_kernel_times", "sg_net_create", "sg_net_destroy", "sg_net_num_params",
             "sg_net_get_params", "sg_net_set_params", "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step",
             "sg_net_train_pairs", "sg_net_save", "sg_net_load", "sg_attach_net", "sg_strerror", "sg_last_error"]

@@ -349,6 +349,21 @@ def test_cgs2_parity():
     assert np.max(np.abs(V.conj() @ out)) <= 1e-14
 
 
+def test_axpby_parity():
+    """sg_axpby: out = αx + βy with complex α, β, in place and with y absent, against numpy."""
+    x, y = rand_vec(10007, 41), rand_vec(10007, 42)
+    a, b = 0.3 - 1.2j, -2.0 + 0.5j
+    out = to_host(sg.axpby(a, to_dev(x), b, to_dev(y)))
+    ref = a * x + b * y
+    assert np.max(np.abs(out - ref)) <= 4e-16 * np.max(np.abs(a * x) + np.abs(b * y))
+    xd = to_dev(x)
+    sg.axpby(a, xd, b, to_dev(y), out=xd)
+    assert np.max(np.abs(to_host(xd) - ref)) <= 4e-16 * np.max(np.abs(a * x) + np.abs(b * y))
+    assert np.max(np.abs(to_host(sg.axpby(a, to_dev(x))) - a * x)) <= 4e-16 * np.max(np.abs(a * x))
+    with pytest.raises(sg.SGError):
+        sg.axpby(1.0, to_dev(x), 1.0, None)
+
+
 def test_norm_parity():
     x = rand_vec(123_457, 9)
     assert abs(sg.norm(to_dev(x)) - np.linalg.norm(x)) <= 1e-14 * np.linalg.norm(x)
