@@ -63,6 +63,9 @@ def lib():
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise ImportError("libsg.so not built: run `python -m paper_2209_14740_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded, so that the
+    # process has one runtime (tensors, streams and the library's kernels share it)
+    import torch  # noqa: F401
     L = C.CDLL(_LIB_PATH)
     vp, i, ll, d = C.c_void_p, C.c_int, C.c_longlong, C.c_double
     L.sg_setup.argtypes = [C.POINTER(Problem), vp, C.POINTER(vp)]
