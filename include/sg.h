@@ -106,7 +106,10 @@ typedef struct {
 
 /* Build the operator for one problem: basis, triple-product tables, coefficient
  * fields, eigenfactors of the 1D mean operator and pivoted tridiagonal factors
- * (host FP64, validated), then upload to the current device.  *out owns all of it. */
+ * (host FP64, validated), then upload to the current device.  *out owns all of it.
+ * Shapes: every (s, degree) with Q·66·16 + |Γ₂|·512 <= 160 KiB (|Γ₂| = 1+2s+s(s-1)/2, the
+ * LDS tile of the generic operator kernel), and beyond that the shapes with a specialised
+ * kernel (2D: s = 3 up to degree 8); any other shape returns SG_EINVAL here. */
 int  sg_setup(const sg_problem* prob, hipStream_t stream, sg_handle* out);
 void sg_destroy(sg_handle h);
 
@@ -129,7 +132,9 @@ int  sg_apply(sg_handle h, const sg_c64* x, sg_c64* y, hipStream_t stream);
  * to sg_apply and to the matrix of sg_gmres, sg_fgmres, sg_stationary and
  * sg_gmres_batched on this handle; the preconditioners and sg_rhs are unchanged.  A second handle of the same problem with
  * beta set solves with the full M, e.g. as the inner solve of a nested FGMRES whose outer
- * matrix is A.  Returns SG_EINVAL for a non-finite beta. */
+ * matrix is A.  Returns SG_EINVAL for a non-finite beta, or when no operator kernel serves
+ * the shifted operator of this shape (shapes with Q > 84 beyond the generic kernel's LDS
+ * tile). */
 int  sg_set_operator_shift(sg_handle h, double beta);
 
 /* z = P^{-1} r for P = A_0 or M_0 (pc = SG_PC_MEAN / SG_PC_CSL_MEAN) by fast

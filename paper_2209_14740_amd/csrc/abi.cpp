@@ -103,6 +103,8 @@ int sg_set_operator_shift(sg_handle h, double beta) {
     SG_TRY({
         if (!h) return fail(SG_EINVAL, "null handle");
         if (!std::isfinite(beta)) return fail(SG_EINVAL, "sg_set_operator_shift: beta must be finite");
+        if (beta != 0.0 && !sgi::apply_available(ctx(h), beta))
+            return fail(SG_EINVAL, "sg_set_operator_shift: no operator kernel serves the shifted operator of this shape");
         ctx(h)->op_csl_beta = beta;
         return SG_OK;
     })

@@ -218,7 +218,19 @@ int launch_apply_grouped(const ApplyArgs* d_tasks, const int* d_start, int ntask
     return SG_OK;
 }
 
+bool apply_available(const Ctx* c, double csl_beta) {
+    ApplyArgs a = make_apply_args(c, nullptr, nullptr);   // null x: the dispatchers only answer
+    a.csl_beta = csl_beta;
+    const int sv = c->s, rv = c->degree;
+    if (c->use_spec_apply && (dispatch_spec_g0(sv, rv, a, 0) || dispatch_spec_g1(sv, rv, a, 0) ||
+                              dispatch_spec_g2(sv, rv, a, 0) || dispatch_spec_g3(sv, rv, a, 0) ||
+                              dispatch_spec_g4(sv, rv, a, 0)))
+        return true;
+    return apply_lds_bytes(c->Q, c->K.nfield) <= 160 * 1024;
+}
+
 int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st) {
+    if (!x || !y) return fail(SG_EINVAL, "sg_apply: null vector");
     if (x == y) return fail(SG_EINVAL, "sg_apply: x and y must not alias");
     const ApplyArgs a = make_apply_args(c, x, y);
     if (c->use_spec_apply) {

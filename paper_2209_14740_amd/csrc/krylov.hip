@@ -213,6 +213,9 @@ __device__ __forceinline__ void cgs_block(long long n, int nv, const double2* __
                 acc[m].y = fma(v[m].x, wi.y, fma(-v[m].y, wi.x, acc[m].y));
             }
         } else {
+            // every wave reads w[i] before the barrier: wave 0 stores the updated value after
+            // it, so a read behind the barrier could see the new value instead of the old one
+            double2 wn = ok ? w[i] : make_double2(0.0, 0.0);
             double2 p = make_double2(0.0, 0.0);
 #pragma unroll
             for (int m = 0; m < NVW; ++m)
@@ -222,7 +225,6 @@ __device__ __forceinline__ void cgs_block(long long n, int nv, const double2* __
                 }
             part[buf][wv][lane] = p;
             __syncthreads();
-            double2 wn = ok ? w[i] : make_double2(0.0, 0.0);
 #pragma unroll
             for (int q = 0; q < RB / 64; ++q) {
                 wn.x += part[buf][q][lane].x;

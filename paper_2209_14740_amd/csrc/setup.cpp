@@ -496,6 +496,11 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
         for (int m = l + 1; m < s; ++m) { auto g = std::vector<int>(s, 0); g[l] = 1; g[m] = 1; c->gamma2.push_back(g); }
     build_coupling(c->alpha, Q, s, c->gamma2, c->K);
     build_coupling(c->alpha, Q, s, c->gamma1, c->B);
+    // a shape that neither a specialised operator kernel nor the generic one (whose LDS tile
+    // grows with Q) can serve is refused here rather than at the first sg_apply
+    if (!apply_available(c.get(), 0.0))
+        return fail(SG_EINVAL, "no operator kernel serves this (dim, s, degree): Q = " + std::to_string(Q) +
+                                   " is too large for the generic kernel's LDS tile");
 
     const int n = p->n;
     std::vector<double> dw(n, 1.0);

@@ -213,6 +213,8 @@ int build_ctx(const sg_problem* prob, hipStream_t stream, Ctx** out);
 
 // apply.hip
 int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st);
+// true if some operator kernel serves the handle's shape with the operator shift csl_beta
+bool apply_available(const Ctx* c, double csl_beta);
 
 // batched.cpp (autotuner table)
 int tune_get(int n, int Q, int precision);

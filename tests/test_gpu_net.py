@@ -12,7 +12,7 @@ below amplify such flips by the same cancellation factor (about 25) as the round
 itself, to 2e-2 on each layer's gradient.  Against the exact oracle the storage rounding itself shows: about 4e-3 on the
 forward output, but 5-13 % on the parameter gradients of random targets, whose sums
 over pixels cancel strongly and so amplify the rounding of their terms (the rounded
-oracle reproduces these figures); held to 1e-2 and 0.2.  Adam is FP32 arithmetic on the
+oracle reproduces these figures); held to 1e-2 and 0.15.  Adam is FP32 arithmetic on the
 same gradient: 1e-5 relative.  Solves are held to the FP64 true residual and to the
 oracle's direct solution (1e-6), whatever the network does.
 """
@@ -92,7 +92,7 @@ def test_net_gradient_matches_oracle(small_net):
     x = rng.standard_normal((B, H, H, CIN))
     t = rng.standard_normal((B, H, H, COUT))
     loss, g = small_net.grad_nhwc(dev32(x), dev32(t))
-    for label, rnd, tol_layer in (("rounded", unet.bf16_round, 2e-2), ("exact", None, 0.2)):
+    for label, rnd, tol_layer in (("rounded", unet.bf16_round, 2e-2), ("exact", None, 0.15)):
         res = [unet.loss_and_grad(th, x[b], t[b], rnd=rnd) for b in range(B)]
         Lref = np.mean([r_[0] for r_ in res])
         gref = np.mean([r_[1] for r_ in res], axis=0)
@@ -217,9 +217,34 @@ def test_fallback_on_bad_network(sg_op):
         sg_op.gmres(b, pc="net")         # needs the flexible method
 
 
-def test_trained_network_gain():
-    """Ablation: a network trained on pairs from plain solves of one family of problems
-    against the same FGMRES without it, on held-out problems of the family."""
+def test_fallback_on_nonfinite_network(sg_op):
+    """A network whose output is not finite (every parameter NaN): the FGMRES cycle with it
+    meets a non-finite Hessenberg entry, the solver falls back to plain A_0-GMRES from
+    x = 0 and still returns the FP64-converged solution, with SG_FALLBACK_USED."""
+    net = sg.Net(sg_op.Q, INST.s, seed=6)
+    th = net.get_params()
+    th[:] = np.nan
+    net.set_params(th)
+    sg_op.attach_net(net)
+    b = sg_op.rhs(INST.f)
+    x, info = sg_op.fgmres(b, restart=10, maxit=400, pc="net", precision="f64", tol=1e-8)
+    r, e = _solve_check(sg_op, INST, x)
+    print("nan net", info["status"], info["iters"], info["fallback"], r, e, flush=True)
+    assert info["status"] == sg.SG_FALLBACK_USED and info["fallback"] == 1
+    assert r <= 1.05e-8 and e <= 1e-6
+    sg_op.attach_net(None)
+
+
+_ABLATION = {}
+
+
+def _ablation():
+    """Train once per session: a network trained on pairs from plain solves of one family of
+    problems, then each held-out problem solved by FGMRES with A_0 alone and with the
+    network (iterations, status, true residual and error against the oracle's direct
+    solve)."""
+    if _ABLATION:
+        return _ABLATION
     n = 33
     train_inst = [config5_instance(10000 + i, n=n) for i in range(8)]
     test_inst = [config5_instance(i, n=n) for i in range(2)]
@@ -244,7 +269,7 @@ def test_trained_network_gain():
         learned.train(net, samples, steps=150, batch=8, lr=1e-3)
         l_after = held_loss()
         print("pairs %d, held-out loss %.4e -> %.4e" % (len(samples), l_before, l_after), flush=True)
-        assert l_after < l_before
+        rows = []
         for op, inst in zip(ops[8:], test_inst):
             b = op.rhs(inst.f)
             _, i0 = op.fgmres(b, restart=50, maxit=500, pc="mean", precision="f64", tol=1e-8)
@@ -254,7 +279,32 @@ def test_trained_network_gain():
             r, e = _solve_check(op, inst, x)
             print("%s: A_0 FGMRES %d iterations, learned %d iterations (status %d, fallback %d), relres %.2e"
                   % (inst.name, i0["iters"], i1["iters"], i1["status"], i1["fallback"], r), flush=True)
-            assert r <= 1.05e-8 and e <= 1e-6
+            rows.append((i0, i1, r, e))
+        net.close()
+        _ABLATION.update(loss=(l_before, l_after), rows=rows)
     finally:
         for op in ops:
             op.close()
+    return _ABLATION
+
+
+def test_trained_network_converges_and_learns():
+    """The trained network lowers the held-out loss, and FGMRES with it (or its fallback)
+    reaches the FP64 true residual 1e-8 and the oracle's solution (1e-6) on every held-out
+    problem."""
+    ab = _ablation()
+    assert ab["loss"][1] < ab["loss"][0]
+    for _, _, r, e in ab["rows"]:
+        assert r <= 1.05e-8 and e <= 1e-6
+
+
+@pytest.mark.xfail(reason="the trained network does not beat A_0 alone: a 3-level 3x3 U-Net sees about 60 "
+                          "pixels, while the correction A^-1 - A_0^-1 of a Helmholtz problem is non-local "
+                          "(measured on config 5: more iterations and time than plain A_0-GMRES)",
+                   strict=False)
+def test_trained_network_gain():
+    """Ablation: the network's gain itself.  FGMRES with the trained network must need no more
+    iterations than FGMRES with A_0 alone on each held-out problem, and must not fall back."""
+    ab = _ablation()
+    for i0, i1, _, _ in ab["rows"]:
+        assert i1["fallback"] == 0 and i1["iters"] <= i0["iters"], (i0["iters"], i1["iters"])

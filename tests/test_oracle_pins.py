@@ -113,6 +113,31 @@ def test_T_kernel_and_determinant_recursion():
     assert dets == [1] * (n - 1) + [0]
 
 
+def test_T_closed_form_eigenvalues():
+    """Theorem A.1: the Dirichlet T = (1/h²) tridiag(-1, 2, -1) on q interior nodes has the
+    eigenvalues (4/h²) sin²(jπ/(2(q+1))), j = 1..q; the 2D Dirichlet Laplacian I⊗T + T⊗I of
+    Theorem A.3 has the sums of two of them.  Theorem A.2: the absorbing T (corner entries
+    1/h²) is the second-difference matrix with reflecting ends, eigenvalues
+    (4/h²) sin²(jπ/(2n)), j = 0..n-1.  A wrong diagonal, sign or scaling moves them."""
+    for q in (1, 2, 7, 30):
+        h = 1.0 / (q + 1)
+        ev = np.sort(np.linalg.eigvalsh(fd.T_dirichlet(q, h).toarray()))
+        j = np.arange(1, q + 1)
+        ref = np.sort(4.0 / h ** 2 * np.sin(j * np.pi / (2 * (q + 1))) ** 2)
+        assert np.allclose(ev, ref, rtol=1e-12, atol=1e-9)
+    q = 9
+    Lap, w, e, h = fd.laplacian(2, q, "dirichlet")
+    assert h == 1.0 / (q + 1) and not np.any(e) and np.all(w == 1.0)
+    lam = 4.0 / h ** 2 * np.sin(np.arange(1, q + 1) * np.pi / (2 * (q + 1))) ** 2
+    ev2 = np.sort(np.linalg.eigvalsh(Lap.toarray()))
+    assert np.allclose(ev2, np.sort((lam[:, None] + lam[None, :]).ravel()), rtol=1e-12, atol=1e-8)
+    for n in (2, 5, 17):
+        h = 1.0 / (n - 1)
+        ev = np.sort(np.linalg.eigvalsh(fd.T_absorbing(n, h).toarray()))
+        ref = np.sort(4.0 / h ** 2 * np.sin(np.arange(n) * np.pi / (2 * n)) ** 2)
+        assert np.allclose(ev, ref, rtol=1e-12, atol=1e-9)
+
+
 def test_1d_closed_form_second_order():
     """Constant k, point source at 1/2: u = (i/2k) e^{ik|x-1/2|} solves -u''-k²u = δ with
     u' ∓ iku = 0; the FD solution (Theorem A.2) converges with order two."""
@@ -308,7 +333,6 @@ def test_wedge_r8_gmres_theta01():
     assert info.converged and abs(info.iters - GOLD["gmres_2d_wedge_r8"]["theta_0.1"]) <= 1
 
 
-@pytest.mark.slow
 def test_wedge_r8_gmres_theta02():
     info = _wedge_gmres(0.2)
     assert info.converged and abs(info.iters - GOLD["gmres_2d_wedge_r8"]["theta_0.2"]) <= 3
@@ -352,6 +376,35 @@ def _deltaS_l2_frobenius(inst):
         Sq = fd.deterministic_S(inst.dim, inst.n, inst.bc, kq).toarray()
         acc += W[q] * np.linalg.norm(Sq - S0, "fro") ** 2
     return math.sqrt(acc)
+
+
+def _phi_tensor(alpha_row, x):
+    """φ_α at the points x (npts × s): products of orthonormal Legendre polynomials built
+    from numpy's Legendre basis, independent of the oracle's recurrence."""
+    v = np.ones(x.shape[0])
+    for l, a in enumerate(alpha_row):
+        v *= math.sqrt(2 * a + 1) * np.polynomial.legendre.Legendre.basis(int(a))(x[:, l])
+    return v
+
+
+def test_phi_product_norms_bruteforce():
+    """Theorem 5.1's constant: Σ_{i,j} ||φ_i φ_j||²_{L²} equals the brute-force s-dimensional
+    tensor Gauss quadrature of E[φ_i² φ_j²] (exact: degree 4r needs 2r+1 nodes per
+    variable), and the closed form 1 + 2·1 + 9/5 = 4.8 for s = 1, r = 1 (φ_1 = √3 ξ,
+    E[ξ⁴] = 1/5).  A dropped pair, a wrong moment or a wrong weight fails one of them."""
+    assert abs(spectral.phi_product_norms(1, 1) - 4.8) < 1e-13
+    for s_, r_ in ((1, 3), (2, 2), (3, 2), (2, 3)):
+        g, wg = np.polynomial.legendre.leggauss(2 * r_ + 1)
+        grids = np.meshgrid(*([g] * s_), indexing="ij")
+        x = np.stack([t.ravel() for t in grids], axis=1)
+        wts = np.ones(x.shape[0])
+        for l, t in enumerate(np.meshgrid(*([wg / 2.0] * s_), indexing="ij")):
+            wts *= t.ravel()
+        alpha = pc.multi_indices(s_, r_)
+        ph = np.array([_phi_tensor(a, x) for a in alpha])
+        brute = float(np.einsum("ip,jp,p->", ph ** 2, ph ** 2, wts))
+        got = spectral.phi_product_norms(s_, r_)
+        assert abs(got - brute) <= 1e-12 * brute, (s_, r_, got, brute)
 
 
 def test_theorem_5_1_bound():
