@@ -216,6 +216,17 @@ int  sg_tune_set(int n, int Q, int precision, int tile);
  * Arnoldi coefficients h_host[0..nv-1] = V^H w (both passes summed), h_host[nv] = ||w||. */
 int  sg_cgs2(long long n, int nv, const sg_c64* V, sg_c64* w, sg_c64* h_host, hipStream_t stream);
 
+/* sg_cgs2 for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * results, bit for bit, but the reduction partials and coefficients live in a fixed
+ * file-scope device array of 2 MiB + 3 KiB per GPU (held until the process ends) instead of
+ * buffers allocated per call, and the coefficients go to the host through h_host itself.
+ * Limit: nv <= 64 (SG_EINVAL above it).  Calls no hipMalloc / hipFree / hipHostMalloc.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams, two threads) race and must be serialised by the caller.  Synchronises the
+ * stream. */
+int  sg_cgs2_noalloc(long long n, int nv, const sg_c64* V, sg_c64* w, sg_c64* h_host, hipStream_t stream);
+
 /* ||x||_2 in FP64 (deterministic two-stage reduction). */
 int  sg_norm(long long n, const sg_c64* x, double* out_host, hipStream_t stream);
 

@@ -82,6 +82,7 @@ def lib():
     L.sg_stationary.argtypes = [vp, vp, vp, i, i, C.POINTER(d), vp]
     L.sg_set_operator_shift.argtypes = [vp, d]
     L.sg_cgs2.argtypes = [ll, i, vp, vp, vp, vp]
+    L.sg_cgs2_noalloc.argtypes = [ll, i, vp, vp, vp, vp]
     L.sg_norm.argtypes = [ll, vp, C.POINTER(d), vp]
     L.sg_axpby.argtypes = [ll, C64, vp, C64, vp, vp, vp]
     L.sg_gmres_batched.argtypes = [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
@@ -112,7 +113,7 @@ def lib():
     L.sg_last_error.argtypes = []
     L.sg_last_error.restype = C.c_char_p
     for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
-                 "sg_stationary", "sg_set_operator_shift", "sg_cgs2", "sg_norm", "sg_axpby", "sg_set_profiling",
+                 "sg_stationary", "sg_set_operator_shift", "sg_cgs2", "sg_cgs2_noalloc", "sg_norm", "sg_axpby", "sg_set_profiling",
                  "sg_kernel_times", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
                  "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step", "sg_net_train_pairs", "sg_net_save",
                  "sg_net_load", "sg_attach_net", "sg_profile_kinds"):
@@ -418,6 +419,16 @@ def cgs2(V, w, stream=None):
     return a[0::2] + 1j * a[1::2]
 
 
+def cgs2_noalloc(V, w, stream=None):
+    """sg_cgs2 without any allocation (scratch in a fixed device array; nv <= 64)."""
+    nv, n = V.shape
+    out = (C.c_double * (2 * (nv + 1)))()
+    check(lib().sg_cgs2_noalloc(n, nv, C.c_void_p(_ptr(V)), C.c_void_p(_ptr(w)), out, C.c_void_p(_stream(stream))),
+          "sg_cgs2_noalloc")
+    a = np.frombuffer(out, dtype=np.float64)
+    return a[0::2] + 1j * a[1::2]
+
+
 def axpby(alpha, x, beta=0.0, y=None, out=None, stream=None):
     """out = alpha x + beta y on the device (sg_axpby); out defaults to a new vector."""
     import torch
@@ -437,7 +448,7 @@ def norm(x, stream=None) -> float:
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
             "sg_fgmres", "sg_stationary", "sg_set_operator_shift", "sg_gmres_batched", "sg_autotune", "sg_tune_get",
-            "sg_tune_set", "sg_cgs2", "sg_norm", "sg_axpby",
+            "sg_tune_set", "sg_cgs2", "sg_cgs2_noalloc", "sg_norm", "sg_axpby",
             "sg_set_profiling", "sg_profile_kinds", "sg_kernel_times", "sg_net_create", "sg_net_destroy", "sg_net_num_params",
             "sg_net_get_params", "sg_net_set_params", "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step",
             "sg_net_train_pairs", "sg_net_save", "sg_net_load", "sg_attach_net", "sg_strerror", "sg_last_error"]
