@@ -74,8 +74,13 @@ typedef struct {
     int degree;               /* total PC degree r, 0..8                                   */
     const double* k_fields;   /* host, (s+1)·n^dim doubles: k_0, ..., k_s at the nodes,
                                  x fastest (eq. random_wavenumber)                          */
-    double k_mean;            /* the mean wavenumber k̄: every entry of k_0 must equal it
-                                 (the preconditioners' block solve needs constant k̄)       */
+    double k_mean;            /* k̄ > 0: the constant mean wavenumber, every entry of k_0 must
+                                 equal it; the block solves of A_0 / M_0 use fast
+                                 diagonalisation (any precision).  0: k_0 varies in space
+                                 (the wedge of Section 7, eq. wavenumber_k123); the block
+                                 solves use an exact line-by-line block LU of S(k_0) in
+                                 FP64 (2D: n <= 257; its host setup costs O(n^4)).  Any
+                                 other value returns SG_EINVAL.                             */
     double csl_beta;          /* β of the CSL shift (Section 4, eq. shifted_helmholtz)      */
 } sg_problem;
 
@@ -84,10 +89,16 @@ typedef struct {
     int maxit;                /* cap on the total number of inner iterations                */
     int precond;              /* SG_PC_*                                                    */
     int precision;            /* SG_PREC_* for the preconditioner                           */
-    double tol;               /* target of the true relative residual ||b-Ax||_2/||b||_2   */
+    double tol;               /* target of the true relative residual ||b-Ax||_2/||b||_2
+                                 (left preconditioning: see side)                           */
     int x0_zero;              /* 1: start from x = 0; 0: x holds the initial guess          */
     double* hist;             /* host, optional: residual estimate after each iteration     */
     int hist_cap;             /* capacity of hist                                           */
+    int side;                 /* 0: right preconditioning A P^{-1} y = b, x = P^{-1} y (tol
+                                 on ||b-Ax||/||b||); 1: left, P^{-1} A x = P^{-1} b (eq.
+                                 CSL_preconditioned), whose residual is P^{-1}(b-Ax): tol on
+                                 ||P^{-1}(b-Ax)||/||P^{-1}b|| (Section 6.3).  Left is
+                                 available in sg_gmres with a built-in preconditioner.      */
 } sg_solve_opts;
 
 typedef struct {
@@ -96,12 +107,14 @@ typedef struct {
     int converged;            /* 1 if the true relative residual <= tol                     */
     int fallback;             /* 1 if the learned correction was switched off               */
     double relres_true;       /* final ||b-Ax||_2/||b||_2 recomputed in FP64                */
-    double relres_est;        /* final Arnoldi estimate |g_{j+1}|/||b||                     */
+    double relres_est;        /* final Arnoldi estimate |g_{j+1}|/||b|| (left: /||P^{-1}b||)  */
     double t_setup;           /* milliseconds                                               */
     double t_precond, t_matvec, t_orth;  /* GPU milliseconds per phase, measured only while
                                  profiling of every kind is on (sg_set_profiling), else 0:
                                  the events between the phases idle the GPU briefly    */
     double t_total;           /* milliseconds                                               */
+    double relres_prec;       /* left preconditioning: final ||P^{-1}(b-Ax)||/||P^{-1}b||, the
+                                 quantity tol applies to (right: equal to relres_true)      */
 } sg_solve_stats;
 
 /* Build the operator for one problem: basis, triple-product tables, coefficient
@@ -126,6 +139,17 @@ int  sg_rhs(sg_handle h, const double* f_host, sg_c64* b_dev, hipStream_t stream
 /* y = A x (Theorem 3.3), FP64, matrix-free; x and y must not overlap. */
 int  sg_apply(sg_handle h, const sg_c64* x, sg_c64* y, hipStream_t stream);
 
+/* Statistics of the SG solution u_m(x,ξ) = Σ_i V_i(x) φ_i(ξ) held in x (Section 7, Figure
+ * bE_Var): mean = E[u_m] = V_0 (device, n^dim complex, may be NULL) and var = [Var[Re u_m];
+ * Var[Im u_m]] = [Σ_{i>=1} (Re V_i)²; Σ_{i>=1} (Im V_i)²] (device, 2·n^dim doubles, may be
+ * NULL, not both).  Asynchronous on the stream. */
+int  sg_moments(sg_handle h, const sg_c64* x, sg_c64* mean, double* var, hipStream_t stream);
+
+/* γ_j = max{ ||V_i||_∞ : total degree of φ_i = j } for j = 0..degree (eq. magnitude_V,
+ * Figure k123_convergence): gamma_host, host, degree+1 doubles.  Synchronises the stream;
+ * SG_ENONFINITE if a coefficient is not finite. */
+int  sg_degree_magnitudes(sg_handle h, const sg_c64* x, double* gamma_host, hipStream_t stream);
+
 /* Select the operator of the handle: beta = 0 gives A (the default); beta != 0 gives the
  * full complex shifted Laplace matrix M(beta) = L - iB - (1 + i beta) K = A - i beta K
  * (eq. M, Section 4: only the k² block K is shifted, the boundary block is not).  It applies
@@ -139,11 +163,14 @@ int  sg_set_operator_shift(sg_handle h, double beta);
 
 /* z = P^{-1} r for P = A_0 or M_0 (pc = SG_PC_MEAN / SG_PC_CSL_MEAN) by fast
  * diagonalisation of the mean block (Section 5; Section 6.3 block reuse), in the given
- * precision; SG_PC_NONE copies.  r and z may alias. */
+ * precision; SG_PC_NONE copies.  With a spatially varying mean (k_mean = 0 at setup) the
+ * block solve is the line block LU, FP64 only (another precision: SG_EINVAL).  r and z may
+ * alias. */
 int  sg_precond(sg_handle h, int pc, int precision, const sg_c64* r, sg_c64* z, hipStream_t stream);
 
-/* Right-preconditioned restarted GMRES(m) (eq. CSL_preconditioned, eq. preconditioned_2d):
- * CGS2 Arnoldi, Givens least squares, true FP64 residual at each cycle end. */
+/* Restarted GMRES(m), right-preconditioned (eq. preconditioned_2d) or, with opts->side = 1,
+ * left-preconditioned (eq. CSL_preconditioned): CGS2 Arnoldi, Givens least squares, true FP64
+ * residual (left: preconditioned residual) at each cycle end. */
 int  sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
               sg_solve_stats* stats, hipStream_t stream);
 
@@ -179,7 +206,7 @@ int  sg_stationary(sg_handle h, const sg_c64* b, sg_c64* x, int pc, int iters, d
  * handles, b and x: host arrays of `count` entries; b[i], x[i] device vectors of
  * sg_size(handles[i]) complex, x[i] is overwritten (the initial guess is zero, opts
  * x0_zero is ignored).  A handle may appear only once.  opts->restart must be in
- * [1, 63]; opts->hist is ignored.  stats: host array of `count` entries or NULL
+ * [1, 63] and opts->side 0; opts->hist is ignored.  stats: host array of `count` entries or NULL
  * (t_precond / t_matvec / t_orth are 0; t_total is the wall time from admission to
  * completion).  The GEMM tile shape of each instance comes from the autotuner table
  * (sg_autotune / sg_tune_set), else a size-based default (3M 32×32 or 64×64 in FP64 and

@@ -16,6 +16,8 @@ Modules
   precond   mean-value (A_0), mean-CSL (M_0) and full CSL (M) preconditioners via sparse LU
   krylov    restarted right-preconditioned GMRES(m), FGMRES(m), stationary iteration
   spectral  dense condition numbers, spectra and norm bounds (Theorems 4.1, 5.1, 5.3)
+  moments   E[u], Var[Re u], Var[Im u] of the SG solution by quadrature over ξ, and the
+            per-degree magnitudes of eq. magnitude_V (Section 7)
   unet      numpy reference of the convolutional correction network of the learned
             preconditioner (forward, backward, Adam, SG vector <-> tensor maps)
 

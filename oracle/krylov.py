@@ -8,6 +8,8 @@ gmres   restarted GMRES(m) with *right* preconditioning: solves A M^{-1} y = b,
         and at the end of each cycle the true residual is recomputed; a cycle
         whose true relative residual is above tol is followed by a restart.
         restart >= maxit gives full GMRES (no restarts) as used in the paper.
+gmres_left  restarted GMRES(m) with *left* preconditioning, M^{-1} A x = M^{-1} b (eq.
+        CSL_preconditioned); residual and stopping test on M^{-1} r (Section 6.3).
 fgmres  flexible variant that stores the preconditioned vectors Z (Saad 1993).
 stationary  the iteration B x^{(i+1)} = b - (A - B) x^{(i)} with B = A_0 and
         x^{(0)} = A_0^{-1} b (eq. stationary_iteration, eq. stationary_iteration_A0).
@@ -27,6 +29,7 @@ class SolveInfo:
     relres_true: float = np.inf
     breakdown: bool = False
     hist: list = field(default_factory=list)
+    relres_prec: float = np.inf   # left preconditioning: ||M^{-1}(b - Ax)|| / ||M^{-1}b||
     H: np.ndarray | None = None   # Hessenberg of the last cycle (unrotated)
     V: np.ndarray | None = None   # Arnoldi basis of the last cycle
 
@@ -125,6 +128,83 @@ def gmres(A, b, M=None, restart: int = 50, tol: float = 1e-8, maxit: int = 10000
             info.relres_true = np.linalg.norm(r) / bnorm
             info.converged = info.relres_true <= tol
             break
+    return x, info
+
+
+def gmres_left(A, b, M=None, restart: int = 50, tol: float = 1e-8, maxit: int = 10000, x0=None):
+    """Left-preconditioned restarted GMRES(m): Arnoldi on M^{-1}A with the start vector
+    M^{-1}(b - A x) (the second system of eq. CSL_preconditioned).  Its residual is the
+    preconditioned one, M^{-1} r (Section 6.3), so the stopping test is
+    ||M^{-1}(b - A x)|| / ||M^{-1} b|| <= tol: the Arnoldi estimate |g_{j+1}| / ||M^{-1} b||
+    during a cycle, the recomputed value at each cycle end.  The update is x += V y (no
+    preconditioner application).  Modified Gram-Schmidt and complex Givens rotations as in
+    ``gmres``.  ``info.relres_prec`` holds the final preconditioned relative residual and
+    ``info.relres_true`` the unpreconditioned ||b - Ax|| / ||b||."""
+    M = M or _identity
+    b = np.asarray(b, dtype=np.complex128)
+    info = SolveInfo()
+    bp = M(b)
+    bpnorm = np.linalg.norm(bp)
+    bnorm = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128)
+    if bnorm == 0.0:
+        info.converged, info.relres_true, info.relres_prec = True, 0.0, 0.0
+        return np.zeros_like(b), info
+    m = int(max(1, min(restart, maxit, b.size)))
+    while True:
+        r = M(b - A(x))
+        beta = np.linalg.norm(r)
+        info.relres_prec = beta / bpnorm
+        if info.relres_prec <= tol:
+            info.converged = True
+            break
+        if info.iters >= maxit:
+            break
+        info.cycles += 1
+        V = np.zeros((m + 1, b.size), dtype=np.complex128)
+        H = np.zeros((m + 1, m), dtype=np.complex128)
+        R = np.zeros((m + 1, m), dtype=np.complex128)
+        cs = np.zeros(m)
+        sn = np.zeros(m, dtype=np.complex128)
+        g = np.zeros(m + 1, dtype=np.complex128)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        for j in range(m):
+            w = M(A(V[j]))
+            for i in range(j + 1):                 # modified Gram-Schmidt
+                H[i, j] = np.vdot(V[i], w)
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            col = H[: j + 2, j].copy()
+            for i in range(j):
+                t = cs[i] * col[i] + sn[i] * col[i + 1]
+                col[i + 1] = -np.conj(sn[i]) * col[i] + cs[i] * col[i + 1]
+                col[i] = t
+            cs[j], sn[j] = givens(col[j], col[j + 1])
+            col[j] = cs[j] * col[j] + sn[j] * col[j + 1]
+            col[j + 1] = 0.0
+            R[: j + 2, j] = col
+            g[j + 1] = -np.conj(sn[j]) * g[j]
+            g[j] = cs[j] * g[j]
+            info.iters += 1
+            k = j + 1
+            est = abs(g[j + 1]) / bpnorm
+            info.hist.append(est)
+            hnorm = np.linalg.norm(H[: j + 2, j])
+            if H[j + 1, j].real <= 1e-14 * max(hnorm, 1e-300):
+                info.breakdown = True
+                break
+            V[j + 1] = w / H[j + 1, j]
+            if est <= tol or info.iters >= maxit:
+                break
+        y = np.linalg.solve(np.triu(R[:k, :k]), g[:k]) if k > 0 else np.zeros(0)
+        x = x + V[:k].T @ y
+        if info.breakdown:
+            info.relres_prec = np.linalg.norm(M(b - A(x))) / bpnorm
+            info.converged = info.relres_prec <= tol
+            break
+    info.relres_true = np.linalg.norm(b - A(x)) / bnorm
     return x, info
 
 

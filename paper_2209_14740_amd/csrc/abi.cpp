@@ -99,6 +99,26 @@ int sg_apply(sg_handle h, const sg_c64* x, sg_c64* y, hipStream_t stream) {
     })
 }
 
+int sg_moments(sg_handle h, const sg_c64* x, sg_c64* mean, double* var, hipStream_t stream) {
+    SG_TRY({
+        if (!h || !x || (!mean && !var)) return fail(SG_EINVAL, "null argument");
+        Ctx* c = ctx(h);
+        if (int rc = guard_device(c)) return rc;
+        ProfBind pb(c);
+        return sgi::launch_moments(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(mean), var,
+                                   stream);
+    })
+}
+
+int sg_degree_magnitudes(sg_handle h, const sg_c64* x, double* gamma_host, hipStream_t stream) {
+    SG_TRY({
+        if (!h || !x || !gamma_host) return fail(SG_EINVAL, "null argument");
+        Ctx* c = ctx(h);
+        if (int rc = guard_device(c)) return rc;
+        return sgi::degree_magnitudes(c, reinterpret_cast<const double2*>(x), gamma_host, stream);
+    })
+}
+
 int sg_set_operator_shift(sg_handle h, double beta) {
     SG_TRY({
         if (!h) return fail(SG_EINVAL, "null handle");
@@ -421,6 +441,7 @@ int sg_attach_net(sg_handle h, sg_net net) {
         if (net) {
             sgi::Net* n = netp(net);
             if (n->device != c->device) return fail(SG_EINVAL, "network and handle are on different devices");
+            if (c->vmean) return fail(SG_EINVAL, "the learned correction needs a constant mean wavenumber");
             if (c->dim != 2 || n->Q != c->Q || n->s != c->s)
                 return fail(SG_EINVAL, "network shape does not match the problem (2D, same Q and s)");
         }

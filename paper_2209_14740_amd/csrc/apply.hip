@@ -187,6 +187,7 @@ ApplyArgs make_apply_args(const Ctx* c, const double2* x, double2* y) {
     a.nrows = c->dim == 2 ? c->n : 1;
     a.KF = c->d_kf;
     a.k0 = c->kbar;
+    a.K0 = c->d_k0;
     a.ih = 1.0 / c->h;
     return a;
 }

@@ -23,6 +23,7 @@ struct ApplyArgs {
     int ntiles_x, nrows;
     const double* KF;     // k_1..k_s at the nodes ([s][P]) for the shape-specialised kernels
     double k0, ih;        // constant mean k_0 and 1/h
+    const double* K0;     // k_0 at the nodes when it varies in space (null: the constant k0)
     double csl_beta;      // 0: the operator A; β: the shifted operator M(β) = A - iβK (k² block times 1+iβ)
 };
 

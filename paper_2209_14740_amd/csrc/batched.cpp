@@ -200,6 +200,10 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
     if (!(o->tol > 0)) return fail(SG_EINVAL, "tol must be positive");
     if (o->precond < SG_PC_NONE || o->precond > SG_PC_CSL_MEAN) return fail(SG_EINVAL, "unsupported preconditioner");
     if (o->precision < SG_PREC_F64 || o->precision > SG_PREC_BF16X3) return fail(SG_EINVAL, "unknown precision");
+    if (o->side != 0) return fail(SG_EINVAL, "batched solve: right preconditioning only");
+    for (int i = 0; i < count; ++i)
+        if (ctx[i] && ctx[i]->vmean)
+            return fail(SG_EINVAL, "batched solve: handles with a spatially varying mean are not supported");
     const int m = o->restart;
     const int pc = o->precond, prec = o->precision;
 
@@ -716,7 +720,7 @@ int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out
     std::map<std::pair<int, int>, std::vector<Ctx*>> classes;
     for (int i = 0; i < count; ++i) {
         if (!ctx[i]) return fail(SG_EINVAL, "null handle");
-        if (ctx[i]->dim == 2) classes[{ctx[i]->n, ctx[i]->Q}].push_back(ctx[i]);
+        if (ctx[i]->dim == 2 && !ctx[i]->vmean) classes[{ctx[i]->n, ctx[i]->Q}].push_back(ctx[i]);
     }
     hipEvent_t e0, e1;
     SG_HIP(hipEventCreate(&e0));

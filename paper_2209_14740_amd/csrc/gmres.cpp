@@ -158,6 +158,10 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
         return fail(SG_EINVAL, "unsupported built-in preconditioner");
     if (!cb && o->precond == SG_PC_MEAN_NET && (!c->net || !flexible))
         return fail(SG_EINVAL, "the learned preconditioner needs an attached network and flexible GMRES");
+    if (o->side != 0 && o->side != 1) return fail(SG_EINVAL, "side must be 0 (right) or 1 (left)");
+    const bool left = o->side == 1;
+    if (left && (flexible || cb || o->precond == SG_PC_MEAN_NET))
+        return fail(SG_EINVAL, "left preconditioning is available in sg_gmres with a built-in preconditioner");
     const int m = o->restart;
     int rc = ensure_workspace(c, m, flexible);
     if (rc) return rc;
@@ -177,17 +181,29 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
     };
 
     double bnorm = 0;
-    // from x = 0 the first residual is b itself: its norm and lazy scale serve the first cycle
-    if ((rc = norm_sync(c, b, &bnorm, stream, o->x0_zero ? W.scale : nullptr))) return rc;
+    // from x = 0 the first residual is b itself (right) or P^{-1} b (left): its norm and lazy
+    // scale serve the first cycle
+    if ((rc = norm_sync(c, b, &bnorm, stream, (o->x0_zero && !left) ? W.scale : nullptr))) return rc;
     if (!std::isfinite(bnorm)) return fail(SG_ENONFINITE, "non-finite right-hand side");
     if (o->x0_zero) SG_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double2), stream));
     if (bnorm == 0.0) {
         SG_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double2), stream));
         SG_HIP(hipStreamSynchronize(stream));
         s.converged = 1;
+        s.relres_prec = 0.0;
         if (st) *st = s;
         return SG_OK;
     }
+    // Left preconditioning (eq. CSL_preconditioned, second system): the residual is the
+    // preconditioned one (Section 6.3), so the relative test uses ||P^{-1} b||.
+    double pbnorm = bnorm;
+    if (left) {
+        if ((rc = precond(b, W.tmp))) return rc;
+        if ((rc = norm_sync(c, W.tmp, &pbnorm, stream, o->x0_zero ? W.scale : nullptr))) return rc;
+        if (!std::isfinite(pbnorm)) return fail(SG_ENONFINITE, "non-finite preconditioned right-hand side");
+        if (pbnorm == 0.0) return fail(SG_EBREAKDOWN, "the preconditioned right-hand side is zero");
+    }
+    const double rden = left ? pbnorm : bnorm;
     // The preconditioner and operator of Arnoldi step j+1 need no host result (the lazy
     // scale of v_{j+1} is formed on the device), so with the built-in preconditioners they
     // are queued before the host waits for step j's coefficients, hiding the host's turn
@@ -206,23 +222,26 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
     int result = SG_ENOTCONV;
 
     while (true) {
-        // r = b - A x, stored as V_0
+        // r = b - A x (left: P^{-1}(b - A x)), stored as V_0
         if (first && o->x0_zero) {
-            SG_HIP(hipMemcpyAsync(Vb, b, (size_t)n * sizeof(double2), hipMemcpyDeviceToDevice, stream));
+            SG_HIP(hipMemcpyAsync(Vb, left ? W.tmp : b, (size_t)n * sizeof(double2), hipMemcpyDeviceToDevice, stream));
         } else {
             tm.record(0, stream);
             if ((rc = launch_apply(c, x, ut, stream))) return rc;
             tm.record(1, stream);
-            if ((rc = launch_axpby(n, make_double2(1, 0), b, make_double2(-1, 0), ut, Vb, stream))) return rc;
+            if ((rc = launch_axpby(n, make_double2(1, 0), b, make_double2(-1, 0), ut, left ? ut : Vb, stream)))
+                return rc;
+            if (left && (rc = precond(ut, Vb))) return rc;
         }
-        double beta = bnorm;
+        double beta = rden;
         if (!(first && o->x0_zero) && (rc = norm_sync(c, Vb, &beta, stream, W.scale)))   // W.scale[0] = 1/beta
             return rc;
         if (!(first && o->x0_zero)) s.t_matvec += tm.between(0, 1);
         first = false;
         if (!std::isfinite(beta)) return fail(SG_ENONFINITE, "non-finite residual");
-        s.relres_true = beta / bnorm;
-        if (s.relres_true <= o->tol) { result = SG_OK; s.converged = 1; break; }
+        if (left) s.relres_prec = beta / rden;
+        else s.relres_true = beta / bnorm;
+        if (beta / rden <= o->tol) { result = SG_OK; s.converged = 1; break; }
         if (s.iters >= o->maxit) break;
         hscale[0] = 1.0 / beta;   // the same value the device stored in W.scale[0]
         std::fill(g.begin(), g.end(), cd(0));
@@ -231,7 +250,13 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
         bool breakdown = false;
         bool queued = false;                 // step j's preconditioner and operator already queued
         double est_prev = s.relres_true;     // latest residual estimate
-        auto queue_pa = [&](int jj) -> int {   // w_{jj+1} = A P^{-1} V_jj (unscaled)
+        auto queue_pa = [&](int jj) -> int {   // w_{jj+1} = A P^{-1} V_jj (left: P^{-1} A V_jj), unscaled
+            if (left) {
+                int r2 = launch_apply(c, Vb + (long long)jj * ldv, ut, stream);
+                if (r2) return r2;
+                tm.record(1, stream);
+                return precond(ut, Vb + (long long)(jj + 1) * ldv);
+            }
             double2* zz = flexible ? W.Z + (long long)jj * ldv : zt;
             int r2 = precond(Vb + (long long)jj * ldv, zz);
             if (r2) return r2;
@@ -298,7 +323,7 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             g[j] = cj * g[j];
             ++s.iters;
             k = j + 1;
-            s.relres_est = std::abs(g[j + 1]) / bnorm;
+            s.relres_est = std::abs(g[j + 1]) / rden;
             est_prev = s.relres_est;
             if (o->hist && s.iters - 1 < o->hist_cap) o->hist[s.iters - 1] = s.relres_est;
             if (!(nrm > 1e-14 * colnorm / (sj > 0 ? sj : 1.0)) || hnext <= 1e-14 * colnorm) { breakdown = true; break; }
@@ -316,7 +341,9 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
         }
         for (int i = 0; i < k; ++i) W.host_pinned[i] = make_double2(y[i].real(), y[i].imag());
         SG_HIP(hipMemcpyAsync(W.coef, W.host_pinned, (size_t)k * sizeof(double2), hipMemcpyHostToDevice, stream));
-        if (flexible) {
+        if (left) {
+            if ((rc = launch_lincomb(n, k, Vb, ldv, W.scale, W.coef, x, stream))) return rc;   // x += V y
+        } else if (flexible) {
             // z_j = P^{-1}(s_j V_j) was formed from the unscaled V_j: the same lazy scales
             // W.scale[0..k) apply to Z
             if ((rc = launch_lincomb(n, k, W.Z, ldv, W.scale, W.coef, x, stream))) return rc;
@@ -334,13 +361,24 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             tm.record(0, stream);
             if ((rc = launch_apply(c, x, ut, stream))) return rc;
             if ((rc = launch_axpby(n, make_double2(1, 0), b, make_double2(-1, 0), ut, ut, stream))) return rc;
+            if (left && (rc = precond(ut, zt))) return rc;
             double rn = 0;
-            if ((rc = norm_sync(c, ut, &rn, stream))) return rc;
-            s.relres_true = rn / bnorm;
-            if (s.relres_true <= o->tol) { result = SG_OK; s.converged = 1; }
+            if ((rc = norm_sync(c, left ? zt : ut, &rn, stream))) return rc;
+            if (left) s.relres_prec = rn / rden;
+            else s.relres_true = rn / bnorm;
+            if (rn / rden <= o->tol) { result = SG_OK; s.converged = 1; }
             else result = SG_EBREAKDOWN;
             break;
         }
+    }
+    if (left) {   // the unpreconditioned residual of the final iterate, reported beside it
+        if ((rc = launch_apply(c, x, ut, stream))) return rc;
+        if ((rc = launch_axpby(n, make_double2(1, 0), b, make_double2(-1, 0), ut, ut, stream))) return rc;
+        double rn = 0;
+        if ((rc = norm_sync(c, ut, &rn, stream))) return rc;
+        s.relres_true = rn / bnorm;
+    } else {
+        s.relres_prec = s.relres_true;
     }
     s.t_setup = c->t_setup_ms;
     s.t_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

@@ -1104,6 +1104,11 @@ int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, 
     }
     if (pc != SG_PC_MEAN && pc != SG_PC_CSL_MEAN) return fail(SG_EINVAL, "sg_precond: unknown preconditioner");
     if (precision < SG_PREC_F64 || precision > SG_PREC_BF16X3) return fail(SG_EINVAL, "sg_precond: unknown precision");
+    if (c->vmean) {
+        if (precision != SG_PREC_F64)
+            return fail(SG_EINVAL, "sg_precond: a spatially varying mean is solved in FP64 only");
+        return launch_line(c, pc, r, z, st);
+    }
     const TriFactors& f = c->tri[pc == SG_PC_MEAN ? 0 : 1];
     const int n = c->n;
     if (c->dim == 1) {

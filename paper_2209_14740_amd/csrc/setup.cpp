@@ -450,6 +450,10 @@ Ctx::~Ctx() {
     if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
     if (ws.done) (void)hipEventDestroy(ws.done);
     (void)hipFree(d_tmp_pc);
+    (void)hipFree(d_k0);
+    (void)hipFree(d_lineE[0]);
+    (void)hipFree(d_lineE[1]);
+    (void)hipFree(d_lineb);
 }
 
 // ------------------------------------------------------------------ setup
@@ -476,10 +480,20 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     for (int d = 0; d < p->dim; ++d) c->P *= p->n;
     const long long P = c->P;
     const int s = p->s;
-    for (long long i = 0; i < P; ++i)
-        if (p->k_fields[i] != p->k_mean)
-            return fail(SG_EINVAL, "k_0 must be spatially constant and equal to k_mean");
-    if (!(p->k_mean > 0)) return fail(SG_EINVAL, "k_mean must be positive");
+    if (p->k_mean == 0.0) {
+        // spatially varying mean (Section 7): exact line block LU instead of fast diagonalisation
+        c->vmean = true;
+        if (p->dim == 2 && p->n > 257)
+            return fail(SG_EINVAL, "a spatially varying mean needs n <= 257 in 2D (its line factorisation costs O(n^4) on the host)");
+        for (long long i = 0; i < P; ++i)
+            if (!std::isfinite(p->k_fields[i])) return fail(SG_EINVAL, "k_0 must be finite");
+    } else {
+        for (long long i = 0; i < P; ++i)
+            if (p->k_fields[i] != p->k_mean)
+                return fail(SG_EINVAL, "k_0 must be spatially constant and equal to k_mean (or k_mean = 0 for a "
+                                       "spatially varying mean)");
+        if (!(p->k_mean > 0)) return fail(SG_EINVAL, "k_mean must be positive");
+    }
 
     c->alpha = make_basis(s, p->degree);
     c->Q = (int)(c->alpha.size() / s);
@@ -577,6 +591,16 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     SG_HIP(hipMalloc(&c->d_kf, (size_t)s * P * sizeof(double)));
     SG_HIP(hipMemcpy(c->d_kf, p->k_fields + P, (size_t)s * P * sizeof(double), hipMemcpyHostToDevice));
 
+    if (c->vmean) {
+        SG_HIP(hipMalloc(&c->d_k0, (size_t)P * sizeof(double)));
+        SG_HIP(hipMemcpy(c->d_k0, p->k_fields, (size_t)P * sizeof(double), hipMemcpyHostToDevice));
+        int rc = build_line_factors(c.get(), p->k_fields);
+        if (rc) return rc;
+        SG_HIP(hipDeviceSynchronize());
+        c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = c.release();
+        return SG_OK;
+    }
     // mean-block factors for A_0 (c = k̄²) and M_0 (c = (1+iβ)k̄²)
     const double kb = p->k_mean;
     const cplx cshift[2] = {cplx(kb * kb, 0.0), cplx(kb * kb, p->csl_beta * kb * kb)};

@@ -202,6 +202,13 @@ struct Ctx {
     double op_csl_beta = 0.0;          // operator of sg_apply and the solvers: A (0) or M(β) = A - iβK
     double2* d_tmp_pc = nullptr;       // preconditioner intermediate: Q·n rows of tld complex (2D)
     int tld = 0;                       // its row length, n rounded up to 8 (128-byte aligned rows)
+    // spatially varying mean k_0 (k_mean = 0 at setup): exact block LU over the grid lines
+    bool vmean = false;
+    double* d_k0 = nullptr;            // k_0 at the nodes for the operator (null: constant kbar)
+    int line_L = 0, line_nl = 0;       // line length and number of lines
+    double2* d_lineE[2] = {};          // inverses of the line Schur complements, [j][k][i], A_0 and M_0
+    double* d_lineb = nullptr;         // diagonal of the line coupling B
+    double line_check[2] = {};         // setup residual of the factorisation (A_0, M_0)
     Net* net = nullptr;                // attached correction network (not owned)
     double t_setup_ms = 0;
 
@@ -219,6 +226,14 @@ bool apply_available(const Ctx* c, double csl_beta);
 // batched.cpp (autotuner table)
 int tune_get(int n, int Q, int precision);
 void tune_set(int n, int Q, int precision, int cfg);
+
+// stats.hip (statistics of the solution)
+int launch_moments(const Ctx* c, const double2* x, double2* mean, double* var, hipStream_t st);
+int degree_magnitudes(const Ctx* c, const double2* x, double* gamma, hipStream_t st);
+
+// line.hip (block solves with a spatially varying mean)
+int build_line_factors(Ctx* c, const double* k0_host);
+int launch_line(Ctx* c, int pc, const double2* r, double2* z, hipStream_t st);
 
 // precond.hip
 int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, hipStream_t st);

@@ -21,6 +21,7 @@ SG_BC_ABSORBING = 0
 
 PC = {"none": SG_PC_NONE, "mean": SG_PC_MEAN, "csl": SG_PC_CSL_MEAN, "net": SG_PC_MEAN_NET}
 PREC = {"f64": SG_PREC_F64, "f32": SG_PREC_F32, "bf16x3": SG_PREC_BF16X3}
+SIDE = {"right": 0, "left": 1}
 
 
 class SGError(RuntimeError):
@@ -38,14 +39,15 @@ class Problem(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("precond", C.c_int), ("precision", C.c_int),
-                ("tol", C.c_double), ("x0_zero", C.c_int), ("hist", C.POINTER(C.c_double)), ("hist_cap", C.c_int)]
+                ("tol", C.c_double), ("x0_zero", C.c_int), ("hist", C.POINTER(C.c_double)), ("hist_cap", C.c_int),
+                ("side", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int), ("fallback", C.c_int),
                 ("relres_true", C.c_double), ("relres_est", C.c_double), ("t_setup", C.c_double),
                 ("t_precond", C.c_double), ("t_matvec", C.c_double), ("t_orth", C.c_double),
-                ("t_total", C.c_double)]
+                ("t_total", C.c_double), ("relres_prec", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -81,6 +83,8 @@ def lib():
     L.sg_fgmres.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), PRECOND_CB, vp, C.POINTER(SolveStats), vp]
     L.sg_stationary.argtypes = [vp, vp, vp, i, i, C.POINTER(d), vp]
     L.sg_set_operator_shift.argtypes = [vp, d]
+    L.sg_moments.argtypes = [vp, vp, vp, vp, vp]
+    L.sg_degree_magnitudes.argtypes = [vp, vp, C.POINTER(d), vp]
     L.sg_cgs2.argtypes = [ll, i, vp, vp, vp, vp]
     L.sg_cgs2_noalloc.argtypes = [ll, i, vp, vp, vp, vp]
     L.sg_norm.argtypes = [ll, vp, C.POINTER(d), vp]
@@ -113,7 +117,8 @@ def lib():
     L.sg_last_error.argtypes = []
     L.sg_last_error.restype = C.c_char_p
     for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
-                 "sg_stationary", "sg_set_operator_shift", "sg_cgs2", "sg_cgs2_noalloc", "sg_norm", "sg_axpby", "sg_set_profiling",
+                 "sg_stationary", "sg_set_operator_shift", "sg_moments", "sg_degree_magnitudes", "sg_cgs2",
+                 "sg_cgs2_noalloc", "sg_norm", "sg_axpby", "sg_set_profiling",
                  "sg_kernel_times", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
                  "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step", "sg_net_train_pairs", "sg_net_save",
                  "sg_net_load", "sg_attach_net", "sg_profile_kinds"):
@@ -165,7 +170,10 @@ class SG:
 
     @classmethod
     def from_instance(cls, inst, stream=None):
-        return cls(inst.dim, inst.n, inst.s, inst.degree, inst.k_fields, inst.k_mean, inst.beta, stream)
+        """Handle for a ``workloads.Instance``; a NaN k_mean (k_0 varies in space) selects the
+        varying-mean block solves (k_mean = 0 at the ABI)."""
+        km = inst.k_mean if np.isfinite(inst.k_mean) else 0.0
+        return cls(inst.dim, inst.n, inst.s, inst.degree, inst.k_fields, km, inst.beta, stream)
 
     def close(self):
         if self._h:
@@ -212,6 +220,23 @@ class SG:
                                C.c_void_p(_stream(stream))), "sg_precond")
         return z
 
+    def moments(self, x, stream=None):
+        """(E[u], Var[Re u], Var[Im u]) of the SG solution x, as torch tensors on the device."""
+        import torch
+        mean = torch.empty(self.n ** self.dim, dtype=torch.complex128, device="cuda")
+        var = torch.empty(2 * self.n ** self.dim, dtype=torch.float64, device="cuda")
+        check(lib().sg_moments(self._h, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(mean)), C.c_void_p(var.data_ptr()),
+                               C.c_void_p(_stream(stream))), "sg_moments")
+        P = self.n ** self.dim
+        return mean, var[:P], var[P:]
+
+    def degree_magnitudes(self, x, stream=None) -> np.ndarray:
+        """γ_j = max ||V_i||_∞ over the basis polynomials of total degree j (j = 0..degree)."""
+        out = (C.c_double * (self.degree + 1))()
+        check(lib().sg_degree_magnitudes(self._h, C.c_void_p(_ptr(x)), out, C.c_void_p(_stream(stream))),
+              "sg_degree_magnitudes")
+        return np.array(out[:])
+
     def set_operator_shift(self, beta: float):
         """Operator of this handle: A (beta = 0) or M(beta) = A - i beta K."""
         check(lib().sg_set_operator_shift(self._h, float(beta)), "sg_set_operator_shift")
@@ -226,18 +251,21 @@ class SG:
                                   C.c_void_p(_stream(stream))), "sg_stationary")
         return x, (list(harr) if hist else None)
 
-    def _opts(self, restart, maxit, pc, precision, tol, x0_zero, hist):
+    def _opts(self, restart, maxit, pc, precision, tol, x0_zero, hist, side="right"):
         harr = None
         if hist:
             harr = (C.c_double * maxit)()
         o = SolveOpts(restart, maxit, PC[pc], PREC[precision], tol, 1 if x0_zero else 0,
-                      C.cast(harr, C.POINTER(C.c_double)) if harr is not None else None, maxit if hist else 0)
+                      C.cast(harr, C.POINTER(C.c_double)) if harr is not None else None, maxit if hist else 0,
+                      SIDE[side])
         return o, harr
 
     def gmres(self, b, x=None, restart=50, maxit=1000, pc="mean", precision="f64", tol=1e-8, x0_zero=True,
-              hist=False, stream=None):
+              hist=False, side="right", stream=None):
+        """Restarted GMRES(m); side="left" preconditions from the left (tol then applies to the
+        preconditioned residual, reported as info["relres_prec"])."""
         x = self.empty() if x is None else x
-        o, harr = self._opts(restart, maxit, pc, precision, tol, x0_zero, hist)
+        o, harr = self._opts(restart, maxit, pc, precision, tol, x0_zero, hist, side)
         st = SolveStats()
         rc = check(lib().sg_gmres(self._h, C.c_void_p(_ptr(b)), C.c_void_p(_ptr(x)), C.byref(o), C.byref(st),
                                   C.c_void_p(_stream(stream))), "sg_gmres")
@@ -307,7 +335,7 @@ def gmres_batched(ops, bs, xs=None, restart=30, maxit=1000, pc="mean", precision
     H = (C.c_void_p * cnt)(*[op._h.value for op in ops])
     B = (C.c_void_p * cnt)(*[_ptr(b) for b in bs])
     X = (C.c_void_p * cnt)(*[_ptr(x) for x in xs])
-    o = SolveOpts(restart, maxit, PC[pc], PREC[precision], tol, 1, None, 0)
+    o = SolveOpts(restart, maxit, PC[pc], PREC[precision], tol, 1, None, 0, 0)
     st = (SolveStats * cnt)()
     rc = check(lib().sg_gmres_batched(cnt, H, B, X, C.byref(o), st, C.c_void_p(_stream(stream))),
                "sg_gmres_batched")
@@ -447,7 +475,7 @@ def norm(x, stream=None) -> float:
 
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
-            "sg_fgmres", "sg_stationary", "sg_set_operator_shift", "sg_gmres_batched", "sg_autotune", "sg_tune_get",
+            "sg_fgmres", "sg_stationary", "sg_set_operator_shift", "sg_moments", "sg_degree_magnitudes", "sg_gmres_batched", "sg_autotune", "sg_tune_get",
             "sg_tune_set", "sg_cgs2", "sg_cgs2_noalloc", "sg_norm", "sg_axpby",
             "sg_set_profiling", "sg_profile_kinds", "sg_kernel_times", "sg_net_create", "sg_net_destroy", "sg_net_num_params",
             "sg_net_get_params", "sg_net_set_params", "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step",

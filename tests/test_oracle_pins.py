@@ -475,3 +475,98 @@ def test_pointwise_rows_equal_assembled_matrix():
         pts = np.array([0, 1, S.P // 2, S.P - 1])
         full = (S.A @ x).reshape(S.Q, S.P)[:, pts]
         np.testing.assert_allclose(assemble.apply_at_points(inst, x, pts), full, rtol=1e-13, atol=1e-9)
+
+
+# ------------------------------------------------ left preconditioning (Section 6.3)
+
+def test_left_gmres_reductions_and_exactness():
+    """Left-preconditioned GMRES (eq. CSL_preconditioned, second system): with M = I it is
+    plain GMRES (same iterates as the right-preconditioned code with M = I); with M = A^{-1}
+    exact it converges in one step; run to full length it reaches the direct solution, and
+    its Arnoldi estimate is the true preconditioned residual of the final iterate."""
+    inst = small_2d(n=9, kbar=4.0, sigma=0.4, s=2, degree=2)
+    S = assemble.from_instance(inst)
+    A = lambda v: S.A @ v                                         # noqa: E731
+    xl, il = krylov.gmres_left(A, S.b, None, restart=15, tol=1e-10, maxit=300)
+    xr, ir = krylov.gmres(A, S.b, None, restart=15, tol=1e-10, maxit=300)
+    assert il.iters == ir.iters and np.allclose(il.hist, ir.hist, rtol=1e-10, atol=0)
+    assert np.max(np.abs(xl - xr)) <= 1e-12 * np.max(np.abs(xr))
+    lu = spla.splu(S.A.tocsc())
+    x1, i1 = krylov.gmres_left(A, S.b, lu.solve, restart=5, tol=1e-12, maxit=5)
+    assert i1.iters == 1 and i1.converged
+    xd = precond.direct_solve(S)
+    P = precond.mean_value(S)
+    xf, info = krylov.gmres_left(A, S.b, P, restart=400, tol=1e-13, maxit=400)
+    assert info.converged and np.max(np.abs(xf - xd)) <= 1e-9 * np.max(np.abs(xd))
+    true_prec = np.linalg.norm(P(S.b - S.A @ xf)) / np.linalg.norm(P(S.b))
+    assert abs(info.hist[-1] - true_prec) <= 1e-3 * true_prec + 1e-15
+    assert info.relres_prec <= 1e-13 and abs(info.relres_true - np.linalg.norm(S.b - S.A @ xf) / np.linalg.norm(S.b)) < 1e-18
+
+
+def test_left_and_right_similar_k50():
+    """Section 6.3, k̄ = 50, θ = 0.1, degree 3: left and right preconditioning give very
+    similar residual histories; the left counts are near the paper's iteration numbers
+    (about 50 for M and M_0, about 25 for A_0; full GMRES to 1e-12) and within a few steps
+    of the right-preconditioned ones."""
+    inst = one_d_paper(50.0, 0.1, degree=3)
+    S = assemble.from_instance(inst)
+    A = lambda v: S.A @ v                                         # noqa: E731
+    for name, P, paper in (("M", precond.full_csl(S, 0.5), 50), ("M0", precond.mean_csl(S, 0.5), 50),
+                           ("A0", precond.mean_value(S), 25)):
+        il = krylov.gmres_left(A, S.b, P, restart=10 ** 6, tol=1e-12, maxit=5000)[1]
+        ir = krylov.gmres(A, S.b, P, restart=10 ** 6, tol=1e-12, maxit=5000)[1]
+        assert il.converged and abs(il.iters - ir.iters) <= 4, (name, il.iters, ir.iters)
+        assert abs(il.iters - paper) <= 0.25 * paper, (name, il.iters)
+
+
+# ------------------------------------------------ statistics of the SG solution (Section 7)
+
+def test_moments_closed_forms_and_reductions():
+    """E[u] and Var[Re u], Var[Im u] computed by quadrature over ξ (the definition) equal the
+    orthonormal-basis closed forms V_0 and Σ_{i>=1} (Re V_i)², (Im V_i)² for any coefficient
+    vector; for σ = 0 the SG solution is the deterministic FD solution (Corollary 3.2), so the
+    mean is that solution and the variance vanishes."""
+    from oracle import moments
+    rng = np.random.default_rng(4)
+    for s_, r_, P in ((1, 4, 7), (2, 3, 5), (3, 2, 4)):
+        Q = math.comb(s_ + r_, s_)
+        V = rng.standard_normal(Q * P) + 1j * rng.standard_normal(Q * P)
+        Vm = V.reshape(Q, P)
+        assert np.allclose(moments.expectation(V, s_, r_, P), Vm[0], rtol=1e-12, atol=1e-12)
+        vr, vi = moments.variance_re_im(V, s_, r_, P)
+        assert np.allclose(vr, (Vm[1:].real ** 2).sum(axis=0), rtol=1e-11)
+        assert np.allclose(vi, (Vm[1:].imag ** 2).sum(axis=0), rtol=1e-11)
+    inst = small_2d(n=11, kbar=5.0, sigma=0.0, s=2, degree=2)
+    S = assemble.from_instance(inst)
+    x = precond.direct_solve(S)
+    ud = spla.spsolve(assemble.mean_block(S).tocsc(), S.b[:S.P])
+    assert np.allclose(moments.expectation(x, 2, 2, S.P), ud, rtol=1e-10, atol=1e-14)
+    vr, vi = moments.variance_re_im(x, 2, 2, S.P)
+    assert np.max(vr) < 1e-24 and np.max(vi) < 1e-24
+
+
+def test_moments_agree_with_collocation_1d():
+    """Independent check of the whole SG chain: E[u] and Var[Re u] of the SG solution (1D,
+    k = 20(1 + 0.1ξ), degree 6) agree with the mean and variance of deterministic FD solves
+    at 24 Gauss-Legendre points in ξ (stochastic collocation), within the SG truncation
+    error, and the per-degree magnitudes γ_j of eq. magnitude_V decay (Section 7)."""
+    from oracle import moments
+    inst = one_d_paper(20.0, 0.1, degree=6)
+    S = assemble.from_instance(inst)
+    x = precond.direct_solve(S)
+    g, w = np.polynomial.legendre.leggauss(24)
+    w = w / 2.0
+    us = []
+    for xi in g:
+        k = inst.k_fields[0] + xi * inst.k_fields[1]
+        Sd = fd.deterministic_S(1, inst.n, "absorbing", k)
+        us.append(spla.spsolve(Sd.tocsc(), S.b[:S.P]))
+    us = np.array(us)
+    mean_c = w @ us
+    var_c = w @ (us.real - mean_c.real) ** 2
+    mean_sg = moments.expectation(x, 1, 6, S.P)
+    var_sg = moments.variance_re_im(x, 1, 6, S.P)[0]
+    assert np.max(np.abs(mean_sg - mean_c)) <= 1e-6 * np.max(np.abs(mean_c))
+    assert np.max(np.abs(var_sg - var_c)) <= 1e-4 * np.max(var_c)
+    gam = moments.degree_magnitudes(x, 1, 6, S.P)
+    assert np.all(np.diff(gam) < 0) and gam[-1] < 1e-3 * gam[0]
