@@ -58,7 +58,9 @@ def set_profiling(op, on):
     sg.check(sg.lib().sg_set_profiling(op._h, 1 if on else 0), "sg_set_profiling")
 
 
-def time_solve(op, b, x, steps, warmup, flexible, **kw):
+def time_solve(op, b, x, steps, warmup, flexible, per_step=None, **kw):
+    """Mean time per solve over `steps` solves after `warmup` untimed ones (each solve returns
+    host results, so it ends synchronised); per_step (a list) receives each solve's time."""
     import torch
     fn = op.fgmres if flexible else op.gmres
     for _ in range(warmup):
@@ -67,7 +69,10 @@ def time_solve(op, b, x, steps, warmup, flexible, **kw):
     t0 = time.perf_counter()
     infos = []
     for _ in range(steps):
+        ts = time.perf_counter()
         _, info = fn(b, x, **kw)
+        if per_step is not None:
+            per_step.append(time.perf_counter() - ts)
         infos.append(info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -147,8 +152,12 @@ def batched_config4(count, log):
     tiles = {}
     for op in ops:
         tiles["n%d_q%d" % (op.n, op.Q)] = sg.tune_get(op.n, op.Q, "f32")
-    # warm-up on a small slice (kernel loading), then the whole batch, timed
-    sg.gmres_batched(ops[:8], bs[:8], xs[:8], restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
+    # warm-up with the whole batch (kernel loading and the solver's device arena, which it
+    # keeps for later calls), then the whole batch, timed
+    t0 = time.perf_counter()
+    sg.gmres_batched(ops, bs, xs, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, rc, infos = sg.gmres_batched(ops, bs, xs, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
@@ -166,6 +175,15 @@ def batched_config4(count, log):
         kern[k] = {"ms": v["ms"], "launches": v["launches"],
                    ("TFLOP/s" if k == "fd_gemm" else "GB/s"): rate / (1e12 if k == "fd_gemm" else 1e9)}
     log("batched: %.3f s for %d solves (%.1f solves/s), rc %d" % (t_solve, count, count / t_solve, rc))
+    # the same batch with the FP64 preconditioner (the plain form of this workload)
+    sg.autotune(ops, precision="f64", reps=3)
+    sg.gmres_batched(ops[:8], bs[:8], xs[:8], restart=30, maxit=1000, pc="mean", precision="f64", tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rc64, infos64 = sg.gmres_batched(ops, bs, xs, restart=30, maxit=1000, pc="mean", precision="f64", tol=1e-8)
+    torch.cuda.synchronize()
+    t_solve64 = time.perf_counter() - t0
+    log("batched FP64 preconditioner: %.3f s (%.1f solves/s), rc %d" % (t_solve64, count / t_solve64, rc64))
     # the same instances one at a time through sg_gmres (same algorithm and precision); the
     # first pass includes each handle's first Krylov-workspace allocation, the second is the
     # steady state
@@ -184,6 +202,11 @@ def batched_config4(count, log):
     out = {"workload": "%d seeded instances, N in {63,127,255}, kbar~U[5,30], sigma=0.1 kbar, s in 1..4, "
                        "degree 2..4; A_0-GMRES(30) to 1e-8, FP64 outer, FP32 preconditioner" % count,
            "solves_per_s": count / t_solve, "solves_per_s_with_setup": count / (t_solve + t_setup),
+           "first_call_s": t_first,
+           "plain_f64_precond": {"solves_per_s": count / t_solve64, "solve_s": t_solve64,
+                                 "all_converged": bool(rc64 == 0),
+                                 "iters_mean": float(np.mean([i["iters"] for i in infos64]))},
+           "f32_speedup_vs_f64_precond": t_solve64 / t_solve,
            "solve_s": t_solve, "one_at_a_time_solves_per_s": count / t_seq[1],
            "one_at_a_time_first_pass_solves_per_s": count / t_seq[0], "setup_s": t_setup, "setup_threads": 8, "autotune_s": t_tune,
            "autotune_gpu_ms": tune_ms, "tiles": tiles, "all_converged": bool(rc == 0),
@@ -269,8 +292,11 @@ def learned_config5(n_pairs, n_eval, log):
             res[name].append((t, info["iters"], info["relres_true"]))
         op.close()
     out = {"workload": "255x255, kbar~U[10,30], sigma=0.15 kbar, s=4, degree 3 (Q=35); U-Net widths 32/64/128, "
-                       "BF16 with FP32 accumulation; trained on %d pairs from plain solves (seeds 10000+), "
-                       "evaluated on seeds 0..%d" % (seen, n_eval - 1),
+                       "BF16 with FP32 accumulation; trained on %d pairs from plain solves (seeds 10000+)%s, "
+                       "evaluated on seeds 0..%d" % (
+                           seen, "" if seen >= 20000 else " -- fewer than the 20k pairs of the learned "
+                           "workload, to keep the default bench run short (--learned-pairs 20000 runs it in full)",
+                           n_eval - 1),
            "pairs": seen, "train_steps": len(losses), "pair_generation_s": t_gen, "training_s": t_train,
            "loss_first": float(np.mean(losses[:8])), "loss_last": float(np.mean(losses[-8:])),
            "fallbacks": fallbacks, "net_conv_ms_in_one_solve": net_ms,
@@ -302,6 +328,21 @@ def mixed_config3(log):
     out = {"workload": "2D 511x511 nodes, kbar=40, sigma=4, s=6 sine modes, degree 3 (Q=84), 21,934,164 unknowns; "
                        "mean-value preconditioner, restart 50, true relres 1e-8 from x=0",
            "setup_s": setup_s, "gemm_tiles": {p_: sg.tune_get(op.n, op.Q, p_) for p_ in ("f64", "f32", "bf16x3")}}
+    # the plain solve's dominant kernel class, then its roofline from events around that class
+    # during two further solves (the timed solves below run without events)
+    common = dict(pc="mean", precision="f64", restart=50, maxit=1000, tol=1e-8)
+    op.gmres(b, x, **common)
+    set_profiling(op, True)
+    op.gmres(b, x, **common)
+    prof = kernel_profile(op)
+    dom_kind = [k for k, v in KIND.items() if v == max(prof, key=lambda k_: prof[k_]["ms"])][0]
+    set_profiling(op, True)
+    sg.check(sg.lib().sg_profile_kinds(op._h, 1 << dom_kind), "sg_profile_kinds")
+    for _ in range(2):
+        op.gmres(b, x, **common)
+    out["roofline_plain"] = roofline_of(kernel_profile(op), "f64", out["gemm_tiles"]["f64"])
+    out["kernels_plain"] = prof
+    set_profiling(op, False)
     x_plain = None
     for name, fn, prec in (("plain_f64_gmres", op.gmres, "f64"), ("mixed_f32_fgmres", op.fgmres, "f32"),
                            ("mixed_bf16x3_fgmres", op.fgmres, "bf16x3")):
@@ -353,6 +394,63 @@ def degree_sweep(log, degrees=range(1, 9)):
                         "degree 1..8 (Q up to 165); GMRES(200) to true relres 1e-8 from x=0", "rows": rows}
 
 
+def config1_leg(log):
+    """Config 1: 1D, 201 nodes, k = 20 + 2ξ, degree 5 (Q = 6), Gaussian source; GMRES(30) to the
+    true relative residual 1e-10 (and 1e-8) without preconditioner, with A_0 and with M_0
+    (five timed solves after one warm-up each)."""
+    from paper_2209_14740_amd import sg
+    from workloads import config1
+    inst = config1()
+    op = sg.SG.from_instance(inst)
+    b = op.rhs(inst.f)
+    x = op.empty()
+    out = {"workload": "1D, 201 nodes, k=20+2 xi, degree 5 (Q=6), 1206 unknowns, Gaussian source; GMRES(30) "
+                       "from x=0", "rows": {}}
+    for pc in ("none", "mean", "csl"):
+        rec = {}
+        for tol in (1e-10, 1e-8):
+            t, info = time_solve(op, b, x, 5, 1, False, pc=pc, precision="f64", restart=30, maxit=20000, tol=tol)
+            rec["tol_%g" % tol] = {"s": t, "iters": info["iters"], "relres_true": info["relres_true"]}
+        out["rows"][pc] = rec
+        log("config 1 %s: %.2f ms, %d iterations to 1e-10" % (pc, rec["tol_1e-10"]["s"] * 1e3,
+                                                                 rec["tol_1e-10"]["iters"]))
+    op.close()
+    return out
+
+
+def wedge_leg(log):
+    """The paper's 2D experiment (Section 7): wedge-shaped piecewise-constant mean (k_1, k_2,
+    k_3 = 30, 15, 20), θ = 0.1 and 0.2, 129² nodes, point source, degree 8 (Q = 165,
+    2,745,765 unknowns), A_0 right preconditioner with its mean block factorised line by
+    line, full GMRES to 1e-8 (three timed solves after one warm-up)."""
+    import torch
+    from paper_2209_14740_amd import sg
+    from workloads import wedge_instance
+    out = {"workload": "Section 7 wedge, 129x129 nodes, degree 8 (Q=165), 2,745,765 unknowns, point source; "
+                       "A_0 (line block LU of the varying-mean block) right preconditioner, full GMRES to 1e-8",
+           "paper_iters": {"theta_0.1": 20, "theta_0.2": 60}}
+    for theta in (0.1, 0.2):
+        inst = wedge_instance(8, theta)
+        t0 = time.perf_counter()
+        op = sg.SG(inst.dim, inst.n, inst.s, inst.degree, inst.k_fields, 0.0, inst.beta)
+        t_setup = time.perf_counter() - t0
+        b = op.rhs(inst.f)
+        x = op.empty()
+        t, info = time_solve(op, b, x, 3, 1, False, pc="mean", precision="f64", restart=200, maxit=200, tol=1e-8)
+        set_profiling(op, True)
+        op.gmres(b, x, pc="mean", precision="f64", restart=200, maxit=200, tol=1e-8)
+        prof = kernel_profile(op)
+        set_profiling(op, False)
+        out["theta_%g" % theta] = {"s": t, "iters": info["iters"], "relres_true": info["relres_true"],
+                                   "setup_s": t_setup, "kernels": prof}
+        log("wedge theta=%g: %.1f ms, %d iterations (paper about %d)" % (theta, t * 1e3, info["iters"],
+                                                                          20 if theta == 0.1 else 60))
+        op.close()
+        del x, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def paper_context():
     """The paper's own timed 1D experiment (Section 6: k̄ = 50, θ = 0.1, degree 3, point
     source, A_0 as right preconditioner, full GMRES to 1e-12), for context only."""
@@ -373,6 +471,15 @@ def paper_context():
         _, info = op.gmres(b, x, **kw)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / 5
+    # the same with left preconditioning (Table time_precond_kbar50 has both)
+    kwl = dict(kw, side="left")
+    op.gmres(b, x, **kwl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        _, info_l = op.gmres(b, x, **kwl)
+    torch.cuda.synchronize()
+    t_left = (time.perf_counter() - t0) / 5
     # the full CSL preconditioner M(β) of the same experiment: outer FGMRES on A, each
     # application an inner M_0-preconditioned GMRES on M(β) (a second handle) to 1e-12
     opm = sg.SG.from_instance(inst)
@@ -397,6 +504,8 @@ def paper_context():
                         "source; A_0 right preconditioner, GMRES without restart to 1e-12" % inst.n,
             "gpu_solve_s": t, "gpu_setup_s": t_setup, "iters": info["iters"], "relres_true": info["relres_true"],
             "paper_s": 0.0148, "paper_machine": "MATLAB R2020b on an i7-7500U @ 2.70GHz, LU of one block included",
+            "left": {"gpu_solve_s": t_left, "iters": info_l["iters"], "relres_prec": info_l["relres_prec"],
+                     "relres_true": info_l["relres_true"], "paper_s": 0.0148},
             "full_csl": {"preconditioner": "M(beta=0.5) applied by inner M_0-GMRES on M to 1e-12, outer FGMRES",
                          "gpu_solve_s": t_m, "outer_iters": info_m["iters"], "relres_true": info_m["relres_true"],
                          "inner_iters_mean": sum(inner_its) / max(1, len(inner_its)),
@@ -405,23 +514,26 @@ def paper_context():
 
 def cpu_baseline():
     """The oracle (numpy/scipy FP64) on the same workload: assembly, block LU of the mean
-    block and MGS GMRES(50) to 1e-8, timed on the host; BLAS restricted to one thread
-    (SuperLU and the sparse matvec are single-threaded anyway)."""
+    block and MGS GMRES(50) to 1e-8, timed on the host with BLAS on the process's cores
+    (sched_getaffinity, at most the 16 of one GPU's share of the host); SuperLU and the
+    sparse matvec are single-threaded."""
     from threadpoolctl import threadpool_limits
 
     from oracle import assemble, krylov, precond
     from workloads import config2
     inst = config2()
-    with threadpool_limits(limits=1):
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    with threadpool_limits(limits=cores):
         t0 = time.perf_counter()
         S = assemble.from_instance(inst)
         t1 = time.perf_counter()
         P = precond.mean_value(S)
         x, info = krylov.gmres(lambda v: S.A @ v, S.b, P, restart=50, tol=1e-8, maxit=1000)
         t2 = time.perf_counter()
-    return {"value": t2 - t1, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": "full config-2 solve (LU of the mean block + MGS GMRES(50) to 1e-8, %d iterations); "
-                      "assembly %.1f s excluded" % (info.iters, t1 - t0),
+    return {"value": t2 - t1, "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": "full config-2 solve (LU of the mean block + MGS GMRES(50) to 1e-8, %d iterations, BLAS "
+                      "on %d threads; SuperLU and the sparse matvec single-threaded); assembly %.1f s excluded"
+                      % (info.iters, cores, t1 - t0),
             "relres_true": info.relres_true}
 
 
@@ -447,6 +559,12 @@ def main():
     ap.add_argument("--matvec-only", action="store_true",
                     help="run only the SG-operator bandwidth leg; prints its JSON object")
     ap.add_argument("--no-degree-sweep", action="store_true")
+    ap.add_argument("--no-paper-context", action="store_true")
+    ap.add_argument("--no-config1", action="store_true")
+    ap.add_argument("--no-wedge", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the config-2 plain solve and its forms (for profiling the headline kernel)")
+    ap.add_argument("--wedge-only", action="store_true", help="run only the wedge leg; prints its JSON object")
     ap.add_argument("--degree-sweep-only", action="store_true",
                     help="run only the degree sweep (s=3, 129x129, degree 1..8); prints its JSON object")
     ap.add_argument("--f64-tile", default=None,
@@ -493,6 +611,13 @@ def main():
     if args.learned_only:
         print(json.dumps({"learned": learned_config5(args.learned_pairs, args.learned_eval, log)}))
         return
+    if args.wedge_only:
+        print(json.dumps({"wedge": wedge_leg(log)}))
+        return
+    if args.headline_only:
+        for k in ("no_matvec", "no_mixed3", "no_degree_sweep", "no_paper_context", "no_config1", "no_wedge",
+                  "no_batched", "no_learned", "no_cpu_baseline"):
+            setattr(args, k, True)
     inst = config2()
     t0 = time.perf_counter()
     op = sg.SG.from_instance(inst)
@@ -525,9 +650,12 @@ def main():
     set_profiling(op, True)
     sg.check(sg.lib().sg_profile_kinds(op._h, 1 << dom_kind), "sg_profile_kinds")
     torch.cuda.synchronize()
+    step_s = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, info = op.gmres(b, x, pc="mean", precision="f64", **common)
+        ts = time.perf_counter()
+        _, info = op.gmres(b, x, pc="mean", precision="f64", **common)   # returns synchronised
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / args.steps
     prof_dom = kernel_profile(op)
@@ -538,7 +666,8 @@ def main():
         sys.exit(1)
 
     log("plain f64: %.2f ms, %d iterations" % (t_plain * 1e3, info["iters"]))
-    forms = {"plain_f64_gmres": {"s": t_plain, "iters": info["iters"], "relres_true": info["relres_true"]}}
+    forms = {"plain_f64_gmres": {"s": t_plain, "median_s": float(np.median(step_s)), "iters": info["iters"],
+                                 "relres_true": info["relres_true"]}}
     steps_f = max(2, min(args.steps, 3))
     for name, flex, pc, prec in (("csl_f64_gmres", False, "csl", "f64"),
                                  ("mixed_f32_fgmres", True, "mean", "f32"),
@@ -549,6 +678,13 @@ def main():
         forms[name] = {"s": t, "iters": inf["iters"], "relres_true": inf["relres_true"],
                        "max_rel_diff_vs_plain": err, "speedup_vs_plain": t_plain / t}
 
+    # the same plain solve with both Gram-Schmidt passes in the same step (the previous driver)
+    op.set_orthogonalisation("cgs2")
+    t, inf = time_solve(op, b, x, steps_f, 1, False, pc="mean", precision="f64", **common)
+    op.set_orthogonalisation("dcgs2")
+    forms["plain_f64_gmres_cgs2"] = {"s": t, "iters": inf["iters"], "relres_true": inf["relres_true"],
+                                     "delayed_cgs2_speedup": t / t_plain}
+    log("plain f64 with two-pass CGS2: %.2f ms, %d iterations" % (t * 1e3, inf["iters"]))
     roof = roofline_of(prof_dom, "f64", tiles["f64"])
     out = {
         "metric": METRIC,
@@ -558,6 +694,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": t_plain * 1e3,
+        "median_ms_per_step": float(np.median(step_s)) * 1e3,
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
@@ -584,8 +721,15 @@ def main():
     if not args.no_degree_sweep:
         log("degree sweep (s=3, 129x129, degree 1..8)")
         out["degree_sweep"] = degree_sweep(log)
-    log("paper context (Section 6, 1D)")
-    out["paper_context"] = paper_context()
+    if not args.no_config1:
+        log("config 1 (1D, Q=6)")
+        out["config1"] = config1_leg(log)
+    if not args.no_wedge:
+        log("wedge (Section 7, degree 8)")
+        out["wedge"] = wedge_leg(log)
+    if not args.no_paper_context:
+        log("paper context (Section 6, 1D)")
+        out["paper_context"] = paper_context()
     if not args.no_batched:
         log("batched config 4")
         out["batched"] = batched_config4(args.batched_count, log)

@@ -139,6 +139,23 @@ int  sg_rhs(sg_handle h, const double* f_host, sg_c64* b_dev, hipStream_t stream
 /* y = A x (Theorem 3.3), FP64, matrix-free; x and y must not overlap. */
 int  sg_apply(sg_handle h, const sg_c64* x, sg_c64* y, hipStream_t stream);
 
+/* How the handle solves its mean block (the block solves of A_0 and M_0): SG_MEAN_FD, fast
+ * diagonalisation (constant k̄; 1D: the tridiagonal solve); SG_MEAN_LINE, the exact block LU
+ * over grid lines (k_mean = 0: spatially varying k_0); SG_MEAN_LINE_FALLBACK, the same block
+ * LU chosen at setup because the eigenfactors of a constant-k̄ 2D block failed their checks
+ * (residual, D-orthonormality, or cond₂ of the eigenvector matrix Ṽ above 1e4, whose
+ * square amplifies the rounding of the transforms); possible for n <= 257, beyond that
+ * sg_setup returns SG_ESETUP.  cond_v (may be NULL) receives the figure checked: the bound
+ * ||Ṽ||_F ||ṼᵀD||_F, or power-iteration estimates of the two 2-norms when that bound is
+ * above 1e3 (2D constant k̄ only, else 0).  The line forms are FP64 only and not served by the batched solver or the
+ * learned correction. */
+enum { SG_MEAN_FD = 0, SG_MEAN_LINE = 1, SG_MEAN_LINE_FALLBACK = 2 };
+int  sg_mean_solver(sg_handle h, int* kind, double* cond_v);
+/* Process-wide limit on that cond₂ figure for later sg_setup calls (default 1e4, >= 1,
+ * else SG_EINVAL); a limit of 1 sends every 2D constant-k̄ problem with n <= 257 to the line
+ * factorisation. */
+int  sg_set_eigen_cond_limit(double limit);
+
 /* Statistics of the SG solution u_m(x,ξ) = Σ_i V_i(x) φ_i(ξ) held in x (Section 7, Figure
  * bE_Var): mean = E[u_m] = V_0 (device, n^dim complex, may be NULL) and var = [Var[Re u_m];
  * Var[Im u_m]] = [Σ_{i>=1} (Re V_i)²; Σ_{i>=1} (Im V_i)²] (device, 2·n^dim doubles, may be
@@ -174,6 +191,21 @@ int  sg_precond(sg_handle h, int pc, int precision, const sg_c64* r, sg_c64* z, 
 int  sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
               sg_solve_stats* stats, hipStream_t stream);
 
+/* Orthogonalisation of sg_gmres / sg_fgmres with a built-in preconditioner and restart <= 64:
+ * SG_ORTH_DCGS2 (the default), classical Gram-Schmidt with one re-orthogonalisation delayed
+ * by one step, so that one pass over the basis re-orthogonalises the previous vector and
+ * projects the new one (two passes over the basis per step, one coefficient exchange with
+ * the host; the Arnoldi process in the flexible form z_j = P^{-1}u_j, x += Z y);
+ * SG_ORTH_CGS2, the same two Gram-Schmidt passes done in the same step (three passes over
+ * the basis).  Other solves (callbacks, the learned correction, left preconditioning,
+ * restart > 64) always use SG_ORTH_CGS2. */
+enum { SG_ORTH_DCGS2 = 0, SG_ORTH_CGS2 = 1 };
+int  sg_set_orthogonalisation(sg_handle h, int kind);
+/* The orthonormal Arnoldi basis v_0..v_{nvec-1} of the last cycle of the handle's last
+ * delayed-CGS2 solve (device, vector-major, owned by the handle, valid until its next solve);
+ * for checks of orthogonality. */
+int  sg_last_basis(sg_handle h, int* nvec, const sg_c64** V);
+
 /* Flexible GMRES(m): the preconditioner may change between iterations.  cb == NULL
  * uses the built-in opts->precond / opts->precision; otherwise cb(user, r, z, stream)
  * must write z ≈ P^{-1} r (device vectors of sg_size()) and return 0. */
@@ -202,7 +234,9 @@ int  sg_stationary(sg_handle h, const sg_c64* b, sg_c64* x, int pc, int iters, d
  * grouped kernel launch over all active instances, with one host synchronisation per
  * step.  Instances are admitted from a queue ordered by estimated cost (largest first)
  * into Krylov workspaces carved from one device arena of at most max(largest instance,
- * half the free device memory), allocated for the call and freed before it returns.
+ * half the available device memory); the arena is kept for later calls on the same device
+ * (allocating it costs more than a batch of solves) until sg_batched_release() or the end of
+ * the process, and calls on one device are serialised.
  * handles, b and x: host arrays of `count` entries; b[i], x[i] device vectors of
  * sg_size(handles[i]) complex, x[i] is overwritten (the initial guess is zero, opts
  * x0_zero is ignored).  A handle may appear only once.  opts->restart must be in
@@ -216,6 +250,8 @@ int  sg_stationary(sg_handle h, const sg_c64* b, sg_c64* x, int pc, int iters, d
  * failure.  Kernel timing, when enabled, is recorded in the profiler of handles[0]. */
 int  sg_gmres_batched(int count, const sg_handle* handles, const sg_c64* const* b, sg_c64* const* x,
                       const sg_solve_opts* opts, sg_solve_stats* stats, hipStream_t stream);
+/* Free the batched solver's arena on the current device (after synchronising the device). */
+int  sg_batched_release(void);
 
 /* GEMM tile-shape autotuner of the preconditioner transforms: for every distinct
  * (n, Q) among the 2D handles, times each tile shape (SG_GEMM_TILE_*) available in

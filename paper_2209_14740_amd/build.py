@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libsg.so")
 SOURCES = ["apply_spec_g0.hip", "apply_spec_g1.hip", "apply_spec_g2.hip", "apply_spec_g3.hip", "apply_spec_g4.hip",
            "setup.cpp",
            "prof.cpp", "abi.cpp", "gmres.cpp", "batched.cpp", "net_host.cpp", "net.hip", "apply.hip", "precond.hip", "krylov.hip",
-           "noalloc.hip", "line.hip", "stats.hip"]
+           "noalloc.hip", "line.hip", "stats.hip", "dcgs2.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -119,6 +119,43 @@ int sg_degree_magnitudes(sg_handle h, const sg_c64* x, double* gamma_host, hipSt
     })
 }
 
+int sg_set_orthogonalisation(sg_handle h, int kind) {
+    SG_TRY({
+        if (!h) return fail(SG_EINVAL, "null handle");
+        if (kind != SG_ORTH_DCGS2 && kind != SG_ORTH_CGS2) return fail(SG_EINVAL, "unknown orthogonalisation");
+        ctx(h)->classic_cgs2 = kind == SG_ORTH_CGS2;
+        return SG_OK;
+    })
+}
+
+int sg_last_basis(sg_handle h, int* nvec, const sg_c64** V) {
+    SG_TRY({
+        if (!h || !nvec || !V) return fail(SG_EINVAL, "null argument");
+        Ctx* c = ctx(h);
+        *nvec = c->last_k;
+        *V = reinterpret_cast<const sg_c64*>(c->ws.V);
+        return SG_OK;
+    })
+}
+
+int sg_set_eigen_cond_limit(double limit) {
+    SG_TRY({
+        if (!(limit >= 1.0)) return fail(SG_EINVAL, "sg_set_eigen_cond_limit: limit must be >= 1");
+        sgi::set_eigen_cond_limit(limit);
+        return SG_OK;
+    })
+}
+
+int sg_mean_solver(sg_handle h, int* kind, double* cond_v) {
+    SG_TRY({
+        if (!h) return fail(SG_EINVAL, "null handle");
+        Ctx* c = ctx(h);
+        if (kind) *kind = !c->vmean ? SG_MEAN_FD : (c->eig_fallback ? SG_MEAN_LINE_FALLBACK : SG_MEAN_LINE);
+        if (cond_v) *cond_v = c->cond_v;
+        return SG_OK;
+    })
+}
+
 int sg_set_operator_shift(sg_handle h, double beta) {
     SG_TRY({
         if (!h) return fail(SG_EINVAL, "null handle");
@@ -154,6 +191,9 @@ int sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
         Ctx* c = ctx(h);
         if (int rc = guard_device(c)) return rc;
         ProfBind pb(c);
+        if (sgi::dcgs2_serves(c, opts, nullptr) && !c->classic_cgs2)
+            return sgi::run_gmres_dcgs2(c, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), opts,
+                                        stats, stream);
         return sgi::run_gmres(c, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), opts, nullptr,
                               nullptr, false, stats, stream);
     })
@@ -179,6 +219,8 @@ int sg_fgmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts
         ProfBind pb(c);
         const double2* bb = reinterpret_cast<const double2*>(b);
         double2* xx = reinterpret_cast<double2*>(x);
+        if (sgi::dcgs2_serves(c, opts, cb) && !c->classic_cgs2)
+            return sgi::run_gmres_dcgs2(c, bb, xx, opts, stats, stream);
         if (cb || !opts || opts->precond != SG_PC_MEAN_NET)
             return sgi::run_gmres(c, bb, xx, opts, cb, user, true, stats, stream);
         if (!c->net) return fail(SG_EINVAL, "sg_fgmres: no network attached");
@@ -301,6 +343,10 @@ int sg_gmres_batched(int count, const sg_handle* handles, const sg_c64* const* b
         ProfBind pb(cs[0]);
         return sgi::run_gmres_batched(count, cs.data(), bs.data(), xs.data(), opts, stats, stream);
     })
+}
+
+int sg_batched_release(void) {
+    SG_TRY({ return sgi::batched_release(); })
 }
 
 int sg_autotune(int count, const sg_handle* handles, int precision, int reps, double* ms_total, hipStream_t stream) {
@@ -441,7 +487,7 @@ int sg_attach_net(sg_handle h, sg_net net) {
         if (net) {
             sgi::Net* n = netp(net);
             if (n->device != c->device) return fail(SG_EINVAL, "network and handle are on different devices");
-            if (c->vmean) return fail(SG_EINVAL, "the learned correction needs a constant mean wavenumber");
+            if (c->vmean) return fail(SG_EINVAL, "the learned correction needs a constant mean wavenumber solved by fast diagonalisation");
             if (c->dim != 2 || n->Q != c->Q || n->s != c->s)
                 return fail(SG_EINVAL, "network shape does not match the problem (2D, same Q and s)");
         }

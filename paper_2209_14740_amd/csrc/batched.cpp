@@ -118,6 +118,14 @@ struct Staging {
     }
 };
 
+constexpr int kMaxDev = 64;
+struct ArenaCache {
+    std::mutex mu;
+    unsigned char* p = nullptr;
+    size_t bytes = 0;
+};
+ArenaCache g_arena[kMaxDev];
+
 // First-fit allocator over one device arena (offsets; freed ranges are merged).
 struct Arena {
     unsigned char* base = nullptr;
@@ -203,7 +211,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
     if (o->side != 0) return fail(SG_EINVAL, "batched solve: right preconditioning only");
     for (int i = 0; i < count; ++i)
         if (ctx[i] && ctx[i]->vmean)
-            return fail(SG_EINVAL, "batched solve: handles with a spatially varying mean are not supported");
+            return fail(SG_EINVAL, "batched solve: handles whose mean block is solved by the line factorisation (spatially varying mean, or the eigenfactor fallback) are not supported");
     const int m = o->restart;
     const int pc = o->precond, prec = o->precision;
 
@@ -221,17 +229,28 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         largest = std::max(largest, need[i]);
         total += need[i];
     }
+    // The arena is kept per device between calls (a fresh allocation of this size costs far
+    // more than the solves: the driver clears the memory it hands out); calls on one device
+    // are serialised by its lock.
+    int dev = 0;
+    SG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(SG_EINVAL, "batched solve: device index out of range");
+    ArenaCache& ac = g_arena[dev];
+    std::lock_guard<std::mutex> arena_lock(ac.mu);
     size_t freeb = 0, totb = 0;
     SG_HIP(hipMemGetInfo(&freeb, &totb));
-    size_t arena_bytes = std::min(total, std::max(largest, freeb / 2));
-    if (arena_bytes > freeb) return fail(SG_ENOMEM, "batched solve: not enough device memory for one instance");
-    unsigned char* arena_mem = nullptr;
-    if (hipMalloc(&arena_mem, arena_bytes) != hipSuccess)
-        return fail(SG_ENOMEM, "batched solve: arena allocation failed");
-    struct Free {
-        unsigned char* p;
-        ~Free() { (void)hipFree(p); }
-    } free_arena{arena_mem};
+    const size_t avail = freeb + ac.bytes;   // the cached arena counts as available
+    size_t arena_bytes = std::min(total, std::max(largest, avail / 2));
+    if (arena_bytes > avail) return fail(SG_ENOMEM, "batched solve: not enough device memory for one instance");
+    if (ac.bytes < arena_bytes) {
+        SG_HIP(hipStreamSynchronize(stream));   // the previous call's work on the arena has ended
+        (void)hipFree(ac.p);
+        ac.p = nullptr;
+        ac.bytes = 0;
+        if (hipMalloc(&ac.p, arena_bytes) != hipSuccess) return fail(SG_ENOMEM, "batched solve: arena allocation failed");
+        ac.bytes = arena_bytes;
+    }
+    unsigned char* arena_mem = ac.p;
     Arena arena;
     arena.init(arena_mem, arena_bytes);
 
@@ -713,6 +732,21 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
 // Autotuner: for every distinct (n, Q) of the 2D handles, time each GEMM tile shape on a
 // grouped launch over up to `group` instances of that shape (the batched setting), and
 // keep the fastest per instance in the process-wide table.
+int batched_release() {
+    int dev = 0;
+    SG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(SG_EINVAL, "device index out of range");
+    ArenaCache& ac = g_arena[dev];
+    std::lock_guard<std::mutex> lk(ac.mu);
+    if (ac.p) {
+        SG_HIP(hipDeviceSynchronize());
+        (void)hipFree(ac.p);
+    }
+    ac.p = nullptr;
+    ac.bytes = 0;
+    return SG_OK;
+}
+
 int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out, hipStream_t stream) {
     if (count < 0 || (count > 0 && !ctx)) return fail(SG_EINVAL, "bad handle list");
     if (precision < SG_PREC_F64 || precision > SG_PREC_BF16X3) return fail(SG_EINVAL, "unknown precision");

@@ -34,6 +34,9 @@ int ensure_workspace(Ctx* c, int m, bool flexible) {
     (void)hipFree(w.partial);
     if (w.host_pinned) (void)hipHostFree(w.host_pinned);
     if (w.done) (void)hipEventDestroy(w.done);
+    (void)hipFree(w.dpart);
+    (void)hipFree(w.dsmall);
+    if (w.hrec) (void)hipHostFree(w.hrec);
     w = Workspace{};
     const size_t nv = (size_t)c->nvec;
     w.m = m;

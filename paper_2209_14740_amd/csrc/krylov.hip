@@ -365,7 +365,271 @@ __global__ __launch_bounds__(RB) void k_axpby_g(const VecTask* __restrict__ task
     }
 }
 
+// ---- delayed CGS2 (one reduction and one update pass per Arnoldi step) ------------------
+//
+// Step j holds the orthonormal v_0..v_{j-1} (slots 0..j-1), the candidate u_j of slot j (w_{j-1}
+// after one Gram-Schmidt pass, not yet re-orthogonalised nor normalised) and w_j = A z_j,
+// z_j = P^{-1} u_j (slot j+1).  One pass over the slots forms
+//     a = V^H u_j,  b = V^H w_j,  α = ||u_j||²,  β = u_j^H w_j,  ω = ||w_j||²;
+// the re-orthogonalisation of u_j is then ν v_j = u_j - V a with ν² = α - ||a||², the
+// projection of w_j on the final basis is (b, (β - a^H b)/ν), and one more pass writes v_j and
+// the next candidate u_{j+1} = w_j - V b - h v_j (dcgs_update).  Reading the basis twice per
+// step instead of three times, with one coefficient exchange with the host.
+
+// partial[b][k]: k < nv: a_k;  nv <= k < 2nv: b_{k-nv};  2nv: α;  2nv+1: β;  2nv+2: ω
+// (w == nullptr: only a and α, laid out as k < nv: a_k, nv: α)
+template <int NVW>
+__global__ __launch_bounds__(RB) void k_dcgs_reduce(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                                    const double2* __restrict__ u, const double2* __restrict__ w,
+                                                    double2* __restrict__ partial) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool hasw = w != nullptr;
+    const int nout = hasw ? 2 * nv + 3 : nv + 1;
+    int nk = 0;
+#pragma unroll
+    for (int m = 0; m < NVW; ++m)
+        if (wv + 4 * m < nv) nk = m + 1;
+    double2 ca[NVW], cb[NVW];
+#pragma unroll
+    for (int m = 0; m < NVW; ++m) ca[m] = cb[m] = make_double2(0.0, 0.0);
+    double2 sc = make_double2(0.0, 0.0);   // wave 0: α; wave 1: β; wave 2: ω
+    for (long long c0 = (long long)blockIdx.x * 64; c0 < n; c0 += (long long)gridDim.x * 64) {
+        const long long i = c0 + lane;
+        const bool ok = i < n;
+        const double2 ui = ok ? u[i] : make_double2(0.0, 0.0);
+        const double2 wi = (ok && hasw) ? w[i] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int m = 0; m < NVW; ++m) {
+            if (m < nk) {
+                const double2 v = ok ? V[(long long)(wv + 4 * m) * ldv + i] : make_double2(0.0, 0.0);
+                ca[m].x = fma(v.x, ui.x, fma(v.y, ui.y, ca[m].x));     // conj(v) u
+                ca[m].y = fma(v.x, ui.y, fma(-v.y, ui.x, ca[m].y));
+                if (hasw) {
+                    cb[m].x = fma(v.x, wi.x, fma(v.y, wi.y, cb[m].x));
+                    cb[m].y = fma(v.x, wi.y, fma(-v.y, wi.x, cb[m].y));
+                }
+            }
+        }
+        if (wv == 0) sc.x = fma(ui.x, ui.x, fma(ui.y, ui.y, sc.x));
+        else if (wv == 1 && hasw) {
+            sc.x = fma(ui.x, wi.x, fma(ui.y, wi.y, sc.x));              // conj(u) w
+            sc.y = fma(ui.x, wi.y, fma(-ui.y, wi.x, sc.y));
+        } else if (wv == 2 && hasw) sc.x = fma(wi.x, wi.x, fma(wi.y, wi.y, sc.x));
+    }
+    double2* out = partial + (long long)blockIdx.x * nout;
+#pragma unroll
+    for (int m = 0; m < NVW; ++m) {
+        const double ax = wave_sum(ca[m].x), ay = wave_sum(ca[m].y);
+        double bx = 0.0, by = 0.0;
+        if (hasw) {
+            bx = wave_sum(cb[m].x);
+            by = wave_sum(cb[m].y);
+        }
+        if (lane == 0 && m < nk) {
+            out[wv + 4 * m] = make_double2(ax, ay);
+            if (hasw) out[nv + wv + 4 * m] = make_double2(bx, by);
+        }
+    }
+    const double sx = wave_sum(sc.x), sy = wave_sum(sc.y);
+    if (lane == 0) {
+        if (!hasw) {
+            if (wv == 0) out[nv] = make_double2(sx, 0.0);
+        } else if (wv < 3) {
+            out[2 * nv + wv] = make_double2(sx, wv == 1 ? sy : 0.0);
+        }
+    }
+}
+
+// One block: the coefficients of step j from the reduced sums red[] (layout of k_dcgs_reduce)
+// and the previous first-pass projection h1prev[0..j) of w_{j-1}.  Writes
+//   rec[0..j]       the completed Hessenberg column j-1 (h1prev + a, then ν)     (j >= 1)
+//   rec[j+1..2j+1]  the first-pass projection h1 of w_j on v_0..v_j             (full step)
+//   rec[2j+2]       (ν, ||u_{j+1}||² predicted as ω - ||h1||²)
+// and, for the update pass, cv[k] (v_j = cu_v u_j + Σ cv_k v_k), cw[k] (u_{j+1} = w_j + cu_u u_j +
+// Σ cw_k v_k), cu = (cu_v, cu_u), and h1prev <- h1.  A non-positive ν² gives ν = 0 (breakdown:
+// the host stops the cycle; the update then writes non-finite values into unused slots).
+__global__ __launch_bounds__(RB) void k_dcgs_finalize(int j, int full, const double2* __restrict__ red,
+                                                      double2* __restrict__ h1prev, double2* __restrict__ rec,
+                                                      double2* __restrict__ cv, double2* __restrict__ cw,
+                                                      double2* __restrict__ cu) {
+    __shared__ double s_nu, s_hx, s_hy;
+    __shared__ double red_a[RB / 64], red_bx[RB / 64], red_by[RB / 64];
+    const int t = threadIdx.x;
+    // ||a||² and a^H b over the threads
+    double aa = 0.0, abx = 0.0, aby = 0.0;
+    for (int k = t; k < j; k += RB) {
+        const double2 a = red[k];
+        aa = fma(a.x, a.x, fma(a.y, a.y, aa));
+        if (full) {
+            const double2 b = red[j + k];
+            abx = fma(a.x, b.x, fma(a.y, b.y, abx));   // conj(a) b
+            aby = fma(a.x, b.y, fma(-a.y, b.x, aby));
+        }
+    }
+    aa = wave_sum(aa);
+    abx = wave_sum(abx);
+    aby = wave_sum(aby);
+    if ((t & 63) == 0) {
+        red_a[t >> 6] = aa;
+        red_bx[t >> 6] = abx;
+        red_by[t >> 6] = aby;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double A = 0.0, X = 0.0, Y = 0.0;
+        for (int q = 0; q < RB / 64; ++q) {
+            A += red_a[q];
+            X += red_bx[q];
+            Y += red_by[q];
+        }
+        const double alpha = full ? red[2 * j].x : red[j].x;
+        const double nu2 = alpha - A;
+        const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+        s_nu = nu;
+        if (full) {
+            const double2 beta = red[2 * j + 1];
+            s_hx = (beta.x - X) / nu;
+            s_hy = (beta.y - Y) / nu;
+        }
+    }
+    __syncthreads();
+    const double nu = s_nu, inu = 1.0 / nu;
+    const double hx = full ? s_hx : 0.0, hy = full ? s_hy : 0.0;   // h1_j = v_j^H w_j
+    for (int k = t; k < j; k += RB) {
+        const double2 a = red[k];
+        rec[k] = make_double2(h1prev[k].x + a.x, h1prev[k].y + a.y);   // completed column j-1
+        cv[k] = make_double2(-a.x * inu, -a.y * inu);
+        if (full) {
+            const double2 b = red[j + k];
+            // cw_k = -(b_k - h1_j a_k / ν)
+            cw[k] = make_double2(-(b.x - (hx * a.x - hy * a.y) * inu), -(b.y - (hx * a.y + hy * a.x) * inu));
+        }
+    }
+    __syncthreads();   // every h1prev read above precedes the overwrite below
+    if (full) {
+        for (int k = t; k < j; k += RB) {
+            const double2 b = red[j + k];
+            rec[j + 1 + k] = b;
+            h1prev[k] = b;
+        }
+    }
+    if (t == 0) {
+        rec[j] = make_double2(nu, 0.0);
+        double pred = 0.0;
+        if (full) {
+            rec[2 * j + 1] = make_double2(hx, hy);
+            h1prev[j] = make_double2(hx, hy);
+            double hh = hx * hx + hy * hy;
+            for (int k = 0; k < j; ++k) hh += red[j + k].x * red[j + k].x + red[j + k].y * red[j + k].y;
+            pred = red[2 * j + 2].x - hh;
+        }
+        rec[2 * j + 2] = make_double2(nu, pred);
+        cu[0] = make_double2(inu, 0.0);
+        cu[1] = make_double2(-hx * inu, -hy * inu);
+    }
+}
+
+// v_j (into u's slot) and u_{j+1} (into w's slot): the wave-split basis of cgs_block, the
+// per-wave partial sums of both combinations meeting in LDS; u and w are read before the
+// barrier, wave 0 stores v_j and wave 1 stores u_{j+1} after it.
+template <int NVW>
+__global__ __launch_bounds__(RB) void k_dcgs_update(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                                    double2* __restrict__ u, double2* __restrict__ w,
+                                                    const double2* __restrict__ cv, const double2* __restrict__ cw,
+                                                    const double2* __restrict__ cu) {
+    __shared__ double2 part[2][RB / 64][2][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int nk = 0;
+    double2 c1[NVW], c2[NVW];
+#pragma unroll
+    for (int m = 0; m < NVW; ++m) {
+        const int k = wv + 4 * m;
+        if (k < nv) {
+            nk = m + 1;
+            c1[m] = cv[k];
+            c2[m] = cw[k];
+        }
+    }
+    const double2 cuv = cu[0], cuu = cu[1];
+    int buf = 0;
+    for (long long c0 = (long long)blockIdx.x * 64; c0 < n; c0 += (long long)gridDim.x * 64, buf ^= 1) {
+        const long long i = c0 + lane;
+        const bool ok = i < n;
+        const double2 ui = ok ? u[i] : make_double2(0.0, 0.0);
+        const double2 wi = ok ? w[i] : make_double2(0.0, 0.0);
+        double2 p1 = make_double2(0.0, 0.0), p2 = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int m = 0; m < NVW; ++m)
+            if (m < nk) {
+                const double2 v = ok ? V[(long long)(wv + 4 * m) * ldv + i] : make_double2(0.0, 0.0);
+                p1.x = fma(v.x, c1[m].x, fma(-v.y, c1[m].y, p1.x));
+                p1.y = fma(v.x, c1[m].y, fma(v.y, c1[m].x, p1.y));
+                p2.x = fma(v.x, c2[m].x, fma(-v.y, c2[m].y, p2.x));
+                p2.y = fma(v.x, c2[m].y, fma(v.y, c2[m].x, p2.y));
+            }
+        part[buf][wv][0][lane] = p1;
+        part[buf][wv][1][lane] = p2;
+        __syncthreads();
+        if (ok && wv < 2) {
+            double2 acc = wv == 0 ? make_double2(ui.x * cuv.x - ui.y * cuv.y, ui.x * cuv.y + ui.y * cuv.x)
+                                  : make_double2(wi.x + ui.x * cuu.x - ui.y * cuu.y, wi.y + ui.x * cuu.y + ui.y * cuu.x);
+#pragma unroll
+            for (int q = 0; q < RB / 64; ++q) {
+                acc.x += part[buf][q][wv][lane].x;
+                acc.y += part[buf][q][wv][lane].y;
+            }
+            if (wv == 0) u[i] = acc;
+            else w[i] = acc;
+        }
+    }
+}
+
 }  // namespace
+
+int launch_dcgs_reduce(long long n, int nv, const double2* V, long long ldv, const double2* u, const double2* w,
+                       double2* partial, int nblocks, double2* red, hipStream_t st) {
+    const int nout = w ? 2 * nv + 3 : nv + 1;
+    const int nvw = (nv + 3) / 4;
+    {
+        KScope ks(SG_K_DOT, 16.0 * (nv + (w ? 2 : 1)) * (double)n, st);
+#define SG_DR(NVW_)                                                                                            \
+    if (nvw <= NVW_) {                                                                                         \
+        hipLaunchKernelGGL((k_dcgs_reduce<NVW_>), dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, u, w, partial); \
+    } else
+        SG_DR(1) SG_DR(2) SG_DR(4) SG_DR(8) SG_DR(16) { return fail(SG_EINVAL, "delayed CGS2: more than 64 basis vectors"); }
+#undef SG_DR
+        SG_HIP(hipGetLastError());
+    }
+    KScope ks(SG_K_NORM, 16.0 * nblocks * (double)nout, st);
+    hipLaunchKernelGGL(k_reduce, dim3(nout), dim3(RB), 0, st, nblocks, nout, partial, (const double*)nullptr, red, 0,
+                       (double*)nullptr);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_dcgs_finalize(int j, bool full, const double2* red, double2* h1prev, double2* rec, double2* cv, double2* cw,
+                         double2* cu, hipStream_t st) {
+    KScope ks(SG_K_NORM, 0.0, st);
+    hipLaunchKernelGGL(k_dcgs_finalize, dim3(1), dim3(RB), 0, st, j, full ? 1 : 0, red, h1prev, rec, cv, cw, cu);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_dcgs_update(long long n, int nv, const double2* V, long long ldv, double2* u, double2* w, const double2* cv,
+                       const double2* cw, const double2* cu, int nblocks, hipStream_t st) {
+    KScope ks(SG_K_AXPY, 16.0 * (nv + 4) * (double)n, st);
+    const int nvw = (nv + 3) / 4;
+#define SG_DU(NVW_)                                                                                                  \
+    if (nvw <= NVW_) {                                                                                               \
+        hipLaunchKernelGGL((k_dcgs_update<NVW_>), dim3(nblocks), dim3(RB), 0, st, n, nv, V, ldv, u, w, cv, cw, cu); \
+    } else
+    SG_DU(1) SG_DU(2) SG_DU(4) SG_DU(8) SG_DU(16) { return fail(SG_EINVAL, "delayed CGS2: more than 64 basis vectors"); }
+#undef SG_DU
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
 
 // First-stage blocks of the reductions: about four 64-element chunks per block (short
 // dependent chains for small vectors), at most MAXBLK.

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -218,7 +219,8 @@ static void tri_solve(int n, const std::vector<cplx>& dl, const std::vector<cplx
 }
 
 // Eigenpairs of (T - iτE_1) v = μ D v on n nodes (1D absorbing T of Theorem A.2).
-static int mean_eigen(int n, double h, double kbar, std::vector<cplx>& mu, std::vector<cplx>& V) {
+static int mean_eigen(int n, double h, double kbar, std::vector<cplx>& mu, std::vector<cplx>& V,
+                      double* cond_out = nullptr) {
     const double ih2 = 1.0 / (h * h), tau = kbar / h;
     std::vector<double> dw(n, 1.0);
     dw[0] = dw[n - 1] = 0.5;
@@ -291,6 +293,49 @@ static int mean_eigen(int n, double h, double kbar, std::vector<cplx>& mu, std::
             for (int i = 0; i < n; ++i) acc += V[(size_t)i * n + a] * dw[i] * V[(size_t)i * n + b];
             orth = std::max(orth, std::abs(acc - (a == b ? 1.0 : 0.0)));
         }
+    // condition of the eigenvector matrix: Ṽ^{-1} = Ṽᵀ D, so cond₂(Ṽ) = ||Ṽ||₂ ||Ṽᵀ D||₂ (the
+    // block solve's rounding grows like cond₂(Ṽ)²).  The Frobenius norms bound it cheaply;
+    // only when that bound exceeds 1e3 are the two 2-norms estimated by power iteration.
+    if (cond_out) {
+        double fa = 0, fb = 0;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                fa += std::norm(V[(size_t)i * n + k]);
+                fb += std::norm(V[(size_t)i * n + k] * dw[i]);
+            }
+        double cond = std::sqrt(fa * fb);
+        if (cond > 1e3) {
+            auto norm2 = [&](bool inverse) {   // M = Ṽ or Ṽᵀ D: sqrt of the top eigenvalue of MᴴM
+                std::vector<cplx> u(n), t(n);
+                for (int i = 0; i < n; ++i) u[i] = cplx(1.0 + 0.1 * std::sin(0.7 * i), 0.05 * std::cos(1.3 * i));
+                double lam = 0;
+                for (int it = 0; it < 30; ++it) {
+                    double nr = 0;
+                    for (auto& z : u) nr += std::norm(z);
+                    nr = std::sqrt(nr);
+                    for (auto& z : u) z /= nr;
+                    for (int i = 0; i < n; ++i) {
+                        cplx acc = 0;
+                        for (int k = 0; k < n; ++k)
+                            acc += (inverse ? V[(size_t)k * n + i] * dw[k] : V[(size_t)i * n + k]) * u[k];
+                        t[i] = acc;
+                    }
+                    for (int k = 0; k < n; ++k) {
+                        cplx acc = 0;
+                        for (int i = 0; i < n; ++i)
+                            acc += std::conj(inverse ? V[(size_t)k * n + i] * dw[k] : V[(size_t)i * n + k]) * t[i];
+                        u[k] = acc;
+                    }
+                    double un = 0;
+                    for (auto& z : u) un += std::norm(z);
+                    lam = std::sqrt(un);
+                }
+                return std::sqrt(lam);
+            };
+            cond = norm2(false) * norm2(true);
+        }
+        *cond_out = cond;
+    }
     if (!(res < 1e-10) || !(orth < 1e-8))
     {
         char msg[160];
@@ -449,6 +494,9 @@ Ctx::~Ctx() {
     (void)hipFree(ws.partial);
     if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
     if (ws.done) (void)hipEventDestroy(ws.done);
+    (void)hipFree(ws.dpart);
+    (void)hipFree(ws.dsmall);
+    if (ws.hrec) (void)hipHostFree(ws.hrec);
     (void)hipFree(d_tmp_pc);
     (void)hipFree(d_k0);
     (void)hipFree(d_lineE[0]);
@@ -457,6 +505,10 @@ Ctx::~Ctx() {
 }
 
 // ------------------------------------------------------------------ setup
+
+static std::atomic<double> g_eigen_cond_limit{1e4};
+double eigen_cond_limit() { return g_eigen_cond_limit.load(); }
+void set_eigen_cond_limit(double v) { g_eigen_cond_limit.store(v); }
 
 int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     auto t0 = std::chrono::steady_clock::now();
@@ -611,7 +663,23 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
             if (rc) return rc;
         }
     } else {
-        int rc = mean_eigen(n, c->h, kb, c->mu, c->Vt);
+        int rc = mean_eigen(n, c->h, kb, c->mu, c->Vt, &c->cond_v);
+        if (rc == SG_OK && !(c->cond_v <= eigen_cond_limit()))
+            rc = fail(SG_ESETUP, "eigenvector matrix of the mean block too ill-conditioned: cond " +
+                                     std::to_string(c->cond_v));
+        if (rc == SG_ESETUP && n <= 257) {
+            // fall back to the exact line factorisation of the same (constant-k̄) mean block,
+            // the paper's own approach of factorising the block (Section 6.3)
+            c->vmean = true;
+            c->eig_fallback = true;
+            std::vector<double> k0(P, kb);
+            rc = build_line_factors(c.get(), k0.data());
+            if (rc) return rc;
+            SG_HIP(hipDeviceSynchronize());
+            c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            *out = c.release();
+            return SG_OK;
+        }
         if (rc) return rc;
         for (int t = 0; t < 2; ++t) {
             std::vector<cplx> sig(n);

@@ -130,6 +130,11 @@ struct Workspace {
     int npartial_blocks = 0;
     double2* host_pinned = nullptr; // pinned host mirror of coef
     hipEvent_t done = nullptr; // host waits of the Arnoldi loop poll this event
+    // delayed CGS2 driver (dcgs2.cpp): reduction partials, small device arrays, pinned records
+    int dm = 0;
+    double2* dpart = nullptr;
+    double2* dsmall = nullptr;
+    double2* hrec = nullptr;
 };
 
 // Optional per-kernel-class event timing (sg_set_profiling / sg_kernel_times).
@@ -202,14 +207,19 @@ struct Ctx {
     double op_csl_beta = 0.0;          // operator of sg_apply and the solvers: A (0) or M(β) = A - iβK
     double2* d_tmp_pc = nullptr;       // preconditioner intermediate: Q·n rows of tld complex (2D)
     int tld = 0;                       // its row length, n rounded up to 8 (128-byte aligned rows)
-    // spatially varying mean k_0 (k_mean = 0 at setup): exact block LU over the grid lines
+    // block solves by the exact block LU over the grid lines: a spatially varying mean k_0
+    // (k_mean = 0 at setup), or the fallback when the eigenfactors fail their checks
     bool vmean = false;
+    bool eig_fallback = false;         // line factorisation chosen because of the eigenfactors
+    double cond_v = 0;                 // estimated cond₂ of the eigenvector matrix (2D, constant k̄)
     double* d_k0 = nullptr;            // k_0 at the nodes for the operator (null: constant kbar)
     int line_L = 0, line_nl = 0;       // line length and number of lines
     double2* d_lineE[2] = {};          // inverses of the line Schur complements, [j][k][i], A_0 and M_0
     double* d_lineb = nullptr;         // diagonal of the line coupling B
     double line_check[2] = {};         // setup residual of the factorisation (A_0, M_0)
     Net* net = nullptr;                // attached correction network (not owned)
+    bool classic_cgs2 = false;         // sg_set_orthogonalisation(SG_ORTH_CGS2): the two-pass driver
+    int last_k = 0;                    // orthonormal basis vectors of the last delayed-CGS2 cycle
     double t_setup_ms = 0;
 
     ~Ctx();
@@ -217,6 +227,8 @@ struct Ctx {
 
 // setup.cpp
 int build_ctx(const sg_problem* prob, hipStream_t stream, Ctx** out);
+double eigen_cond_limit();
+void set_eigen_cond_limit(double v);
 
 // apply.hip
 int launch_apply(const Ctx* c, const double2* x, double2* y, hipStream_t st);
@@ -275,6 +287,13 @@ int launch_axpby(long long n, double2 a, const double2* x, double2 b, const doub
                  hipStream_t st);
 int launch_scale_copy(long long n, double a, const double2* x, double2* out, hipStream_t st);
 int reduction_blocks(long long n);
+// Delayed CGS2 (see krylov.hip): reduction (w may be null: only a and α), coefficients, update.
+int launch_dcgs_reduce(long long n, int nv, const double2* V, long long ldv, const double2* u, const double2* w,
+                       double2* partial, int nblocks, double2* red, hipStream_t st);
+int launch_dcgs_finalize(int j, bool full, const double2* red, double2* h1prev, double2* rec, double2* cv, double2* cw,
+                         double2* cu, hipStream_t st);
+int launch_dcgs_update(long long n, int nv, const double2* V, long long ldv, double2* u, double2* w, const double2* cv,
+                       const double2* cw, const double2* cu, int nblocks, hipStream_t st);
 // Grouped forms: task t of d_tasks owns blocks [start[t], start[t+1]) of the launch.
 int launch_multidot_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv, double bytes,
                             hipStream_t st);
@@ -291,6 +310,7 @@ int launch_axpby_grouped(const VecTask* d_tasks, const int* d_start, int ntask, 
 int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, double2* const* x,
                       const sg_solve_opts* o, sg_solve_stats* stats, hipStream_t stream);
 int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out, hipStream_t stream);
+int batched_release();
 int tune_get(int n, int Q, int precision);
 void tune_set(int n, int Q, int precision, int cfg);
 
@@ -303,6 +323,10 @@ int wait_stream(hipStream_t st, hipEvent_t ev);
 int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_precond_cb cb,
               void* user, bool flexible, sg_solve_stats* st, hipStream_t stream);
 int run_stationary(Ctx* c, const double2* b, double2* x, int pc, int iters, double* hist, hipStream_t st);
+// dcgs2.cpp: the delayed-CGS2 driver of the built-in right preconditioners (restart <= 64)
+bool dcgs2_serves(const Ctx* c, const sg_solve_opts* o, sg_precond_cb cb);
+int run_gmres_dcgs2(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_solve_stats* st,
+                    hipStream_t stream);
 // d_next_scale (device, may be null) receives 1/||w|| after the two passes; the host waits
 // for the coefficients by polling `done` (null: a blocking stream synchronisation); with
 // wait = false (and done given) it only records `done` after the copy

@@ -84,6 +84,10 @@ def lib():
     L.sg_stationary.argtypes = [vp, vp, vp, i, i, C.POINTER(d), vp]
     L.sg_set_operator_shift.argtypes = [vp, d]
     L.sg_moments.argtypes = [vp, vp, vp, vp, vp]
+    L.sg_mean_solver.argtypes = [vp, C.POINTER(i), C.POINTER(d)]
+    L.sg_set_eigen_cond_limit.argtypes = [d]
+    L.sg_set_orthogonalisation.argtypes = [vp, i]
+    L.sg_last_basis.argtypes = [vp, C.POINTER(i), C.POINTER(vp)]
     L.sg_degree_magnitudes.argtypes = [vp, vp, C.POINTER(d), vp]
     L.sg_cgs2.argtypes = [ll, i, vp, vp, vp, vp]
     L.sg_cgs2_noalloc.argtypes = [ll, i, vp, vp, vp, vp]
@@ -92,6 +96,7 @@ def lib():
     L.sg_gmres_batched.argtypes = [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
                                    C.POINTER(SolveStats), vp]
     L.sg_autotune.argtypes = [i, C.POINTER(vp), i, i, C.POINTER(d), vp]
+    L.sg_batched_release.argtypes = []
     L.sg_tune_get.argtypes = [i, i, i]
     L.sg_tune_set.argtypes = [i, i, i, i]
     f = C.c_float
@@ -117,9 +122,9 @@ def lib():
     L.sg_last_error.argtypes = []
     L.sg_last_error.restype = C.c_char_p
     for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
-                 "sg_stationary", "sg_set_operator_shift", "sg_moments", "sg_degree_magnitudes", "sg_cgs2",
+                 "sg_stationary", "sg_set_operator_shift", "sg_moments", "sg_degree_magnitudes", "sg_mean_solver", "sg_set_eigen_cond_limit", "sg_set_orthogonalisation", "sg_last_basis", "sg_cgs2",
                  "sg_cgs2_noalloc", "sg_norm", "sg_axpby", "sg_set_profiling",
-                 "sg_kernel_times", "sg_gmres_batched", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
+                 "sg_kernel_times", "sg_gmres_batched", "sg_batched_release", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
                  "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step", "sg_net_train_pairs", "sg_net_save",
                  "sg_net_load", "sg_attach_net", "sg_profile_kinds"):
         getattr(L, name).restype = C.c_int
@@ -219,6 +224,22 @@ class SG:
         check(lib().sg_precond(self._h, PC[pc], PREC[precision], C.c_void_p(_ptr(r)), C.c_void_p(_ptr(z)),
                                C.c_void_p(_stream(stream))), "sg_precond")
         return z
+
+    def set_orthogonalisation(self, kind: str):
+        """"dcgs2" (default: delayed re-orthogonalisation) or "cgs2" (both passes in the same step)."""
+        check(lib().sg_set_orthogonalisation(self._h, {"dcgs2": 0, "cgs2": 1}[kind]), "sg_set_orthogonalisation")
+
+    def last_basis(self):
+        """The orthonormal basis of the last delayed-CGS2 cycle as a (k, size) torch view."""
+        k, p = C.c_int(), C.c_void_p()
+        check(lib().sg_last_basis(self._h, C.byref(k), C.byref(p)), "sg_last_basis")
+        return _wrap_device(p.value, k.value * self.size).view(k.value, self.size) if k.value else None
+
+    def mean_solver(self):
+        """("fd" | "line" | "line_fallback", estimated cond₂ of the eigenvector matrix)."""
+        k, cv = C.c_int(), C.c_double()
+        check(lib().sg_mean_solver(self._h, C.byref(k), C.byref(cv)), "sg_mean_solver")
+        return ("fd", "line", "line_fallback")[k.value], cv.value
 
     def moments(self, x, stream=None):
         """(E[u], Var[Re u], Var[Im u]) of the SG solution x, as torch tensors on the device."""
@@ -322,6 +343,12 @@ TILES = {"128x128": 0, "64x128": 1, "64x64": 2, "64x32": 3, "32x64": 4, "3m32x32
          "3m64x64": 8, "64x256": 9, "128x256": 10}
 
 
+def set_eigen_cond_limit(limit: float):
+    """Limit on cond₂ of the mean block's eigenvector matrix above which later setups use the
+    line factorisation (default 1e4)."""
+    check(lib().sg_set_eigen_cond_limit(float(limit)), "sg_set_eigen_cond_limit")
+
+
 def gmres_batched(ops, bs, xs=None, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8, stream=None):
     """Batched right-preconditioned GMRES over independent operators (``SG`` objects);
     returns (xs, status, [info per instance])."""
@@ -340,6 +367,11 @@ def gmres_batched(ops, bs, xs=None, restart=30, maxit=1000, pc="mean", precision
     rc = check(lib().sg_gmres_batched(cnt, H, B, X, C.byref(o), st, C.c_void_p(_stream(stream))),
                "sg_gmres_batched")
     return xs, rc, [st[i].as_dict() for i in range(cnt)]
+
+
+def batched_release():
+    """Free the batched solver's arena on the current device."""
+    check(lib().sg_batched_release(), "sg_batched_release")
 
 
 def autotune(ops, precision="f32", reps=5, stream=None) -> float:
@@ -475,7 +507,9 @@ def norm(x, stream=None) -> float:
 
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
-            "sg_fgmres", "sg_stationary", "sg_set_operator_shift", "sg_moments", "sg_degree_magnitudes", "sg_gmres_batched", "sg_autotune", "sg_tune_get",
+            "sg_fgmres", "sg_stationary", "sg_set_operator_shift", "sg_moments", "sg_degree_magnitudes", "sg_mean_solver",
+            "sg_set_eigen_cond_limit", "sg_set_orthogonalisation", "sg_last_basis", "sg_gmres_batched",
+            "sg_batched_release", "sg_autotune", "sg_tune_get",
             "sg_tune_set", "sg_cgs2", "sg_cgs2_noalloc", "sg_norm", "sg_axpby",
             "sg_set_profiling", "sg_profile_kinds", "sg_kernel_times", "sg_net_create", "sg_net_destroy", "sg_net_num_params",
             "sg_net_get_params", "sg_net_set_params", "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step",

@@ -635,3 +635,34 @@ def test_config3_forms_full_size():
         assert np.max(np.abs(bh[idx] - ax.ravel() - rh[idx])) <= 64 * 2.2e-16 * rowsum
     finally:
         op.close()
+
+
+@pytest.mark.parametrize("key,restart", [("2d_n150_s3_r3", 10), ("2d_n37_s2_r4", 40), ("c1_1d", 30)])
+def test_delayed_cgs2_orthogonality_and_counts(key, restart):
+    """Delayed CGS2 (the default) against the two-pass CGS2 of the same step: the Arnoldi
+    basis of the last cycle is orthonormal to ||VᴴV - I||_max <= 1e-12, the iteration
+    counts agree with CGS2's and with the oracle's modified Gram-Schmidt GMRES (±1), and the
+    solutions agree with the oracle's direct solution (1e-6)."""
+    inst = SMALL[key]()
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    try:
+        b = op.rhs(inst.f)
+        xd_, id_ = op.gmres(b, restart=restart, maxit=5000, pc="mean", tol=1e-10)
+        V = op.last_basis()
+        k = V.shape[0]
+        G = (V.conj() @ V.T).cpu().numpy()
+        orth = float(np.max(np.abs(G - np.eye(k))))
+        op.set_orthogonalisation("cgs2")
+        xc_, ic_ = op.gmres(b, restart=restart, maxit=5000, pc="mean", tol=1e-10)
+        op.set_orthogonalisation("dcgs2")
+        _, io = krylov.gmres(lambda v: S.A @ v, S.b, precond.mean_value(S), restart=restart, tol=1e-10, maxit=5000)
+        print("%s m=%d: dcgs2 %d its (basis %d, orth %.2e), cgs2 %d, oracle %d" % (
+            key, restart, id_["iters"], k, orth, ic_["iters"], io.iters), flush=True)
+        assert k >= 2 and orth <= 1e-12
+        assert abs(id_["iters"] - ic_["iters"]) <= 1 and abs(id_["iters"] - io.iters) <= 1
+        xd = reference_solution(key, S)
+        _check_solution(S, to_host(xd_), 1e-10, xd)
+        _check_solution(S, to_host(xc_), 1e-10, xd)
+    finally:
+        op.close()

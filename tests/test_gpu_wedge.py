@@ -305,3 +305,43 @@ def test_moments_match_oracle(key):
         assert np.allclose(g, g_ref, rtol=1e-14, atol=0)
     finally:
         op.close()
+
+
+# ------------------------------------------------ eigenfactor fallback
+
+def test_eigenfactor_fallback_to_line_factorisation():
+    """A constant-k̄ 2D block whose eigenfactors fail their checks is solved by the exact line
+    factorisation instead (forced here by a conditioning limit of 1): the handle reports the
+    fallback, its block solves match the oracle's sparse LU, and GMRES reaches the oracle's
+    solution.  The configs' own eigenvector matrices are far inside the default limit."""
+    from workloads import config2
+    key_inst = small_2d(n=40, kbar=9.0, sigma=0.9, s=2, degree=2)
+    S = assemble.from_instance(key_inst)
+    op = sg.SG.from_instance(key_inst)
+    kind, cond = op.mean_solver()
+    print("fd handle: %s, cond %.3g" % (kind, cond), flush=True)
+    assert kind == "fd" and 1.0 <= cond <= 1e4
+    op.close()
+    sg.set_eigen_cond_limit(1.0)
+    try:
+        op = sg.SG.from_instance(key_inst)
+    finally:
+        sg.set_eigen_cond_limit(1e4)
+    try:
+        assert op.mean_solver()[0] == "line_fallback"
+        r = rand_vec(S.A.shape[0], 9)
+        for pc, P in (("mean", precond.mean_value(S)), ("csl", precond.mean_csl(S, key_inst.beta))):
+            ref = P(r)
+            z = to_host(op.precond(to_dev(r), pc=pc))
+            assert np.max(np.abs(z - ref)) <= 1e-9 * np.max(np.abs(ref))
+        x, info = op.gmres(op.rhs(key_inst.f), restart=30, maxit=300, pc="mean", tol=1e-10)
+        xd = precond.direct_solve(S)
+        assert info["converged"] == 1 and np.max(np.abs(to_host(x) - xd)) <= 1e-6 * np.max(np.abs(xd))
+    finally:
+        op.close()
+    with pytest.raises(sg.SGError):
+        sg.set_eigen_cond_limit(0.5)
+    big = sg.SG.from_instance(config2())
+    print("config 2 eigenvector conditioning %.3g" % big.mean_solver()[1], flush=True)
+    assert big.mean_solver()[0] == "fd"
+    big.close()
