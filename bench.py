@@ -231,6 +231,10 @@ def learned_config5(n_pairs, n_eval, log):
     from paper_2209_14740_amd import learned, sg
     from workloads import config5_instance
     net = sg.Net(35, 4, seed=0)
+    # fixed transform tiles, so that the pairs, targets and hence the training do not depend on
+    # the autotuner's timing-based choices earlier in the process
+    sg.tune_set(255, 35, "f64", "3m32x32")
+    sg.tune_set(255, 35, "bf16x3", "64x128")
     rng = np.random.default_rng(0)
     seen, seed, losses = 0, 10000, []
     t_gen = t_train = 0.0

@@ -308,3 +308,25 @@ def test_trained_network_gain():
     ab = _ablation()
     for i0, i1, _, _ in ab["rows"]:
         assert i1["fallback"] == 0 and i1["iters"] <= i0["iters"], (i0["iters"], i1["iters"])
+
+
+def test_training_is_bit_reproducible():
+    """Two trainings from the same seed on the same solver pairs give bit-identical
+    parameters: the weight and bias gradients are reduced in a fixed order (per-block
+    partials, then one ordered sum), with no atomics."""
+    inst = [config5_instance(10000 + i, n=33) for i in range(2)]
+    ops = [sg.SG.from_instance(i) for i in inst]
+    try:
+        samples = []
+        for op, i in zip(ops, inst):
+            samples += [(op, r, e) for r, e in learned.solver_pairs(op, op.rhs(i.f), cycle=2, max_pairs=6)]
+        params = []
+        for _ in range(2):
+            net = sg.Net(35, 4, seed=7)
+            learned.train(net, samples, steps=12, batch=4, lr=1e-3)
+            params.append(net.get_params())
+            net.close()
+        assert np.array_equal(params[0], params[1])
+    finally:
+        for op in ops:
+            op.close()
