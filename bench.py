@@ -186,7 +186,9 @@ def batched_config4(count, log):
     log("batched FP64 preconditioner: %.3f s (%.1f solves/s), rc %d" % (t_solve64, count / t_solve64, rc64))
     # the same instances one at a time through sg_gmres (same algorithm and precision); the
     # first pass includes each handle's first Krylov-workspace allocation, the second is the
-    # steady state
+    # steady state. The batched solver's cached arena is handed back first: the 512 handles'
+    # own workspaces need that memory.
+    sg.batched_release()
     t_seq = []
     for _ in range(2):
         torch.cuda.synchronize()

@@ -729,9 +729,6 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
     return any_notconv ? SG_ENOTCONV : SG_OK;
 }
 
-// Autotuner: for every distinct (n, Q) of the 2D handles, time each GEMM tile shape on a
-// grouped launch over up to `group` instances of that shape (the batched setting), and
-// keep the fastest per instance in the process-wide table.
 int batched_release() {
     int dev = 0;
     SG_HIP(hipGetDevice(&dev));
@@ -747,6 +744,32 @@ int batched_release() {
     return SG_OK;
 }
 
+// Allocation of the per-handle buffers: when the device is full while an idle cached arena
+// holds memory, the arena is returned first and the allocation tried once more. An arena
+// that a batched solve is using (its lock held) is left alone.
+hipError_t device_alloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) return e;
+    (void)hipGetLastError();
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return e;
+    ArenaCache& ac = g_arena[dev];
+    {
+        std::unique_lock<std::mutex> lk(ac.mu, std::try_to_lock);
+        if (!lk.owns_lock() || !ac.p) return e;
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ac.p);
+        ac.p = nullptr;
+        ac.bytes = 0;
+    }
+    e = hipMalloc(p, bytes);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
+}
+
+// Autotuner: for every distinct (n, Q) of the 2D handles, time each GEMM tile shape on a
+// grouped launch over up to `group` instances of that shape (the batched setting), and
+// keep the fastest per instance in the process-wide table.
 int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out, hipStream_t stream) {
     if (count < 0 || (count > 0 && !ctx)) return fail(SG_EINVAL, "bad handle list");
     if (precision < SG_PREC_F64 || precision > SG_PREC_BF16X3) return fail(SG_EINVAL, "unknown precision");

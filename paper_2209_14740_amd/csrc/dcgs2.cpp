@@ -106,15 +106,17 @@ struct Givens {
 // Extra buffers of the delayed CGS2 driver inside the handle's workspace.
 static int ensure_dcgs(Ctx* c, int m) {
     Workspace& w = c->ws;
-    if (w.dpart && w.dm >= m) return SG_OK;
+    if (w.dpart && w.dsmall && w.hrec && w.dm >= m) return SG_OK;
     (void)hipFree(w.dpart);
     (void)hipFree(w.dsmall);
     if (w.hrec) (void)hipHostFree(w.hrec);
     w.dpart = w.dsmall = w.hrec = nullptr;
-    w.dm = m;
-    SG_HIP(hipMalloc(&w.dpart, (size_t)w.npartial_blocks * (2 * m + 3) * sizeof(double2)));
-    SG_HIP(hipMalloc(&w.dsmall, (size_t)(10 * m + 16) * sizeof(double2)));
+    w.dm = 0;
+    if (device_alloc((void**)&w.dpart, (size_t)w.npartial_blocks * (2 * m + 3) * sizeof(double2)) != hipSuccess ||
+        device_alloc((void**)&w.dsmall, (size_t)(10 * m + 16) * sizeof(double2)) != hipSuccess)
+        return fail(SG_ENOMEM, "delayed CGS2 buffer allocation failed");
     SG_HIP(hipHostMalloc(&w.hrec, (size_t)2 * (2 * m + 3) * sizeof(double2), hipHostMallocDefault));
+    w.dm = m;
     return SG_OK;
 }
 

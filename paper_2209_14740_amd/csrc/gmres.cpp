@@ -25,7 +25,7 @@ namespace sgi {
 
 int ensure_workspace(Ctx* c, int m, bool flexible) {
     Workspace& w = c->ws;
-    if (w.V && w.m >= m && (!flexible || w.Z)) return SG_OK;
+    if (w.V && w.done && w.m >= m && (!flexible || w.Z)) return SG_OK;   // w.done is set last
     (void)hipFree(w.V);
     (void)hipFree(w.Z);
     (void)hipFree(w.tmp);
@@ -42,10 +42,12 @@ int ensure_workspace(Ctx* c, int m, bool flexible) {
     w.m = m;
     w.flexible = flexible;
     w.npartial_blocks = reduction_blocks(c->nvec);
-    if (hipMalloc(&w.V, (size_t)(m + 1) * nv * sizeof(double2)) != hipSuccess) return fail(SG_ENOMEM, "Krylov basis allocation failed");
-    if (flexible && hipMalloc(&w.Z, (size_t)m * nv * sizeof(double2)) != hipSuccess)
+    if (device_alloc((void**)&w.V, (size_t)(m + 1) * nv * sizeof(double2)) != hipSuccess)
+        return fail(SG_ENOMEM, "Krylov basis allocation failed");
+    if (flexible && device_alloc((void**)&w.Z, (size_t)m * nv * sizeof(double2)) != hipSuccess)
         return fail(SG_ENOMEM, "flexible basis allocation failed");
-    if (hipMalloc(&w.tmp, 2 * nv * sizeof(double2)) != hipSuccess) return fail(SG_ENOMEM, "scratch allocation failed");
+    if (device_alloc((void**)&w.tmp, 2 * nv * sizeof(double2)) != hipSuccess)
+        return fail(SG_ENOMEM, "scratch allocation failed");
     SG_HIP(hipMalloc(&w.scale, (size_t)(m + 2) * sizeof(double)));
     SG_HIP(hipMalloc(&w.coef, (size_t)3 * (m + 2) * sizeof(double2)));
     SG_HIP(hipMalloc(&w.partial, (size_t)w.npartial_blocks * (m + 2) * sizeof(double2)));

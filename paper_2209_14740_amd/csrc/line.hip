@@ -17,9 +17,19 @@
 //     forward   y_0 = E_0 r_0,   y_j = E_j (r_j - B y_{j-1})
 //     backward  x_{n-1} = y_{n-1},   x_j = y_j - E_j B x_{j+1}.
 // The factors are checked at setup by solving a random system and measuring the residual
-// with the sparse block itself.  One GPU workgroup runs both sweeps for NC of the Q
-// right-hand sides; each line step is a dense L×L matrix times an L×NC block, the k range
-// split over KS thread groups so that enough loads of E_j are in flight.
+// with the sparse block itself.  Each line step is a dense L×L matrix-vector product per
+// right-hand side, and a step has to wait for the previous one, so the sweep is a chain of
+// 2n-1 dependent steps whose length is set by how fast one CU can stream E_j (L·L·16 bytes)
+// from L2 or the Infinity Cache.
+//   k_line_pipe (L <= 132): one workgroup per right-hand side; the rows of E_j are spread
+//     over the waves (16 per wave) and the k range of a row over the four 16-lane groups of
+//     a wave, whose partial sums are joined by lane exchanges (no LDS, one barrier per
+//     step).  Each lane keeps its KCM entries of the matrix in registers and loads those of
+//     the next step's matrix as it consumes the current ones, so the loads of step s+1 are in
+//     flight during the reduction and barrier of step s.  The k groups cover 4·KCM >= L rows;
+//     the rows past L-1 (the next matrix, or zero padding after the last one) meet t = 0.
+//   k_line_lu (longer lines): NC right-hand sides per workgroup, the k range split over KS
+//     thread groups joined through LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -128,6 +138,105 @@ __global__ __launch_bounds__(LT) void k_line_lu(const double2* __restrict__ E, c
             }
         __syncthreads();
     }
+}
+
+constexpr int PIPE_LMAX = 132;   // longest line of the pipelined kernel (4 groups of 33 rows)
+
+// Row-block base, advanced by one row and hidden from the optimiser: the bases are formed one
+// after another next to their loads (formed all at once they would hold one register pair
+// per row for the whole step).
+__device__ __forceinline__ const double2* next_row(const double2* p, int L) {
+    p += L;
+    asm volatile("" : "+s"(p));
+    return p;
+}
+// A wave-uniform base plus a 32-bit per-lane byte offset (one offset register for all loads).
+__device__ __forceinline__ double2 ld_off(const double2* base, unsigned boff) {
+    return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + boff);
+}
+
+template <int KCM>
+__global__ __launch_bounds__(576) void k_line_pipe(const double2* __restrict__ E, const double* __restrict__ b,
+                                                   const double2* r, double2* X, int L, int nl, long long P) {
+    constexpr int KG = 4, RW = 64 / KG;
+    __shared__ double2 t[2][PIPE_LMAX];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane / RW, ii = lane - g * RW;
+    const int i = w * RW + ii;
+    const bool rowok = i < L;
+    const int ic = rowok ? i : L - 1;
+    const bool lead = g == 0 && rowok;        // lane (0, i) owns row i's result
+    const int k0 = g * KCM;                   // this lane's rows k0 .. k0+KCM-1 of E_j
+    const long long q = blockIdx.x;
+    const double bi = b[ic];
+    const double2* rq = r + q * P + ic;
+    double2* xq = X + q * P + ic;
+    const int nsteps = 2 * nl - 1;            // forward j = 0..nl-1, then backward j = nl-2..0
+    auto mat = [&](int s) { return s < nl ? s : 2 * nl - 2 - s; };
+    const unsigned voff = (unsigned)(k0 * L + ic) * 16u;
+    double2 e[KCM];
+    {
+        const double2* Ep = E;
+#pragma unroll
+        for (int m = 0; m < KCM; ++m) {
+            e[m] = ld_off(Ep, voff);
+            Ep = next_row(Ep, L);
+        }
+    }
+    for (int k = L + (int)threadIdx.x; k < KG * KCM; k += blockDim.x) t[0][k] = t[1][k] = make_double2(0.0, 0.0);
+    if (lead) t[0][i] = rq[0];
+    // nxt: the right-hand side of the next forward step, then y_j of the next backward step
+    double2 nxt = lead && nl > 1 ? rq[(long long)L] : make_double2(0.0, 0.0);
+    __syncthreads();
+    int buf = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        const bool fwd = s < nl;
+        const int j = mat(s);
+        const double2 cur = nxt;
+        if (lead) {
+            if (fwd && j + 2 < nl) nxt = rq[(long long)(j + 2) * L];
+            else if (fwd && j == nl - 1 && nl >= 2) nxt = xq[(long long)(nl - 2) * L];
+            else if (!fwd && j >= 1) nxt = xq[(long long)(j - 1) * L];
+        }
+        double2 acc = make_double2(0.0, 0.0);
+        // the next step's matrix (the last step reloads its own: no branch in the loop)
+        const double2* Ep = E + (long long)mat(s + 1 < nsteps ? s + 1 : s) * L * L;
+#pragma unroll
+        for (int m = 0; m < KCM; ++m) {
+            const double2 tv = t[buf][k0 + m];
+            acc.x = fma(e[m].x, tv.x, fma(-e[m].y, tv.y, acc.x));
+            acc.y = fma(e[m].x, tv.y, fma(e[m].y, tv.x, acc.y));
+            e[m] = ld_off(Ep, voff);
+            Ep = next_row(Ep, L);
+        }
+#pragma unroll
+        for (int off = RW; off < 64; off <<= 1) {
+            acc.x += __shfl_xor(acc.x, off, 64);
+            acc.y += __shfl_xor(acc.y, off, 64);
+        }
+        if (lead) {
+            double2 x;
+            if (fwd) {   // y_j = E_j (r_j - B y_{j-1}); then r_{j+1} - B y_j, or B y_{n-1} to start backward
+                x = acc;
+                t[buf ^ 1][i] = j + 1 < nl ? make_double2(fma(-bi, x.x, cur.x), fma(-bi, x.y, cur.y))
+                                           : make_double2(bi * x.x, bi * x.y);
+            } else {     // x_j = y_j - E_j B x_{j+1}; then B x_j
+                x = make_double2(cur.x - acc.x, cur.y - acc.y);
+                t[buf ^ 1][i] = make_double2(bi * x.x, bi * x.y);
+            }
+            xq[(long long)j * L] = x;
+        }
+        buf ^= 1;
+        __syncthreads();
+    }
+}
+
+// Rows of each line factor the pipelined kernel reads (4·KCM >= L), or 0 for the LDS kernel.
+int pipe_kcm(int L) {
+    if (L <= 32) return 8;
+    if (L <= 64) return 16;
+    if (L <= PIPE_LMAX) return 33;
+    return 0;
 }
 
 // ---- host factorisation -----------------------------------------------------------
@@ -317,8 +426,13 @@ int build_line_factors(Ctx* c, const double* k0_host) {
                     const cplx v = Einv[((size_t)j * L + i) * L + k];
                     dev[((size_t)j * L + k) * L + i] = make_double2(v.real(), v.imag());
                 }
-        SG_HIP(hipMalloc(&c->d_lineE[t], dev.size() * sizeof(double2)));
+        // zero padding after the last factor: the pipelined kernel's last k group reads up to
+        // 4·KCM - L rows past the end of a factor
+        const int kcm = pipe_kcm(L);
+        const size_t pad = kcm ? (size_t)std::max(0, 4 * kcm - L) * L : 0;
+        SG_HIP(hipMalloc(&c->d_lineE[t], (dev.size() + pad) * sizeof(double2)));
         SG_HIP(hipMemcpy(c->d_lineE[t], dev.data(), dev.size() * sizeof(double2), hipMemcpyHostToDevice));
+        if (pad) SG_HIP(hipMemset(c->d_lineE[t] + dev.size(), 0, pad * sizeof(double2)));
     }
     SG_HIP(hipMalloc(&c->d_lineb, (size_t)L * sizeof(double)));
     SG_HIP(hipMemcpy(c->d_lineb, bl.data(), (size_t)L * sizeof(double), hipMemcpyHostToDevice));
@@ -328,11 +442,22 @@ int build_line_factors(Ctx* c, const double* k0_host) {
 int launch_line(Ctx* c, int pc, const double2* r, double2* z, hipStream_t st) {
     const int L = c->line_L, nl = c->line_nl;
     if (L < 1 || L > LT) return fail(SG_EINVAL, "varying-mean block solve: line length out of range");
+    const double2* E = c->d_lineE[pc == SG_PC_MEAN ? 0 : 1];
+    const int kcm = pipe_kcm(L);
+    if (kcm) {
+        // every workgroup streams all 2n-1 factors once (from L2 / the Infinity Cache)
+        KScope ks(SG_K_TRI, 16.0 * (2.0 * nl - 1.0) * L * L * c->Q + 48.0 * (double)c->nvec, st);
+        const dim3 grid((unsigned)c->Q), block((unsigned)(64 * ((L + 15) / 16)));
+        if (kcm == 8) hipLaunchKernelGGL(k_line_pipe<8>, grid, block, 0, st, E, c->d_lineb, r, z, L, nl, c->P);
+        else if (kcm == 16) hipLaunchKernelGGL(k_line_pipe<16>, grid, block, 0, st, E, c->d_lineb, r, z, L, nl, c->P);
+        else hipLaunchKernelGGL(k_line_pipe<33>, grid, block, 0, st, E, c->d_lineb, r, z, L, nl, c->P);
+        SG_HIP(hipGetLastError());
+        return SG_OK;
+    }
     const int KS = std::max(1, std::min(8, LT / L));   // KS > 1 only for L <= 256: the partial sums fit
     const int nblk = (c->Q + NC - 1) / NC;
     KScope ks(SG_K_TRI, 2.0 * 16.0 * (double)nl * L * L * nblk + 48.0 * (double)c->nvec, st);
-    hipLaunchKernelGGL(k_line_lu, dim3(nblk), dim3(LT), 0, st, c->d_lineE[pc == SG_PC_MEAN ? 0 : 1], c->d_lineb,
-                       r, z, L, nl, c->Q, KS, c->P);
+    hipLaunchKernelGGL(k_line_lu, dim3(nblk), dim3(LT), 0, st, E, c->d_lineb, r, z, L, nl, c->Q, KS, c->P);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }

@@ -558,6 +558,14 @@ __global__ __launch_bounds__(64) void k_tri(double2* __restrict__ X, TriFactors 
 __device__ __forceinline__ double2 csel(bool c, double2 a, double2 b) {
     return make_double2(c ? a.x : b.x, c ? a.y : b.y);
 }
+// The same row index, made to depend on v: the address formed from it, and the load, come
+// only after v is known, so the factor prefetches stay at the distance written (instead of
+// their addresses or loads being hoisted together and kept live through a pass) and each
+// pass reloads its rows.
+__device__ __forceinline__ int after(int i, double v) {
+    asm volatile("" : "+v"(i) : "v"(v));
+    return i;
+}
 __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {   // a*b + c
     return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
@@ -629,15 +637,26 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
             if (qok[r] && u <= L && i < len) b[r][u] = x[r][(long long)i * se];
         }
     }
+    // The row loops below read the factor rows PF rows ahead of their use, outside the
+    // per-row conditions and from clamped, always valid rows, so that a row step never
+    // waits for its own factor load.
+    constexpr int PF = NR == 2 ? 2 : 4;   // two right-hand sides: fewer registers, three waves per SIMD
+    const int ldl = max(len - 2, 0), lrow = len - 1;
+    auto rdl = [&](int i) { return (long long)min(i, ldl) * fs; };    // row i of dl, clamped
+    auto rrow = [&](int i) { return (long long)min(i, lrow) * fs; };  // row i of the others
     // forward, local run (segment 0 starts from b_0, the others from zero)
     double2 cur[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) cur[r] = csel(k == 0, b[r][0], zero);
+    double2 pl[PF], pd[PF];
+#pragma unroll
+    for (int d = 0; d < PF; ++d) pl[d] = dl[rdl(s0 + d)];
 #pragma unroll
     for (int u = 0; u < SEGL; ++u) {
         const int i = s0 + u;
+        const double2 l = pl[u % PF];
+        if (u + PF < SEGL) pl[u % PF] = dl[rdl(after(s0 + u + PF, cur[0].x))];
         if (i < e0 && i <= len - 2) {
-            const double2 l = dl[(long long)i * fs];
             const bool pv = (pm >> u) & 1u;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -670,12 +689,20 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
 #pragma unroll
     for (int r = 0; r < NR; ++r) cur[r] = csel(k == 0, b[r][0], sm.p[1 + r][max(tid - SYS, 0)]);
 #pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        pl[d] = dl[rdl(after(s0 + d, cur[0].x))];
+        pd[d] = dinv[rrow(after(s0 + d, cur[0].x))];
+    }
+#pragma unroll
     for (int u = 0; u < SEGL; ++u) {
         const int i = s0 + u;
+        const double2 l = pl[u % PF], di = pd[u % PF];
+        if (u + PF < SEGL) {
+            pl[u % PF] = dl[rdl(after(s0 + u + PF, cur[0].x))];
+            pd[u % PF] = dinv[rrow(after(s0 + u + PF, cur[0].x))];
+        }
         if (i < e0) {
-            const double2 di = dinv[(long long)i * fs];
             if (i <= len - 2) {
-                const double2 l = dl[(long long)i * fs];
                 const bool pv = (pm >> u) & 1u;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
@@ -696,11 +723,19 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
 #pragma unroll
     for (int r = 0; r < NR; ++r) x1[r] = x2[r] = zero;
 #pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        pl[d] = u1p[rrow(after(s0 + SEGL - 1 - d, b[0][0].x))];
+        pd[d] = u2p[rrow(after(s0 + SEGL - 1 - d, b[0][0].x))];
+    }
+#pragma unroll
     for (int u = SEGL - 1; u >= 0; --u) {
-        const int i = s0 + u;
+        const int i = s0 + u, slot = (SEGL - 1 - u) % PF;
+        const double2 w1 = pl[slot], w2 = pd[slot];
+        if (u - PF >= 0) {
+            pl[slot] = u1p[rrow(after(s0 + u - PF, x1[0].x))];
+            pd[slot] = u2p[rrow(after(s0 + u - PF, x1[0].x))];
+        }
         if (i < e0) {
-            const long long ro = (long long)i * fs;
-            const double2 w1 = u1p[ro], w2 = u2p[ro];
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const double2 xi = csub(csub(b[r][u], cmul(w1, x1[r])), cmul(w2, x2[r]));
@@ -758,11 +793,19 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
         x2[r] = csel(k == K - 1, zero, sm.p[5 + 2 * r][nxt_seg]);
     }
 #pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        pl[d] = u1p[rrow(after(s0 + SEGL - 1 - d, x1[0].x))];
+        pd[d] = u2p[rrow(after(s0 + SEGL - 1 - d, x1[0].x))];
+    }
+#pragma unroll
     for (int u = SEGL - 1; u >= 0; --u) {
-        const int i = s0 + u;
+        const int i = s0 + u, slot = (SEGL - 1 - u) % PF;
+        const double2 w1 = pl[slot], w2 = pd[slot];
+        if (u - PF >= 0) {
+            pl[slot] = u1p[rrow(after(s0 + u - PF, x1[0].x))];
+            pd[slot] = u2p[rrow(after(s0 + u - PF, x1[0].x))];
+        }
         if (i < e0) {
-            const long long ro = (long long)i * fs;
-            const double2 w1 = u1p[ro], w2 = u2p[ro];
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const double2 xi = csub(csub(b[r][u], cmul(w1, x1[r])), cmul(w2, x2[r]));

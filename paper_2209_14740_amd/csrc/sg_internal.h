@@ -311,6 +311,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                       const sg_solve_opts* o, sg_solve_stats* stats, hipStream_t stream);
 int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out, hipStream_t stream);
 int batched_release();
+hipError_t device_alloc(void** p, size_t bytes);
 int tune_get(int n, int Q, int precision);
 void tune_set(int n, int Q, int precision, int cfg);
 
