@@ -64,6 +64,12 @@ BLOCK_CASES = {
     "wedge_q127_r1": lambda: wedge_instance(1, 0.1, q=127),
     "wedge_q62_r1": lambda: wedge_instance(1, 0.2, q=62),        # n = 64: no line of 2^k + 1 nodes
     "const_k_line_path": lambda: small_2d(n=40, kbar=9.0, sigma=0.9, s=2, degree=2),
+    # line lengths at the edges of the line kernels: 24 (8 rows per lane group), 132 (the
+    # longest line of the register-pipelined kernel, 4 groups of 33 rows exactly) and 133
+    # (the LDS kernel for longer lines)
+    "wedge_q22_r2": lambda: wedge_instance(2, 0.1, q=22),
+    "wedge_q130_r1": lambda: wedge_instance(1, 0.1, q=130),
+    "wedge_q131_r1": lambda: wedge_instance(1, 0.2, q=131),
     "one_d_varying": _one_d_varying,
 }
 
