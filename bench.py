@@ -138,8 +138,9 @@ def batched_config4(count, log):
     from paper_2209_14740_amd import sg
     from workloads import config4_instances
     insts = config4_instances(count)
+    threads = setup_threads()
     t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
         ops = list(ex.map(sg.SG.from_instance, insts))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
@@ -184,19 +185,26 @@ def batched_config4(count, log):
     torch.cuda.synchronize()
     t_solve64 = time.perf_counter() - t0
     log("batched FP64 preconditioner: %.3f s (%.1f solves/s), rc %d" % (t_solve64, count / t_solve64, rc64))
-    # the same instances one at a time through sg_gmres (same algorithm and precision); the
-    # first pass includes each handle's first Krylov-workspace allocation, the second is the
-    # steady state. The batched solver's cached arena is handed back first: the 512 handles'
-    # own workspaces need that memory.
+    pipe = batched_pipelined(insts, 128, threads, log)
+    # the same instances one at a time through sg_gmres (same algorithm and precision), in
+    # windows of 64 handles: a first pass over the window with each handle's Krylov-workspace
+    # allocation, a second pass in the steady state (63 other solves between a handle's two
+    # solves, so its data is no longer in the caches), then the window's handles are freed
+    # (the flexible workspaces of all 512 handles, 61 vectors each, would not fit in device
+    # memory together).  The batched solver's cached arena is handed back first.
     sg.batched_release()
-    t_seq = []
-    for _ in range(2):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for op, b, x in zip(ops, bs, xs):
-            op.gmres(b, x, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
-        torch.cuda.synchronize()
-        t_seq.append(time.perf_counter() - t0)
+    t_seq = [0.0, 0.0]
+    for w0 in range(0, count, 64):
+        win = list(zip(ops, bs, xs))[w0:w0 + 64]
+        for k in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for op, b, x in win:
+                op.gmres(b, x, restart=30, maxit=1000, pc="mean", precision="f32", tol=1e-8)
+            torch.cuda.synchronize()
+            t_seq[k] += time.perf_counter() - t0
+        for op, _, _ in win:
+            op.close()
     log("one at a time: %.3f s with workspace allocation, %.3f s steady (%.1f solves/s)"
         % (t_seq[0], t_seq[1], count / t_seq[1]))
     its = np.array([i["iters"] for i in infos])
@@ -210,7 +218,8 @@ def batched_config4(count, log):
                                  "iters_mean": float(np.mean([i["iters"] for i in infos64]))},
            "f32_speedup_vs_f64_precond": t_solve64 / t_solve,
            "solve_s": t_solve, "one_at_a_time_solves_per_s": count / t_seq[1],
-           "one_at_a_time_first_pass_solves_per_s": count / t_seq[0], "setup_s": t_setup, "setup_threads": 8, "autotune_s": t_tune,
+           "one_at_a_time_first_pass_solves_per_s": count / t_seq[0], "setup_s": t_setup, "setup_threads": threads,
+           "setup_overlapped": pipe, "autotune_s": t_tune,
            "autotune_gpu_ms": tune_ms, "tiles": tiles, "all_converged": bool(rc == 0),
            "iters_mean": float(its.mean()), "iters_max": int(its.max()), "relres_true_max": float(rel.max()),
            "kernels": kern}
@@ -219,6 +228,45 @@ def batched_config4(count, log):
     del bs, xs
     torch.cuda.empty_cache()
     return out
+
+
+def setup_threads():
+    """Host threads for instance setup: the cores this process may use, at most 16."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def batched_pipelined(insts, chunk, threads, log):
+    """Setup overlapped with the solves: host threads set up the instances in order while
+    the main thread solves them in chunks of `chunk` (one sg_gmres_batched call each, on a
+    stream of its own) as soon as a chunk's handles exist.  Timed from no handles to all
+    solved; the handles are freed afterwards."""
+    import concurrent.futures as cf
+
+    import torch
+    from paper_2209_14740_amd import sg
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ops, iters, rc_all = [], [], 0
+    with cf.ThreadPoolExecutor(max_workers=max(1, threads - 1)) as ex:
+        futs = [ex.submit(sg.SG.from_instance, inst) for inst in insts]
+        with torch.cuda.stream(stream):
+            for c0 in range(0, len(insts), chunk):
+                part = [f.result() for f in futs[c0:c0 + chunk]]
+                ops += part
+                bs = [op.rhs(i.f) for op, i in zip(part, insts[c0:c0 + chunk])]
+                _, rc, infos = sg.gmres_batched(part, bs, None, restart=30, maxit=1000, pc="mean",
+                                                precision="f32", tol=1e-8, stream=stream)
+                rc_all = rc_all or rc
+                iters += [i["iters"] for i in infos]
+        stream.synchronize()
+    t = time.perf_counter() - t0
+    for op in ops:
+        op.close()
+    log("batched with setup overlapped (%d host threads, chunks of %d): %.3f s (%.1f solves/s), rc %d"
+        % (threads - 1, chunk, t, len(insts) / t, rc_all))
+    return {"s": t, "solves_per_s": len(insts) / t, "chunk": chunk, "host_threads": threads - 1,
+            "all_converged": bool(rc_all == 0), "iters_mean": float(np.mean(iters))}
 
 
 def learned_config5(n_pairs, n_eval, log):
