@@ -250,22 +250,29 @@ def batched_pipelined(insts, chunk, threads, log):
     ops, iters, rc_all = [], [], 0
     with cf.ThreadPoolExecutor(max_workers=max(1, threads - 1)) as ex:
         futs = [ex.submit(sg.SG.from_instance, inst) for inst in insts]
+        t_wait = t_solve = 0.0
         with torch.cuda.stream(stream):
             for c0 in range(0, len(insts), chunk):
+                ta = time.perf_counter()
                 part = [f.result() for f in futs[c0:c0 + chunk]]
+                tb = time.perf_counter()
                 ops += part
                 bs = [op.rhs(i.f) for op, i in zip(part, insts[c0:c0 + chunk])]
                 _, rc, infos = sg.gmres_batched(part, bs, None, restart=30, maxit=1000, pc="mean",
                                                 precision="f32", tol=1e-8, stream=stream)
+                stream.synchronize()
+                t_wait += tb - ta
+                t_solve += time.perf_counter() - tb
                 rc_all = rc_all or rc
                 iters += [i["iters"] for i in infos]
         stream.synchronize()
     t = time.perf_counter() - t0
     for op in ops:
         op.close()
-    log("batched with setup overlapped (%d host threads, chunks of %d): %.3f s (%.1f solves/s), rc %d"
-        % (threads - 1, chunk, t, len(insts) / t, rc_all))
+    log("batched with setup overlapped (%d host threads, chunks of %d): %.3f s (%.1f solves/s), rc %d; "
+        "waiting for setups %.3f s, in the solves %.3f s" % (threads - 1, chunk, t, len(insts) / t, rc_all, t_wait, t_solve))
     return {"s": t, "solves_per_s": len(insts) / t, "chunk": chunk, "host_threads": threads - 1,
+            "wait_setup_s": t_wait, "solve_s": t_solve,
             "all_converged": bool(rc_all == 0), "iters_mean": float(np.mean(iters))}
 
 

@@ -230,11 +230,14 @@ int  sg_stationary(sg_handle h, const sg_c64* b, sg_c64* x, int pc, int iters, d
 /* Batched right-preconditioned GMRES(m) over `count` independent problems of any
  * size (instances of a parametric study, each with its own handle).
  * The algorithm per instance is that of sg_gmres (Section 5 preconditioners, Section 6.3
- * block reuse); the instances advance in lockstep steps, each phase of a step being one
- * grouped kernel launch over all active instances, with one host synchronisation per
- * step.  Instances are admitted from a queue ordered by estimated cost (largest first)
- * into Krylov workspaces carved from one device arena of at most max(largest instance,
- * half the available device memory); the arena is kept for later calls on the same device
+ * block reuse), with the delayed CGS2 in the flexible form (2m+2 vectors of workspace per
+ * instance), or with the two-pass CGS2 and x += P^{-1}(V y) (m+3 vectors) when every handle
+ * of the batch is set to SG_ORTH_CGS2; the instances advance in lockstep steps, each phase of
+ * a step being one grouped kernel launch over all active instances, with one host
+ * synchronisation per step.  Instances are admitted from a queue ordered by estimated cost
+ * (largest first) into Krylov workspaces carved from one device arena of at most
+ * max(largest instance, half the available device memory); the arena is kept for later
+ * calls on the same device
  * (allocating it costs more than a batch of solves) until sg_batched_release() or the end of
  * the process, and calls on one device are serialised.
  * handles, b and x: host arrays of `count` entries; b[i], x[i] device vectors of

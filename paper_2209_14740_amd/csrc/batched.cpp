@@ -1,9 +1,10 @@
 // Batched restarted GMRES over many independent SG systems of uneven size (grid N and
 // PC size Q differ per instance), and the tile-shape autotuner of its GEMMs.
 //
-// Every instance runs the right-preconditioned GMRES(m) of gmres.cpp (the mean-value or
-// mean-CSL block solve of Section 5, CGS2 Arnoldi, Givens least squares, FP64 true
-// residual at the end of every cycle).  The batch advances in lockstep steps: in one
+// Every instance runs the right-preconditioned GMRES(m) of dcgs2.cpp (the mean-value or
+// mean-CSL block solve of Section 5, delayed-CGS2 Arnoldi in the flexible form, Givens
+// least squares, FP64 true residual at the end of every cycle), or that of gmres.cpp
+// (two-pass CGS2) when every handle asks for it.  The batch advances in lockstep steps: in one
 // step each active instance does one unit of work (start, one Arnoldi step, or the end of
 // a cycle), and every phase of the step is ONE grouped launch over all instances (the
 // block → instance map is a prefix table), followed by one host synchronisation for the
@@ -198,6 +199,541 @@ double cost_estimate(const Ctx* c) {
 
 }  // namespace
 
+// ---- delayed-CGS2 form ---------------------------------------------------------------------
+//
+// The per-instance process of dcgs2.cpp in lockstep steps: the Arnoldi process in the
+// flexible form (z_j = P^{-1} u_j kept in a Z basis, x += Z y), the second Gram-Schmidt pass
+// delayed by one step, so that each step reads an instance's basis twice (one reduction,
+// one update) instead of three times.  Column j-1 of H is complete at step j; when the
+// predicted residual of column j reaches the tolerance (or the cycle is full) step j+1 is a
+// finishing reduction of u_{j+1} alone.  The first step of an instance also copies b into
+// the basis and zeroes x; a cycle end forms x += Z y and the true residual r = b - A x in
+// slot 0, the next cycle's candidate u_0.
+namespace {
+
+struct DSlot {
+    int inst = -1;
+    Ctx* c = nullptr;
+    const double2* b = nullptr;
+    double2* x = nullptr;
+    double2 *V = nullptr, *Z = nullptr, *ut = nullptr, *partial = nullptr;
+    double2 *red = nullptr, *h1 = nullptr, *cv = nullptr, *cw = nullptr, *cu = nullptr;
+    int nblk = 0;
+    size_t off = 0, bytes = 0;
+    bool used = false;
+    bool start = false;     // the next step also copies b into slot 0 and zeroes x
+    bool end = false;       // the next step is a cycle end (x += Z y, residual)
+    bool full = true;       // the next Arnoldi step is a full one (else a finishing reduction)
+    bool breakdown = false;
+    int j = 0, k = 0;
+    double bnorm = 0, est = 1.0;
+    std::vector<cd> R, g, sn, y;
+    std::vector<double> cs;
+    sg_solve_stats st{};
+    std::chrono::steady_clock::time_point t0;
+
+    void new_cycle(int m) {
+        R.assign((size_t)(m + 1) * m, 0.0);
+        g.assign(m + 1, 0.0);
+        sn.assign(m, 0.0);
+        cs.assign(m, 0.0);
+        j = 0;
+        k = 0;
+        full = true;
+        end = false;
+    }
+    // Givens rotation of column jj (entries col[0..jj+1]); returns |g_{jj+1}|.  Without
+    // commit nothing is stored (a prediction).
+    double add(int m, int jj, std::vector<cd> col, bool commit) {
+        for (int i = 0; i < jj; ++i) {
+            const cd t = cs[i] * col[i] + sn[i] * col[i + 1];
+            col[i + 1] = -std::conj(sn[i]) * col[i] + cs[i] * col[i + 1];
+            col[i] = t;
+        }
+        const cd a = col[jj], bb = col[jj + 1];
+        double cj;
+        cd sj;
+        if (std::abs(bb) == 0.0) { cj = 1.0; sj = 0.0; }
+        else if (std::abs(a) == 0.0) { cj = 0.0; sj = std::conj(bb) / std::abs(bb); }
+        else {
+            const double t = std::hypot(std::abs(a), std::abs(bb));
+            cj = std::abs(a) / t;
+            sj = (a / std::abs(a)) * std::conj(bb) / t;
+        }
+        const cd gnext = -std::conj(sj) * g[jj];
+        if (commit) {
+            cs[jj] = cj;
+            sn[jj] = sj;
+            col[jj] = cj * a + sj * bb;
+            col[jj + 1] = 0.0;
+            for (int i = 0; i <= jj + 1; ++i) R[(size_t)i * m + jj] = col[i];
+            g[jj + 1] = gnext;
+            g[jj] = cj * g[jj];
+        }
+        return std::abs(gnext);
+    }
+};
+
+}  // namespace
+
+static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* const* b, double2* const* x,
+                                  const sg_solve_opts* o, sg_solve_stats* stats, hipStream_t stream) {
+    const int m = o->restart;
+    const int pc = o->precond, prec = o->precision;
+    const int RW = 2 * m + 3;        // record words per slot (also holds a cycle end's residual norm)
+    const int SW = 6 * m + 8;        // small device words per slot: red, h1, cv, cw, cu
+    std::vector<size_t> need(count);
+    size_t largest = 0, total = 0;
+    for (int i = 0; i < count; ++i) {
+        const size_t nv = (size_t)ctx[i]->nvec;
+        need[i] = align_up((size_t)(2 * m + 2) * nv * sizeof(double2)) +
+                  align_up((size_t)reduction_blocks(ctx[i]->nvec) * RW * sizeof(double2)) +
+                  align_up((size_t)SW * sizeof(double2));
+        largest = std::max(largest, need[i]);
+        total += need[i];
+    }
+    int dev = 0;
+    SG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(SG_EINVAL, "batched solve: device index out of range");
+    ArenaCache& ac = g_arena[dev];
+    std::lock_guard<std::mutex> arena_lock(ac.mu);
+    size_t freeb = 0, totb = 0;
+    SG_HIP(hipMemGetInfo(&freeb, &totb));
+    const size_t avail = freeb + ac.bytes;
+    const size_t arena_bytes = std::min(total, std::max(largest, avail / 2));
+    if (arena_bytes > avail) return fail(SG_ENOMEM, "batched solve: not enough device memory for one instance");
+    if (ac.bytes < arena_bytes) {
+        SG_HIP(hipStreamSynchronize(stream));
+        (void)hipFree(ac.p);
+        ac.p = nullptr;
+        ac.bytes = 0;
+        if (hipMalloc(&ac.p, arena_bytes) != hipSuccess) return fail(SG_ENOMEM, "batched solve: arena allocation failed");
+        ac.bytes = arena_bytes;
+    }
+    Arena arena;
+    arena.init(ac.p, arena_bytes);
+
+    std::vector<int> queue(count);
+    for (int i = 0; i < count; ++i) queue[i] = i;
+    std::stable_sort(queue.begin(), queue.end(),
+                     [&](int a, int c2) { return cost_estimate(ctx[a]) > cost_estimate(ctx[c2]); });
+    size_t qhead = 0;
+
+    const int S = count;
+    std::vector<DSlot> slots(S);
+    double2* d_rec = nullptr;
+    if (hipMalloc(&d_rec, (size_t)S * RW * sizeof(double2)) != hipSuccess)
+        return fail(SG_ENOMEM, "batched solve: record table allocation failed");
+    struct FreeD {
+        double2* p;
+        ~FreeD() { (void)hipFree(p); }
+    } free_rec{d_rec};
+    double2* h_rec = nullptr;
+    SG_HIP(hipHostMalloc(&h_rec, (size_t)S * RW * sizeof(double2), hipHostMallocDefault));
+    struct FreeH {
+        double2* p;
+        ~FreeH() { (void)hipHostFree(p); }
+    } free_hrec{h_rec};
+    int tri_nr = 2;
+    if (pc == SG_PC_NONE) tri_nr = 1;
+    for (int i = 0; i < count && tri_nr == 2; ++i)
+        if (!tri_nr_ok(ctx[i]->tri[pc == SG_PC_MEAN ? 0 : 1], ctx[i]->n, ctx[i]->Q, ctx[i]->dim)) tri_nr = 1;
+    hipEvent_t step_done = nullptr;
+    SG_HIP(hipEventCreateWithFlags(&step_done, hipEventDisableTiming));
+    struct FreeE {
+        hipEvent_t e;
+        ~FreeE() { (void)hipEventDestroy(e); }
+    } free_ev{step_done};
+    Staging stg;
+
+    std::vector<int> active;
+    bool any_notconv = false;
+    Group<VecTask> g_copy, g_lin, g_pcopy, g_xupd, g_res, g_norm, g_nred;
+    Group<ApplyArgs> g_apply;
+    std::map<std::pair<int, int>, Group<ApplyArgs>> g_spec;
+    Group<TriTask> g_tri;
+    std::vector<Group<GemmTask>> g_fwd(SG_GEMM_NCFG), g_inv(SG_GEMM_NCFG);
+    Group<DcgsTask> g_dred, g_dsum, g_dfin, g_dupd;
+    std::vector<double2> y_tab((size_t)S * (m + 1));
+
+    auto admit = [&]() {
+        while (qhead < queue.size()) {
+            const int i = queue[qhead];
+            size_t off = 0;
+            if (!arena.alloc(need[i], &off)) break;
+            int sidx = -1;
+            for (int sI = 0; sI < S; ++sI)
+                if (!slots[sI].used) { sidx = sI; break; }
+            if (sidx < 0) { arena.release(off, need[i]); break; }
+            ++qhead;
+            DSlot& s = slots[sidx];
+            s = DSlot{};
+            s.used = true;
+            s.inst = i;
+            s.c = ctx[i];
+            s.b = b[i];
+            s.x = x[i];
+            s.off = off;
+            s.bytes = need[i];
+            const size_t nv = (size_t)s.c->nvec;
+            unsigned char* p = arena.base + off;
+            s.V = reinterpret_cast<double2*>(p);
+            s.Z = s.V + (size_t)(m + 1) * nv;
+            s.ut = s.Z + (size_t)m * nv;
+            p += align_up((size_t)(2 * m + 2) * nv * sizeof(double2));
+            s.partial = reinterpret_cast<double2*>(p);
+            s.nblk = reduction_blocks(s.c->nvec);
+            p += align_up((size_t)s.nblk * RW * sizeof(double2));
+            s.red = reinterpret_cast<double2*>(p);   // 2m+3
+            s.h1 = s.red + RW;                       // m+1
+            s.cv = s.h1 + (m + 1);                   // m
+            s.cw = s.cv + m;                         // m
+            s.cu = s.cw + m;                         // 2
+            s.new_cycle(m);
+            s.start = true;
+            s.st.t_setup = s.c->t_setup_ms;
+            s.t0 = std::chrono::steady_clock::now();
+            active.push_back(sidx);
+        }
+    };
+    auto vt_base = [&](const DSlot& s) {
+        VecTask t{};
+        t.n = s.c->nvec;
+        t.nblocks = s.nblk;
+        t.ldv = s.c->nvec;
+        return t;
+    };
+
+    admit();
+    if (active.empty()) return fail(SG_ENOMEM, "batched solve: no instance fits the arena");
+    int rc = SG_OK;
+    while (!active.empty()) {
+        for (auto* gp : {&g_copy, &g_lin, &g_pcopy, &g_xupd, &g_res, &g_norm, &g_nred}) gp->clear();
+        g_apply.clear();
+        for (auto& kv : g_spec) kv.second.clear();
+        g_tri.clear();
+        for (auto& gg : g_fwd) gg.clear();
+        for (auto& gg : g_inv) gg.clear();
+        for (auto* gp : {&g_dred, &g_dsum, &g_dfin, &g_dupd}) gp->clear();
+        stg.reset();
+        int nslot = 0;
+        for (int sI : active) nslot = std::max(nslot, sI + 1);
+        for (int sI : active) {
+            const DSlot& s = slots[sI];
+            if (s.end)
+                for (int i = 0; i < s.k; ++i) y_tab[(size_t)sI * (m + 1) + i] = make_double2(s.y[i].real(), s.y[i].imag());
+        }
+        const size_t off_y = stg.put(y_tab.data(), (size_t)nslot * (m + 1) * sizeof(double2));
+        auto dy = [&](int sI) { return reinterpret_cast<const double2*>(stg.dev + off_y) + (size_t)sI * (m + 1); };
+        {
+            const size_t per = sizeof(VecTask) * 8 + sizeof(ApplyArgs) + sizeof(TriTask) + 2 * sizeof(GemmTask) +
+                               4 * sizeof(DcgsTask) + 48 * 4;
+            if ((rc = stg.ensure(align_up(stg.used) + (size_t)active.size() * per + 160 * ALIGN * 2))) return rc;
+        }
+        unsigned char* const dev_before = stg.dev;
+
+        size_t lds = 0;
+        auto add_apply = [&](Ctx* c, const double2* xin, double2* yout) {
+            const ApplyArgs aa = make_apply_args(c, xin, yout);
+            const double abytes = (double)c->P * (32.0 * c->Q + 8.0 * c->K.nfield);
+            if (c->dim == 2 && c->use_spec_apply && c->op_csl_beta == 0.0 &&
+                (long long)c->n * c->n * 16 < (1ll << 32) &&
+                dispatch_spec_grouped(c->s, c->degree, nullptr, nullptr, 0, 0, nullptr)) {
+                g_spec[{c->s, c->degree}].add(aa, spec_row_blocks(c->n), abytes);
+            } else {
+                g_apply.add(aa, aa.ntiles_x * aa.nrows, abytes);
+                lds = std::max(lds, apply_lds_bytes(c->Q, c->K.nfield));
+            }
+        };
+        int maxj = 0;
+        for (int sI : active) {
+            DSlot& s = slots[sI];
+            Ctx* c = s.c;
+            const long long n = c->nvec;
+            double2* rec = d_rec + (size_t)sI * RW;
+            if (s.end) {
+                // x += Z y; r = b - A x into slot 0; ||r|| into the record
+                VecTask t = vt_base(s);
+                t.V = s.Z;
+                t.nv = s.k;
+                t.coef = dy(sI);
+                t.w = s.ut;
+                g_lin.add(t, s.nblk, 16.0 * (s.k + 1) * n);
+                g_lin.maxnv = std::max(g_lin.maxnv, s.k);
+                VecTask xu = vt_base(s);
+                xu.x = s.x;
+                xu.y = s.ut;
+                xu.a = make_double2(1, 0);
+                xu.b = make_double2(1, 0);
+                xu.w = s.x;
+                g_xupd.add(xu, s.nblk, 48.0 * n);
+                add_apply(c, s.x, s.ut);
+                VecTask r = vt_base(s);
+                r.x = s.b;
+                r.y = s.ut;
+                r.a = make_double2(1, 0);
+                r.b = make_double2(-1, 0);
+                r.w = s.V;
+                g_res.add(r, s.nblk, 48.0 * n);
+                VecTask nm = vt_base(s);
+                nm.V = s.V;
+                nm.nv = 0;
+                nm.w = s.V;
+                nm.partial = s.partial;
+                g_norm.add(nm, s.nblk, 16.0 * n);
+                VecTask rn = nm;
+                rn.out = rec;
+                g_nred.add(rn, 1);
+                continue;
+            }
+            if (s.start) {
+                VecTask t = vt_base(s);   // u_0 = b (x = 0)
+                t.x = s.b;
+                t.a = make_double2(1, 0);
+                t.w = s.V;
+                g_copy.add(t, s.nblk, 32.0 * n);
+                VecTask z = vt_base(s);
+                z.a = make_double2(1, 0);
+                z.w = s.x;
+                g_copy.add(z, s.nblk, 16.0 * n);
+            }
+            const int j = s.j;
+            double2* uj = s.V + (size_t)j * n;
+            if (s.full) {
+                double2* zj = s.Z + (size_t)j * n;
+                if (pc == SG_PC_NONE || c->dim == 1) {
+                    VecTask t = vt_base(s);
+                    t.x = uj;
+                    t.a = make_double2(1, 0);
+                    t.w = zj;
+                    g_pcopy.add(t, s.nblk, 32.0 * n);
+                }
+                if (pc != SG_PC_NONE) {
+                    const TriFactors& f = c->tri[pc == SG_PC_MEAN ? 0 : 1];
+                    if (c->dim == 1) {
+                        TriTask tt = make_tri_task(f, zj, c->n, c->n, c->Q, 1, tri_nr);
+                        g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
+                    } else {
+                        const int cfg = gemm_cfg_for(c->n, c->Q * c->n, prec);
+                        const int M = c->Q * c->n;
+                        GemmTask gf = make_gemm_task(prec, reinterpret_cast<const double*>(uj), c->n, c->fwd, c->n,
+                                                     reinterpret_cast<double*>(c->d_tmp_pc), c->tld, M, cfg);
+                        GemmTask gi = make_gemm_task(prec, reinterpret_cast<const double*>(c->d_tmp_pc), c->tld, c->inv,
+                                                     c->n, reinterpret_cast<double*>(zj), c->n, M, cfg);
+                        const double fl = (gemm_cfg_3m(cfg) ? 6.0 : 8.0) * M * (double)c->n * c->n;
+                        g_fwd[cfg].add(gf, gf.tiles_m * gf.tiles_n, fl);
+                        g_inv[cfg].add(gi, gi.tiles_m * gi.tiles_n, fl);
+                        TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->tld, c->Q, 2, tri_nr);
+                        g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
+                    }
+                }
+                add_apply(c, zj, uj + n);
+            }
+            DcgsTask d{};
+            d.V = s.V;
+            d.ldv = n;
+            d.n = n;
+            d.partial = s.partial;
+            d.red = s.red;
+            d.h1 = s.h1;
+            d.rec = rec;
+            d.cv = s.cv;
+            d.cw = s.cw;
+            d.cu = s.cu;
+            d.j = j;
+            d.full = s.full ? 1 : 0;
+            d.nblocks = s.nblk;
+            maxj = std::max(maxj, j);
+            g_dred.add(d, s.nblk, 16.0 * (j + (s.full ? 2 : 1)) * n);
+            g_dsum.add(d, s.full ? 2 * j + 3 : j + 1);
+            g_dfin.add(d, 1);
+            if (s.full) g_dupd.add(d, s.nblk, 16.0 * (j + 4) * n);
+        }
+
+        for (auto* gp : {&g_copy, &g_lin, &g_pcopy, &g_xupd, &g_res, &g_norm, &g_nred}) stg.put_group(*gp);
+        stg.put_group(g_apply);
+        for (auto& kv : g_spec) stg.put_group(kv.second);
+        stg.put_group(g_tri);
+        for (auto& gg : g_fwd) stg.put_group(gg);
+        for (auto& gg : g_inv) stg.put_group(gg);
+        for (auto* gp : {&g_dred, &g_dsum, &g_dfin, &g_dupd}) stg.put_group(*gp);
+        if (stg.used > stg.cap || stg.dev != dev_before) return fail(SG_EINVAL, "batched solve: staging overflow");
+        std::memcpy(stg.pinned, stg.host.data(), stg.used);
+        SG_HIP(hipMemcpyAsync(stg.dev, stg.pinned, stg.used, hipMemcpyHostToDevice, stream));
+
+        // launches, in dependency order
+        if ((rc = launch_axpby_grouped(stg.dtasks(g_copy), stg.dstart(g_copy), g_copy.n(), g_copy.total(), g_copy.work,
+                                       stream)))
+            return rc;
+        if ((rc = launch_lincomb_grouped(stg.dtasks(g_lin), stg.dstart(g_lin), g_lin.n(), g_lin.total(), g_lin.maxnv,
+                                         g_lin.work, stream)))
+            return rc;
+        if ((rc = launch_axpby_grouped(stg.dtasks(g_pcopy), stg.dstart(g_pcopy), g_pcopy.n(), g_pcopy.total(),
+                                       g_pcopy.work, stream)))
+            return rc;
+        for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg)
+            if ((rc = launch_gemm_grouped(prec, cfg, stg.dtasks(g_fwd[cfg]), stg.dstart(g_fwd[cfg]), g_fwd[cfg].n(),
+                                          g_fwd[cfg].total(), g_fwd[cfg].work, stream)))
+                return rc;
+        int max_seg = 0;
+        for (const TriTask& tt : g_tri.tasks) max_seg = std::max(max_seg, tt.f.L);
+        if ((rc = launch_tri_grouped(stg.dtasks(g_tri), stg.dstart(g_tri), g_tri.n(), g_tri.total(), max_seg, tri_nr,
+                                     g_tri.work, stream)))
+            return rc;
+        for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg)
+            if ((rc = launch_gemm_grouped(prec, cfg, stg.dtasks(g_inv[cfg]), stg.dstart(g_inv[cfg]), g_inv[cfg].n(),
+                                          g_inv[cfg].total(), g_inv[cfg].work, stream)))
+                return rc;
+        if ((rc = launch_axpby_grouped(stg.dtasks(g_xupd), stg.dstart(g_xupd), g_xupd.n(), g_xupd.total(), g_xupd.work,
+                                       stream)))
+            return rc;
+        if ((rc = launch_apply_grouped(stg.dtasks(g_apply), stg.dstart(g_apply), g_apply.n(), g_apply.total(), lds,
+                                       g_apply.work, stream)))
+            return rc;
+        for (auto& kv : g_spec) {
+            Group<ApplyArgs>& gg = kv.second;
+            if (gg.n() == 0) continue;
+            KScope ks(SG_K_APPLY, gg.work, stream);
+            dispatch_spec_grouped(kv.first.first, kv.first.second, stg.dtasks(gg), stg.dstart(gg), gg.n(), gg.total(),
+                                  stream);
+            SG_HIP(hipGetLastError());
+        }
+        if ((rc = launch_axpby_grouped(stg.dtasks(g_res), stg.dstart(g_res), g_res.n(), g_res.total(), g_res.work,
+                                       stream)))
+            return rc;
+        if ((rc = launch_dcgs_reduce_grouped(stg.dtasks(g_dred), stg.dstart(g_dred), g_dred.n(), g_dred.total(), maxj,
+                                             g_dred.work, stream)))
+            return rc;
+        if ((rc = launch_dcgs_sum_grouped(stg.dtasks(g_dsum), stg.dstart(g_dsum), g_dsum.n(), g_dsum.total(), stream)))
+            return rc;
+        if ((rc = launch_dcgs_finalize_grouped(stg.dtasks(g_dfin), g_dfin.n(), stream))) return rc;
+        if ((rc = launch_dcgs_update_grouped(stg.dtasks(g_dupd), stg.dstart(g_dupd), g_dupd.n(), g_dupd.total(), maxj,
+                                             g_dupd.work, stream)))
+            return rc;
+        if ((rc = launch_upd_grouped(stg.dtasks(g_norm), stg.dstart(g_norm), g_norm.n(), g_norm.total(), 0, false,
+                                     g_norm.work, stream)))
+            return rc;
+        if ((rc = launch_reduce_grouped(stg.dtasks(g_nred), stg.dstart(g_nred), g_nred.n(), g_nred.total(), 1, stream)))
+            return rc;
+        SG_HIP(hipMemcpyAsync(h_rec, d_rec, (size_t)nslot * RW * sizeof(double2), hipMemcpyDeviceToHost, stream));
+        if ((rc = wait_stream(stream, step_done))) return rc;
+
+        // host part of every active instance
+        std::vector<int> still;
+        for (int sI : active) {
+            DSlot& s = slots[sI];
+            const double2* hr = h_rec + (size_t)sI * RW;
+            bool finished = false;
+            if (s.end) {
+                const double beta = hr[0].x;
+                ++s.st.restarts;
+                s.st.relres_true = beta / s.bnorm;
+                if (!std::isfinite(beta)) {
+                    s.st.relres_true = NAN;
+                    finished = true;
+                } else if (s.st.relres_true <= o->tol) {
+                    s.st.converged = 1;
+                    finished = true;
+                } else if (s.breakdown || s.st.iters >= o->maxit) {
+                    finished = true;
+                } else {
+                    s.new_cycle(m);   // u_0 = r is in slot 0
+                    s.est = s.st.relres_true;
+                }
+            } else {
+                const int j = s.j;
+                const bool was_full = s.full;
+                s.start = false;
+                const double nu = hr[j].x;
+                bool end = false;
+                if (!std::isfinite(nu)) {
+                    s.st.relres_true = NAN;
+                    finished = true;
+                } else if (j == 0) {
+                    if (s.bnorm == 0.0) {   // first step of the solve: ||u_0|| = ||b||
+                        s.bnorm = nu;
+                        s.st.relres_true = 1.0;
+                        if (nu == 0.0) {
+                            s.st.converged = 1;
+                            s.st.relres_true = 0.0;
+                            finished = true;
+                        }
+                    }
+                    s.g[0] = nu;
+                } else if (s.k < j) {
+                    // column j-1: rows 0..j-1 from the record, row j = ν_j
+                    std::vector<cd> col(j + 1);
+                    double colnorm = 0.0;
+                    bool bad = false;
+                    for (int i = 0; i < j; ++i) {
+                        col[i] = cd(hr[i].x, hr[i].y);
+                        if (!std::isfinite(col[i].real()) || !std::isfinite(col[i].imag())) bad = true;
+                        colnorm += std::norm(col[i]);
+                    }
+                    col[j] = nu;
+                    colnorm = std::sqrt(colnorm + nu * nu);
+                    if (bad) {
+                        s.st.relres_true = NAN;
+                        finished = true;
+                    } else {
+                        const double gn = s.add(m, j - 1, col, true);
+                        ++s.st.iters;
+                        s.k = j;
+                        s.est = gn / s.bnorm;
+                        s.st.relres_est = s.est;
+                        s.breakdown = !(nu > 1e-14 * colnorm);
+                        end = s.breakdown || s.est <= o->tol || s.st.iters >= o->maxit || j == m;
+                    }
+                }
+                if (!finished && end) {
+                    const int k = s.k;
+                    s.y.assign(k, 0.0);
+                    bool bad = false;
+                    for (int i = k - 1; i >= 0; --i) {
+                        cd acc = s.g[i];
+                        for (int l = i + 1; l < k; ++l) acc -= s.R[(size_t)i * m + l] * s.y[l];
+                        s.y[i] = acc / s.R[(size_t)i * m + i];
+                        if (!std::isfinite(s.y[i].real()) || !std::isfinite(s.y[i].imag())) bad = true;
+                    }
+                    if (bad) {
+                        s.st.relres_true = NAN;
+                        finished = true;
+                    } else {
+                        s.end = true;
+                    }
+                } else if (!finished && !was_full) {
+                    s.full = true;   // the finishing reduction fell short: step j again, in full
+                } else if (!finished) {
+                    // predict column j from step j's record: first-pass projection of w_j and
+                    // ||u_{j+1}||² = ||w_j||² - ||h||²; decide the kind of step j+1
+                    const double pred = hr[2 * j + 2].y;
+                    std::vector<cd> pcol(j + 2);
+                    for (int i = 0; i <= j; ++i) pcol[i] = cd(hr[j + 1 + i].x, hr[j + 1 + i].y);
+                    pcol[j + 1] = pred > 0.0 ? std::sqrt(pred) : 0.0;
+                    const double pest = s.add(m, j, pcol, false) / s.bnorm;
+                    const bool finish_next = j + 1 == m || s.st.iters + 1 >= o->maxit ||
+                                             (s.est <= 30.0 * o->tol && pest <= o->tol);
+                    s.j = j + 1;
+                    s.full = !finish_next;
+                }
+            }
+            if (finished) {
+                s.st.t_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - s.t0).count();
+                if (!s.st.converged) any_notconv = true;
+                if (stats) stats[s.inst] = s.st;
+                arena.release(s.off, s.bytes);
+                s.used = false;
+            } else {
+                still.push_back(sI);
+            }
+        }
+        active.swap(still);
+        admit();
+        if (active.empty() && qhead < queue.size()) return fail(SG_ENOMEM, "batched solve: arena fragmentation");
+    }
+    return any_notconv ? SG_ENOTCONV : SG_OK;
+}
+
 int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, double2* const* x,
                       const sg_solve_opts* o, sg_solve_stats* stats, hipStream_t stream) {
     if (count < 0) return fail(SG_EINVAL, "count must be >= 0");
@@ -229,6 +765,10 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         largest = std::max(largest, need[i]);
         total += need[i];
     }
+    // the delayed-CGS2 form unless a handle asks for the two-pass CGS2 (sg_set_orthogonalisation)
+    bool dcgs = true;
+    for (int i = 0; i < count; ++i) dcgs = dcgs && !ctx[i]->classic_cgs2;
+    if (dcgs) return run_gmres_batched_dcgs(count, ctx, b, x, o, stats, stream);
     // The arena is kept per device between calls (a fresh allocation of this size costs far
     // more than the solves: the driver clears the memory it hands out); calls on one device
     // are serialised by its lock.

@@ -383,9 +383,9 @@ __global__ __launch_bounds__(RB) void k_axpby_g(const VecTask* __restrict__ task
 // iteration: all their loads are issued before the first product (each lane still adds its
 // chunks in grid-stride order).
 template <int NVW, int UNR>
-__global__ __launch_bounds__(RB) void k_dcgs_reduce(long long n, int nv, const double2* __restrict__ V, long long ldv,
-                                                    const double2* __restrict__ u, const double2* __restrict__ w,
-                                                    double2* __restrict__ partial) {
+__device__ __forceinline__ void dcgs_reduce_block(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                                  const double2* __restrict__ u, const double2* __restrict__ w,
+                                                  double2* __restrict__ partial, int lb, int nblk) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool hasw = w != nullptr;
@@ -398,8 +398,8 @@ __global__ __launch_bounds__(RB) void k_dcgs_reduce(long long n, int nv, const d
 #pragma unroll
     for (int m = 0; m < NVW; ++m) ca[m] = cb[m] = make_double2(0.0, 0.0);
     double2 sc = make_double2(0.0, 0.0);   // wave 0: α; wave 1: β; wave 2: ω
-    const long long stride = (long long)gridDim.x * 64;
-    for (long long c0 = (long long)blockIdx.x * 64; c0 < n; c0 += stride * UNR) {
+    const long long stride = (long long)nblk * 64;
+    for (long long c0 = (long long)lb * 64; c0 < n; c0 += stride * UNR) {
         double2 ui[UNR], wi[UNR], vv[UNR][NVW];
 #pragma unroll
         for (int q = 0; q < UNR; ++q) {
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(RB) void k_dcgs_reduce(long long n, int nv, const d
             } else if (wv == 2 && hasw) sc.x = fma(wi[q].x, wi[q].x, fma(wi[q].y, wi[q].y, sc.x));
         }
     }
-    double2* out = partial + (long long)blockIdx.x * nout;
+    double2* out = partial + (long long)lb * nout;
 #pragma unroll
     for (int m = 0; m < NVW; ++m) {
         const double ax = wave_sum(ca[m].x), ay = wave_sum(ca[m].y);
@@ -456,6 +456,13 @@ __global__ __launch_bounds__(RB) void k_dcgs_reduce(long long n, int nv, const d
     }
 }
 
+template <int NVW, int UNR>
+__global__ __launch_bounds__(RB) void k_dcgs_reduce(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                                    const double2* __restrict__ u, const double2* __restrict__ w,
+                                                    double2* __restrict__ partial) {
+    dcgs_reduce_block<NVW, UNR>(n, nv, V, ldv, u, w, partial, blockIdx.x, gridDim.x);
+}
+
 // One block: the coefficients of step j from the reduced sums red[] (layout of k_dcgs_reduce)
 // and the previous first-pass projection h1prev[0..j) of w_{j-1}.  Writes
 //   rec[0..j]       the completed Hessenberg column j-1 (h1prev + a, then ν)     (j >= 1)
@@ -464,10 +471,10 @@ __global__ __launch_bounds__(RB) void k_dcgs_reduce(long long n, int nv, const d
 // and, for the update pass, cv[k] (v_j = cu_v u_j + Σ cv_k v_k), cw[k] (u_{j+1} = w_j + cu_u u_j +
 // Σ cw_k v_k), cu = (cu_v, cu_u), and h1prev <- h1.  A non-positive ν² gives ν = 0 (breakdown:
 // the host stops the cycle; the update then writes non-finite values into unused slots).
-__global__ __launch_bounds__(RB) void k_dcgs_finalize(int j, int full, const double2* __restrict__ red,
-                                                      double2* __restrict__ h1prev, double2* __restrict__ rec,
-                                                      double2* __restrict__ cv, double2* __restrict__ cw,
-                                                      double2* __restrict__ cu) {
+__device__ __forceinline__ void dcgs_finalize_block(int j, int full, const double2* __restrict__ red,
+                                                    double2* __restrict__ h1prev, double2* __restrict__ rec,
+                                                    double2* __restrict__ cv, double2* __restrict__ cw,
+                                                    double2* __restrict__ cu) {
     __shared__ double s_nu, s_hx, s_hy;
     __shared__ double red_a[RB / 64], red_bx[RB / 64], red_by[RB / 64];
     const int t = threadIdx.x;
@@ -545,15 +552,22 @@ __global__ __launch_bounds__(RB) void k_dcgs_finalize(int j, int full, const dou
     }
 }
 
+__global__ __launch_bounds__(RB) void k_dcgs_finalize(int j, int full, const double2* __restrict__ red,
+                                                      double2* __restrict__ h1prev, double2* __restrict__ rec,
+                                                      double2* __restrict__ cv, double2* __restrict__ cw,
+                                                      double2* __restrict__ cu) {
+    dcgs_finalize_block(j, full, red, h1prev, rec, cv, cw, cu);
+}
+
 // v_j (into u's slot) and u_{j+1} (into w's slot): the wave-split basis of cgs_block, the
 // per-wave partial sums of both combinations meeting in LDS; u (waves 0 and 1) and w (wave 1)
 // are read before the barrier, wave 0 stores v_j and wave 1 stores u_{j+1} after it.  UNR
 // grid-stride chunks per iteration, their loads issued together.
 template <int NVW, int UNR>
-__global__ __launch_bounds__(RB) void k_dcgs_update(long long n, int nv, const double2* __restrict__ V, long long ldv,
-                                                    double2* __restrict__ u, double2* __restrict__ w,
-                                                    const double2* __restrict__ cv, const double2* __restrict__ cw,
-                                                    const double2* __restrict__ cu) {
+__device__ __forceinline__ void dcgs_update_block(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                                  double2* __restrict__ u, double2* __restrict__ w,
+                                                  const double2* __restrict__ cv, const double2* __restrict__ cw,
+                                                  const double2* __restrict__ cu, int lb, int nblk) {
     __shared__ double2 part[2][RB / 64][UNR][2][64];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -569,9 +583,9 @@ __global__ __launch_bounds__(RB) void k_dcgs_update(long long n, int nv, const d
         }
     }
     const double2 cuv = cu[0], cuu = cu[1];
-    const long long stride = (long long)gridDim.x * 64;
+    const long long stride = (long long)nblk * 64;
     int buf = 0;
-    for (long long c0 = (long long)blockIdx.x * 64; c0 < n; c0 += stride * UNR, buf ^= 1) {
+    for (long long c0 = (long long)lb * 64; c0 < n; c0 += stride * UNR, buf ^= 1) {
         double2 vv[UNR][NVW], ui[UNR], wi[UNR];
         bool ok[UNR];
 #pragma unroll
@@ -617,6 +631,70 @@ __global__ __launch_bounds__(RB) void k_dcgs_update(long long n, int nv, const d
             }
         }
     }
+}
+
+template <int NVW, int UNR>
+__global__ __launch_bounds__(RB) void k_dcgs_update(long long n, int nv, const double2* __restrict__ V, long long ldv,
+                                                    double2* __restrict__ u, double2* __restrict__ w,
+                                                    const double2* __restrict__ cv, const double2* __restrict__ cw,
+                                                    const double2* __restrict__ cu) {
+    dcgs_update_block<NVW, UNR>(n, nv, V, ldv, u, w, cv, cw, cu, blockIdx.x, gridDim.x);
+}
+
+// ---- grouped delayed CGS2 (the batched solver): one launch per phase over the instances
+// of a lockstep step; the block -> task map is the prefix table of the other grouped kernels.
+
+template <int NVW, int UNR>
+__global__ __launch_bounds__(RB) void k_dcgs_reduce_g(const DcgsTask* __restrict__ tasks, const int* __restrict__ start,
+                                                      int ntask) {
+    const int t = task_of(start, ntask, blockIdx.x);
+    const DcgsTask& g = tasks[t];
+    const double2* u = g.V + (long long)g.j * g.ldv;
+    dcgs_reduce_block<NVW, UNR>(g.n, g.j, g.V, g.ldv, u, g.full ? u + g.ldv : nullptr, g.partial,
+                                blockIdx.x - start[t], g.nblocks);
+}
+
+// One block per (task, output k): red[k] = Σ_b partial[b][k] over the task's first-stage blocks.
+__global__ __launch_bounds__(RB) void k_dcgs_sum_g(const DcgsTask* __restrict__ tasks, const int* __restrict__ start,
+                                                   int ntask) {
+    __shared__ double2 red[RB / 64];
+    const int t = task_of(start, ntask, blockIdx.x);
+    const DcgsTask& g = tasks[t];
+    const int k = blockIdx.x - start[t];
+    const int nout = g.full ? 2 * g.j + 3 : g.j + 1;
+    double sx = 0.0, sy = 0.0;
+    for (int b = threadIdx.x; b < g.nblocks; b += RB) {
+        const double2 p = g.partial[(long long)b * nout + k];
+        sx += p.x;
+        sy += p.y;
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double2(sx, sy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tx = 0.0, ty = 0.0;
+        for (int w = 0; w < RB / 64; ++w) {
+            tx += red[w].x;
+            ty += red[w].y;
+        }
+        g.red[k] = make_double2(tx, ty);
+    }
+}
+
+__global__ __launch_bounds__(RB) void k_dcgs_finalize_g(const DcgsTask* __restrict__ tasks, int ntask) {
+    const DcgsTask& g = tasks[blockIdx.x];
+    dcgs_finalize_block(g.j, g.full, g.red, g.h1, g.rec, g.cv, g.cw, g.cu);
+}
+
+template <int NVW, int UNR>
+__global__ __launch_bounds__(RB) void k_dcgs_update_g(const DcgsTask* __restrict__ tasks, const int* __restrict__ start,
+                                                      int ntask) {
+    const int t = task_of(start, ntask, blockIdx.x);
+    const DcgsTask& g = tasks[t];
+    double2* u = const_cast<double2*>(g.V) + (long long)g.j * g.ldv;
+    dcgs_update_block<NVW, UNR>(g.n, g.j, g.V, g.ldv, u, u + g.ldv, g.cv, g.cw, g.cu, blockIdx.x - start[t],
+                                g.nblocks);
 }
 
 }  // namespace
@@ -843,6 +921,54 @@ int launch_lincomb_grouped(const VecTask* d_tasks, const int* d_start, int ntask
     SG_LCG(64)
 #undef SG_LCG
     return fail(SG_EINVAL, "batched solve: restart length above 64");
+}
+
+int launch_dcgs_reduce_grouped(const DcgsTask* d_tasks, const int* d_start, int ntask, int total, int maxj, double bytes,
+                               hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_DOT, bytes, st);
+    const int nvw = (maxj + 3) / 4;
+#define SG_DRG(NVW_)                                                                                             \
+    if (nvw <= NVW_) {                                                                                           \
+        hipLaunchKernelGGL((k_dcgs_reduce_g<NVW_, 1>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);  \
+        SG_HIP(hipGetLastError());                                                                               \
+        return SG_OK;                                                                                            \
+    }
+    SG_DRG(1) SG_DRG(2) SG_DRG(4) SG_DRG(8) SG_DRG(16)
+#undef SG_DRG
+    return fail(SG_EINVAL, "batched solve: more than 64 basis vectors");
+}
+
+int launch_dcgs_sum_grouped(const DcgsTask* d_tasks, const int* d_start, int ntask, int total, hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_NORM, 0.0, st);
+    hipLaunchKernelGGL(k_dcgs_sum_g, dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_dcgs_finalize_grouped(const DcgsTask* d_tasks, int ntask, hipStream_t st) {
+    if (ntask <= 0) return SG_OK;
+    KScope ks(SG_K_NORM, 0.0, st);
+    hipLaunchKernelGGL(k_dcgs_finalize_g, dim3(ntask), dim3(RB), 0, st, d_tasks, ntask);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_dcgs_update_grouped(const DcgsTask* d_tasks, const int* d_start, int ntask, int total, int maxj, double bytes,
+                               hipStream_t st) {
+    if (ntask <= 0 || total <= 0) return SG_OK;
+    KScope ks(SG_K_AXPY, bytes, st);
+    const int nvw = (maxj + 3) / 4;
+#define SG_DUG(NVW_)                                                                                             \
+    if (nvw <= NVW_) {                                                                                           \
+        hipLaunchKernelGGL((k_dcgs_update_g<NVW_, 1>), dim3(total), dim3(RB), 0, st, d_tasks, d_start, ntask);  \
+        SG_HIP(hipGetLastError());                                                                               \
+        return SG_OK;                                                                                            \
+    }
+    SG_DUG(1) SG_DUG(2) SG_DUG(4) SG_DUG(8) SG_DUG(16)
+#undef SG_DUG
+    return fail(SG_EINVAL, "batched solve: more than 64 basis vectors");
 }
 
 int launch_axpby_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, double bytes,

@@ -118,6 +118,25 @@ struct VecTask {
     int nblocks;             // blocks of the first-stage kernels
 };
 
+// One instance's delayed-CGS2 step in a grouped launch (batched solver).  The basis holds the
+// orthonormal v_0..v_{j-1} in slots 0..j-1, the candidate u_j in slot j and, for a full step,
+// w_j = A z_j in slot j+1; the update pass overwrites slot j with v_j and slot j+1 with
+// u_{j+1}.
+struct DcgsTask {
+    const double2* V;
+    long long ldv, n;
+    double2* partial;   // first-stage sums [block][2j+3] (finishing step: [block][j+1])
+    double2* red;       // their totals
+    double2* h1;        // first-pass projection of the previous step (j+1 entries)
+    double2* rec;       // the step's record for the host (2j+3 entries)
+    double2* cv;        // update coefficients (j, j and 2 entries)
+    double2* cw;
+    double2* cu;
+    int j;              // basis vectors before the candidate
+    int full;           // 1: w_j present; 0: finishing reduction of u_j alone (no update)
+    int nblocks;        // first-stage blocks of this task
+};
+
 struct Workspace {
     int m = 0;                 // restart length the buffers were sized for
     bool flexible = false;
@@ -301,6 +320,12 @@ int launch_reduce_grouped(const VecTask* d_tasks, const int* d_start, int ntask,
                           hipStream_t st);
 int launch_upd_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv, bool dot,
                        double bytes, hipStream_t st);
+int launch_dcgs_reduce_grouped(const DcgsTask* d_tasks, const int* d_start, int ntask, int total, int maxj, double bytes,
+                               hipStream_t st);
+int launch_dcgs_sum_grouped(const DcgsTask* d_tasks, const int* d_start, int ntask, int total, hipStream_t st);
+int launch_dcgs_finalize_grouped(const DcgsTask* d_tasks, int ntask, hipStream_t st);
+int launch_dcgs_update_grouped(const DcgsTask* d_tasks, const int* d_start, int ntask, int total, int maxj, double bytes,
+                               hipStream_t st);
 int launch_lincomb_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, int maxnv,
                            double bytes, hipStream_t st);
 int launch_axpby_grouped(const VecTask* d_tasks, const int* d_start, int ntask, int total, double bytes,

@@ -107,6 +107,40 @@ def test_batched_iterations_match_single(small_ops):
         assert d <= 1e-9
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batched_delayed_and_two_pass_cgs2_agree(small_ops, precision):
+    """The batch with the delayed CGS2 (the default: flexible Arnoldi, one reduction and one
+    update pass per step) and with the two-pass CGS2 (every handle set to "cgs2"): both
+    converge to the oracle's solution.  With the FP64 preconditioner the two generate the
+    same Krylov space: iteration counts within one, solutions within 1e-7.  With the FP32
+    preconditioner the two-pass form applies P^{-1} again to V y at the cycle end (it assumes
+    a linear preconditioner) while the flexible form keeps the z_j it used, so the delayed
+    form needs at most as many iterations (one of slack) and the solutions agree to 1e-6."""
+    bs = [op.rhs(inst.f) for op, inst in zip(small_ops, SMALL)]
+    xd, rcd, infd = sg.gmres_batched(small_ops, bs, restart=12, maxit=600, pc="mean", precision=precision, tol=1e-9)
+    try:
+        for op in small_ops:
+            op.set_orthogonalisation("cgs2")
+        xc, rcc, infc = sg.gmres_batched(small_ops, bs, restart=12, maxit=600, pc="mean", precision=precision,
+                                         tol=1e-9)
+    finally:
+        for op in small_ops:
+            op.set_orthogonalisation("dcgs2")
+    assert rcd == sg.SG_OK and rcc == sg.SG_OK
+    for inst, a, c, ia, ic in zip(SMALL, xd, xc, infd, infc):
+        S, xref = ref(inst)
+        for xv in (a, c):
+            err = np.linalg.norm(to_host(xv) - xref) / np.linalg.norm(xref)
+            assert err <= 1e-6, (inst.name, err)
+        print(inst.name, precision, ia["iters"], ic["iters"], ia["restarts"], ic["restarts"], flush=True)
+        if precision == "f64":
+            assert abs(ia["iters"] - ic["iters"]) <= 1, (inst.name, ia["iters"], ic["iters"])
+            assert float((a - c).abs().max() / c.abs().max()) <= 1e-7
+        else:
+            assert ia["iters"] <= ic["iters"] + 1, (inst.name, ia["iters"], ic["iters"])
+            assert float((a - c).abs().max() / c.abs().max()) <= 1e-6
+
+
 @pytest.mark.parametrize("tile", ["128x128", "64x128", "64x64", "64x32", "32x64", "3m32x32", "3m64x32", "3m32x64",
                                   "3m64x64"])
 def test_batched_tile_shapes(small_ops, tile):
