@@ -141,6 +141,31 @@ def test_batched_delayed_and_two_pass_cgs2_agree(small_ops, precision):
             assert float((a - c).abs().max() / c.abs().max()) <= 1e-6
 
 
+@pytest.mark.parametrize("restart,pc", [(1, "mean"), (2, "csl"), (3, "none")])
+def test_batched_short_restarts_match_single(small_ops, restart, pc):
+    """Restart lengths 1-3 (every cycle ends in a finishing reduction of the delayed CGS2 at
+    j = m) and the unpreconditioned solve: the batch against the single-instance solver
+    (the same delayed CGS2), iterations within one and solutions within 1e-6 where they
+    converge; where neither converges within maxit (GMRES(3) without a preconditioner) the
+    same iteration count and true residuals within 10 % (the iterates of a stagnating
+    restarted GMRES drift apart with the rounding of the two launch layouts)."""
+    ops = small_ops if pc != "none" else small_ops[:5]
+    insts = SMALL if pc != "none" else SMALL[:5]
+    bs = [op.rhs(inst.f) for op, inst in zip(ops, insts)]
+    maxit = 3000 if pc != "none" else 400
+    xs, rc, infos = sg.gmres_batched(ops, bs, restart=restart, maxit=maxit, pc=pc, precision="f64", tol=1e-7)
+    for op, inst, b, x, info in zip(ops, insts, bs, xs, infos):
+        x1, i1 = op.gmres(b, restart=restart, maxit=maxit, pc=pc, precision="f64", tol=1e-7)
+        print(inst.name, restart, pc, info["iters"], i1["iters"], info["converged"], i1["converged"], flush=True)
+        assert info["converged"] == i1["converged"]
+        assert abs(i1["iters"] - info["iters"]) <= 1, (inst.name, i1["iters"], info["iters"])
+        assert bool(torch.isfinite(torch.view_as_real(x)).all())
+        if info["converged"]:
+            assert float((x - x1).abs().max() / x1.abs().max()) <= 1e-6
+        else:
+            assert abs(info["relres_true"] - i1["relres_true"]) <= 0.1 * i1["relres_true"]
+
+
 @pytest.mark.parametrize("tile", ["128x128", "64x128", "64x64", "64x32", "32x64", "3m32x32", "3m64x32", "3m32x64",
                                   "3m64x64"])
 def test_batched_tile_shapes(small_ops, tile):
