@@ -648,7 +648,7 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
         SG_HIP(hipMemcpy(c->d_k0, p->k_fields, (size_t)P * sizeof(double), hipMemcpyHostToDevice));
         int rc = build_line_factors(c.get(), p->k_fields);
         if (rc) return rc;
-        SG_HIP(hipDeviceSynchronize());
+        SG_HIP(hipStreamSynchronize(nullptr));
         c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         *out = c.release();
         return SG_OK;
@@ -675,7 +675,7 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
             std::vector<double> k0(P, kb);
             rc = build_line_factors(c.get(), k0.data());
             if (rc) return rc;
-            SG_HIP(hipDeviceSynchronize());
+            SG_HIP(hipStreamSynchronize(nullptr));
             c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             *out = c.release();
             return SG_OK;
@@ -694,7 +694,10 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     // transforms' row pieces are whole cache lines
     c->tld = c->dim == 2 ? (n + 7) / 8 * 8 : n;
     SG_HIP(hipMalloc(&c->d_tmp_pc, (c->dim == 2 ? (size_t)c->Q * n * c->tld : (size_t)c->nvec) * sizeof(double2)));
-    SG_HIP(hipDeviceSynchronize());
+    // setup issues only allocations, synchronous copies and null-stream memsets: waiting for
+    // the null stream is enough (a device-wide wait would also wait for solves that other
+    // threads run on their own streams meanwhile)
+    SG_HIP(hipStreamSynchronize(nullptr));
     c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = c.release();
     return SG_OK;
