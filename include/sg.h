@@ -191,14 +191,19 @@ int  sg_precond(sg_handle h, int pc, int precision, const sg_c64* r, sg_c64* z, 
 int  sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
               sg_solve_stats* stats, hipStream_t stream);
 
-/* Orthogonalisation of sg_gmres / sg_fgmres with a built-in preconditioner and restart <= 64:
+/* Orthogonalisation of sg_gmres / sg_fgmres with a built-in preconditioner (restart <= 512):
  * SG_ORTH_DCGS2 (the default), classical Gram-Schmidt with one re-orthogonalisation delayed
  * by one step, so that one pass over the basis re-orthogonalises the previous vector and
  * projects the new one (two passes over the basis per step, one coefficient exchange with
  * the host; the Arnoldi process in the flexible form z_j = P^{-1}u_j, x += Z y);
  * SG_ORTH_CGS2, the same two Gram-Schmidt passes done in the same step (three passes over
- * the basis).  Other solves (callbacks, the learned correction, left preconditioning,
- * restart > 64) always use SG_ORTH_CGS2. */
+ * the basis).  Other solves (callbacks, the learned correction, left preconditioning)
+ * always use SG_ORTH_CGS2.  Beyond 64 basis vectors the delayed form reduces over chunks of
+ * 64 vectors in one launch and updates chunk by chunk (u and w read and written once more
+ * per further chunk).  The delayed form stores each candidate scaled to about unit norm; the
+ * two-pass form keeps its candidates unnormalised (lazy scales), so on a poorly scaled
+ * operator (||A P^{-1}|| >> 1, e.g. no preconditioner) a long cycle can overflow there:
+ * it then stops with SG_ENONFINITE. */
 enum { SG_ORTH_DCGS2 = 0, SG_ORTH_CGS2 = 1 };
 int  sg_set_orthogonalisation(sg_handle h, int kind);
 /* The orthonormal Arnoldi basis v_0..v_{nvec-1} of the last cycle of the handle's last

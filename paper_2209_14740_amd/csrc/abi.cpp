@@ -191,9 +191,13 @@ int sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts,
         Ctx* c = ctx(h);
         if (int rc = guard_device(c)) return rc;
         ProfBind pb(c);
-        if (sgi::dcgs2_serves(c, opts, nullptr) && !c->classic_cgs2)
-            return sgi::run_gmres_dcgs2(c, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), opts,
-                                        stats, stream);
+        if (sgi::dcgs2_serves(c, opts, nullptr) && !c->classic_cgs2) {
+            const int rc = sgi::run_gmres_dcgs2(c, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x),
+                                                opts, stats, stream);
+            // the delayed form keeps a flexible basis (2m+1 vectors); when it does not fit, the
+            // two-pass driver solves with m+1
+            if (rc != SG_ENOMEM) return rc;
+        }
         return sgi::run_gmres(c, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), opts, nullptr,
                               nullptr, false, stats, stream);
     })

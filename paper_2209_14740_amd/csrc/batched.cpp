@@ -281,7 +281,7 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
     const int m = o->restart;
     const int pc = o->precond, prec = o->precision;
     const int RW = 2 * m + 3;        // record words per slot (also holds a cycle end's residual norm)
-    const int SW = 6 * m + 8;        // small device words per slot: red, h1, cv, cw, cu
+    const int SW = 6 * m + 16;       // small device words per slot: red, h1, cv, cw, cu (7)
     std::vector<size_t> need(count);
     size_t largest = 0, total = 0;
     for (int i = 0; i < count; ++i) {
@@ -388,7 +388,7 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
             s.h1 = s.red + RW;                       // m+1
             s.cv = s.h1 + (m + 1);                   // m
             s.cw = s.cv + m;                         // m
-            s.cu = s.cw + m;                         // 2
+            s.cu = s.cw + m;                         // 7
             s.new_cycle(m);
             s.start = true;
             s.st.t_setup = s.c->t_setup_ms;

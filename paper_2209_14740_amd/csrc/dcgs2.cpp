@@ -121,7 +121,7 @@ static int ensure_dcgs(Ctx* c, int m) {
 }
 
 bool dcgs2_serves(const Ctx*, const sg_solve_opts* o, sg_precond_cb cb) {
-    return o && !cb && o->side == 0 && o->restart >= 1 && o->restart <= 64 &&
+    return o && !cb && o->side == 0 && o->restart >= 1 && o->restart <= 512 &&
            (o->precond == SG_PC_NONE || o->precond == SG_PC_MEAN || o->precond == SG_PC_CSL_MEAN);
 }
 
@@ -146,7 +146,7 @@ int run_gmres_dcgs2(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o
     double2* rec = h1 + (m + 1);             // 2m+3
     double2* cv = rec + (2 * m + 3);         // m
     double2* cw = cv + m;                    // m
-    double2* cu = cw + m;                    // 2
+    double2* cu = cw + m;                    // 7: update coefficients and the scale of the candidate
     sg_solve_stats s{};
     Timer tm(c->prof.on && c->prof.mask == ~0u);
     hipEvent_t evs[2] = {nullptr, nullptr};

@@ -383,13 +383,18 @@ __global__ __launch_bounds__(RB) void k_axpby_g(const VecTask* __restrict__ task
 // iteration: all their loads are issued before the first product (each lane still adds its
 // chunks in grid-stride order).
 template <int NVW, int UNR>
+// Chunk form for more than 64 basis vectors: the block covers vectors koff .. koff+nv-1 of
+// the nvt of the step (V points at vector koff) and writes their columns of the partial row;
+// α, β, ω come from the chunk at koff = 0.
 __device__ __forceinline__ void dcgs_reduce_block(long long n, int nv, const double2* __restrict__ V, long long ldv,
                                                   const double2* __restrict__ u, const double2* __restrict__ w,
-                                                  double2* __restrict__ partial, int lb, int nblk) {
+                                                  double2* __restrict__ partial, int lb, int nblk, int nvt = -1,
+                                                  int koff = 0) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool hasw = w != nullptr;
-    const int nout = hasw ? 2 * nv + 3 : nv + 1;
+    if (nvt < 0) nvt = nv;
+    const int nout = hasw ? 2 * nvt + 3 : nvt + 1;
     int nk = 0;
 #pragma unroll
     for (int m = 0; m < NVW; ++m)
@@ -442,25 +447,28 @@ __device__ __forceinline__ void dcgs_reduce_block(long long n, int nv, const dou
             by = wave_sum(cb[m].y);
         }
         if (lane == 0 && m < nk) {
-            out[wv + 4 * m] = make_double2(ax, ay);
-            if (hasw) out[nv + wv + 4 * m] = make_double2(bx, by);
+            out[koff + wv + 4 * m] = make_double2(ax, ay);
+            if (hasw) out[nvt + koff + wv + 4 * m] = make_double2(bx, by);
         }
     }
     const double sx = wave_sum(sc.x), sy = wave_sum(sc.y);
-    if (lane == 0) {
+    if (lane == 0 && koff == 0) {
         if (!hasw) {
-            if (wv == 0) out[nv] = make_double2(sx, 0.0);
+            if (wv == 0) out[nvt] = make_double2(sx, 0.0);
         } else if (wv < 3) {
-            out[2 * nv + wv] = make_double2(sx, wv == 1 ? sy : 0.0);
+            out[2 * nvt + wv] = make_double2(sx, wv == 1 ? sy : 0.0);
         }
     }
 }
 
+// blockIdx.y: chunk of 64 basis vectors
 template <int NVW, int UNR>
 __global__ __launch_bounds__(RB) void k_dcgs_reduce(long long n, int nv, const double2* __restrict__ V, long long ldv,
                                                     const double2* __restrict__ u, const double2* __restrict__ w,
                                                     double2* __restrict__ partial) {
-    dcgs_reduce_block<NVW, UNR>(n, nv, V, ldv, u, w, partial, blockIdx.x, gridDim.x);
+    const int koff = 64 * blockIdx.y;
+    dcgs_reduce_block<NVW, UNR>(n, min(64, nv - koff), V + (long long)koff * ldv, ldv, u, w, partial, blockIdx.x,
+                                gridDim.x, nv, koff);
 }
 
 // One block: the coefficients of step j from the reduced sums red[] (layout of k_dcgs_reduce)
@@ -471,15 +479,27 @@ __global__ __launch_bounds__(RB) void k_dcgs_reduce(long long n, int nv, const d
 // and, for the update pass, cv[k] (v_j = cu_v u_j + Σ cv_k v_k), cw[k] (u_{j+1} = w_j + cu_u u_j +
 // Σ cw_k v_k), cu = (cu_v, cu_u), and h1prev <- h1.  A non-positive ν² gives ν = 0 (breakdown:
 // the host stops the cycle; the update then writes non-finite values into unused slots).
+// Scaling: the candidate u_{j+1} is stored multiplied by s_{j+1} = 1/||u_{j+1}|| as predicted
+// (Pythagoras: ||w_j||² - ||h||²), so that the vectors the preconditioner and the operator
+// see stay of unit size (without it they grow like ||A P^{-1}||^j and overflow in long
+// cycles of a poorly scaled operator).  The flexible relation A z_j = Σ h_ij v_i holds for
+// the z_j actually used, so the coefficients of w_j need no correction; the record carries
+// a and ν of u_j unscaled (divided by s_j, kept in cu[6]; s_0 = 1, the raw residual).
+// Coefficients: cu[0..2] = (1/ν, -h s_{j+1}/ν, s_{j+1}) act on the stored u_j and w_j.
+// kraw > 0 (more than 64 basis vectors, updated in chunks): the chunks below kraw are
+// applied first with the raw coefficients cv_k = -a_k, cw_k = -b_k and cu[3..5] = (1, 0, 1),
+// the last chunk then with the final ones (the algebra of the one-pass update, split).
 __device__ __forceinline__ void dcgs_finalize_block(int j, int full, const double2* __restrict__ red,
                                                     double2* __restrict__ h1prev, double2* __restrict__ rec,
                                                     double2* __restrict__ cv, double2* __restrict__ cw,
-                                                    double2* __restrict__ cu) {
-    __shared__ double s_nu, s_hx, s_hy;
-    __shared__ double red_a[RB / 64], red_bx[RB / 64], red_by[RB / 64];
+                                                    double2* __restrict__ cu, int kraw = 0) {
+    __shared__ double s_nu, s_hx, s_hy, s_next;
+    __shared__ double red_a[RB / 64], red_bx[RB / 64], red_by[RB / 64], red_bb[RB / 64];
     const int t = threadIdx.x;
-    // ||a||² and a^H b over the threads
-    double aa = 0.0, abx = 0.0, aby = 0.0;
+    const double sj = j == 0 ? 1.0 : cu[6].x;   // read before thread 0 rewrites it below
+    const double isj = 1.0 / sj;
+    // ||a||², a^H b and ||b||² over the threads
+    double aa = 0.0, abx = 0.0, aby = 0.0, bb = 0.0;
     for (int k = t; k < j; k += RB) {
         const double2 a = red[k];
         aa = fma(a.x, a.x, fma(a.y, a.y, aa));
@@ -487,45 +507,62 @@ __device__ __forceinline__ void dcgs_finalize_block(int j, int full, const doubl
             const double2 b = red[j + k];
             abx = fma(a.x, b.x, fma(a.y, b.y, abx));   // conj(a) b
             aby = fma(a.x, b.y, fma(-a.y, b.x, aby));
+            bb = fma(b.x, b.x, fma(b.y, b.y, bb));
         }
     }
     aa = wave_sum(aa);
     abx = wave_sum(abx);
     aby = wave_sum(aby);
+    bb = wave_sum(bb);
     if ((t & 63) == 0) {
         red_a[t >> 6] = aa;
         red_bx[t >> 6] = abx;
         red_by[t >> 6] = aby;
+        red_bb[t >> 6] = bb;
     }
     __syncthreads();
     if (t == 0) {
-        double A = 0.0, X = 0.0, Y = 0.0;
+        double A = 0.0, X = 0.0, Y = 0.0, Bq = 0.0;
         for (int q = 0; q < RB / 64; ++q) {
             A += red_a[q];
             X += red_bx[q];
             Y += red_by[q];
+            Bq += red_bb[q];
         }
         const double alpha = full ? red[2 * j].x : red[j].x;
         const double nu2 = alpha - A;
         const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
         s_nu = nu;
+        double snext = 1.0;
         if (full) {
             const double2 beta = red[2 * j + 1];
             s_hx = (beta.x - X) / nu;
             s_hy = (beta.y - Y) / nu;
+            const double omega = red[2 * j + 2].x;
+            const double pred = omega - (s_hx * s_hx + s_hy * s_hy) - Bq;
+            snext = pred > 1e-12 * omega ? 1.0 / sqrt(pred) : (omega > 0.0 ? 1.0 / sqrt(omega) : 1.0);
+            rec[2 * j + 2] = make_double2(nu * isj, pred);
+        } else {
+            rec[2 * j + 2] = make_double2(nu * isj, 0.0);
         }
+        s_next = snext;
     }
     __syncthreads();
-    const double nu = s_nu, inu = 1.0 / nu;
+    const double nu = s_nu, inu = 1.0 / nu, sn = s_next;
     const double hx = full ? s_hx : 0.0, hy = full ? s_hy : 0.0;   // h1_j = v_j^H w_j
     for (int k = t; k < j; k += RB) {
         const double2 a = red[k];
-        rec[k] = make_double2(h1prev[k].x + a.x, h1prev[k].y + a.y);   // completed column j-1
+        rec[k] = make_double2(h1prev[k].x + a.x * isj, h1prev[k].y + a.y * isj);   // completed column j-1
+        if (k < kraw) {
+            cv[k] = make_double2(-a.x, -a.y);
+            if (full) cw[k] = make_double2(-red[j + k].x, -red[j + k].y);
+            continue;
+        }
         cv[k] = make_double2(-a.x * inu, -a.y * inu);
         if (full) {
             const double2 b = red[j + k];
-            // cw_k = -(b_k - h1_j a_k / ν)
-            cw[k] = make_double2(-(b.x - (hx * a.x - hy * a.y) * inu), -(b.y - (hx * a.y + hy * a.x) * inu));
+            // cw_k = -(b_k - h1_j a_k / ν) s_{j+1}
+            cw[k] = make_double2(-(b.x - (hx * a.x - hy * a.y) * inu) * sn, -(b.y - (hx * a.y + hy * a.x) * inu) * sn);
         }
     }
     __syncthreads();   // every h1prev read above precedes the overwrite below
@@ -537,26 +574,26 @@ __device__ __forceinline__ void dcgs_finalize_block(int j, int full, const doubl
         }
     }
     if (t == 0) {
-        rec[j] = make_double2(nu, 0.0);
-        double pred = 0.0;
+        rec[j] = make_double2(nu * isj, 0.0);
         if (full) {
             rec[2 * j + 1] = make_double2(hx, hy);
             h1prev[j] = make_double2(hx, hy);
-            double hh = hx * hx + hy * hy;
-            for (int k = 0; k < j; ++k) hh += red[j + k].x * red[j + k].x + red[j + k].y * red[j + k].y;
-            pred = red[2 * j + 2].x - hh;
+            cu[6] = make_double2(sn, 0.0);
         }
-        rec[2 * j + 2] = make_double2(nu, pred);
         cu[0] = make_double2(inu, 0.0);
-        cu[1] = make_double2(-hx * inu, -hy * inu);
+        cu[1] = make_double2(-hx * inu * sn, -hy * inu * sn);
+        cu[2] = make_double2(sn, 0.0);
+        cu[3] = make_double2(1.0, 0.0);
+        cu[4] = make_double2(0.0, 0.0);
+        cu[5] = make_double2(1.0, 0.0);
     }
 }
 
 __global__ __launch_bounds__(RB) void k_dcgs_finalize(int j, int full, const double2* __restrict__ red,
                                                       double2* __restrict__ h1prev, double2* __restrict__ rec,
                                                       double2* __restrict__ cv, double2* __restrict__ cw,
-                                                      double2* __restrict__ cu) {
-    dcgs_finalize_block(j, full, red, h1prev, rec, cv, cw, cu);
+                                                      double2* __restrict__ cu, int kraw) {
+    dcgs_finalize_block(j, full, red, h1prev, rec, cv, cw, cu, kraw);
 }
 
 // v_j (into u's slot) and u_{j+1} (into w's slot): the wave-split basis of cgs_block, the
@@ -583,6 +620,7 @@ __device__ __forceinline__ void dcgs_update_block(long long n, int nv, const dou
         }
     }
     const double2 cuv = cu[0], cuu = cu[1];
+    const double cww = cu[2].x;
     const long long stride = (long long)nblk * 64;
     int buf = 0;
     for (long long c0 = (long long)lb * 64; c0 < n; c0 += stride * UNR, buf ^= 1) {
@@ -619,8 +657,8 @@ __device__ __forceinline__ void dcgs_update_block(long long n, int nv, const dou
             if (ok[q] && wv < 2) {
                 const long long i = c0 + q * stride + lane;
                 double2 acc = wv == 0 ? make_double2(ui[q].x * cuv.x - ui[q].y * cuv.y, ui[q].x * cuv.y + ui[q].y * cuv.x)
-                                      : make_double2(wi[q].x + ui[q].x * cuu.x - ui[q].y * cuu.y,
-                                                     wi[q].y + ui[q].x * cuu.y + ui[q].y * cuu.x);
+                                      : make_double2(cww * wi[q].x + ui[q].x * cuu.x - ui[q].y * cuu.y,
+                                                     cww * wi[q].y + ui[q].x * cuu.y + ui[q].y * cuu.x);
 #pragma unroll
                 for (int p = 0; p < RB / 64; ++p) {
                     acc.x += part[buf][p][q][wv][lane].x;
@@ -701,19 +739,22 @@ __global__ __launch_bounds__(RB) void k_dcgs_update_g(const DcgsTask* __restrict
 
 int launch_dcgs_reduce(long long n, int nv, const double2* V, long long ldv, const double2* u, const double2* w,
                        double2* partial, int nblocks, double2* red, hipStream_t st) {
+    if (nv > 512) return fail(SG_EINVAL, "delayed CGS2: more than 512 basis vectors");
     const int nout = w ? 2 * nv + 3 : nv + 1;
-    const int nvw = (nv + 3) / 4;
+    const int nchunk = std::max(1, (nv + 63) / 64);   // chunks of 64 basis vectors (grid y)
+    const int nvw = (std::min(nv, 64) + 3) / 4;
     // from four basis vectors per wave on: half the blocks, two chunks per iteration each
     // (measured 5-11 % faster on 36 MB and 351 MB vectors; no gain with one or two)
     const int nb = nvw >= 3 ? std::max(1, nblocks / 2) : nblocks;
     {
-        KScope ks(SG_K_DOT, 16.0 * (nv + (w ? 2 : 1)) * (double)n, st);
+        KScope ks(SG_K_DOT, 16.0 * (nv + (w ? 2 : 1) * nchunk) * (double)n, st);
+        const dim3 grid(nb, nchunk);
 #define SG_DR(NVW_, UNR_)                                                                                         \
     if (nvw <= NVW_) {                                                                                            \
-        hipLaunchKernelGGL((k_dcgs_reduce<NVW_, UNR_>), dim3(nb), dim3(RB), 0, st, n, nv, V, ldv, u, w, partial); \
+        hipLaunchKernelGGL((k_dcgs_reduce<NVW_, UNR_>), grid, dim3(RB), 0, st, n, nv, V, ldv, u, w, partial);     \
     } else
         SG_DR(1, 1) SG_DR(2, 1) SG_DR(4, 2) SG_DR(8, 2) SG_DR(16, 2) {
-            return fail(SG_EINVAL, "delayed CGS2: more than 64 basis vectors");
+            return fail(SG_EINVAL, "delayed CGS2: more than 64 basis vectors per chunk");
         }
 #undef SG_DR
         SG_HIP(hipGetLastError());
@@ -728,25 +769,36 @@ int launch_dcgs_reduce(long long n, int nv, const double2* V, long long ldv, con
 int launch_dcgs_finalize(int j, bool full, const double2* red, double2* h1prev, double2* rec, double2* cv, double2* cw,
                          double2* cu, hipStream_t st) {
     KScope ks(SG_K_NORM, 0.0, st);
-    hipLaunchKernelGGL(k_dcgs_finalize, dim3(1), dim3(RB), 0, st, j, full ? 1 : 0, red, h1prev, rec, cv, cw, cu);
+    const int kraw = j > 64 ? 64 * ((j - 1) / 64) : 0;   // the last chunk's first vector
+    hipLaunchKernelGGL(k_dcgs_finalize, dim3(1), dim3(RB), 0, st, j, full ? 1 : 0, red, h1prev, rec, cv, cw, cu, kraw);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
 
+// cu holds 7 entries (the final triple, the raw triple of the earlier chunks, the scale).
 int launch_dcgs_update(long long n, int nv, const double2* V, long long ldv, double2* u, double2* w, const double2* cv,
                        const double2* cw, const double2* cu, int nblocks, hipStream_t st) {
-    KScope ks(SG_K_AXPY, 16.0 * (nv + 4) * (double)n, st);
-    const int nvw = (nv + 3) / 4;
-    const int nb = nvw >= 3 ? std::max(1, nblocks / 2) : nblocks;   // as in the reduction
+    if (nv > 512) return fail(SG_EINVAL, "delayed CGS2: more than 512 basis vectors");
+    const int nchunk = std::max(1, (nv + 63) / 64);
+    KScope ks(SG_K_AXPY, 16.0 * (nv + 4 * nchunk) * (double)n, st);
+    for (int c = 0; c < nchunk; ++c) {
+        const int koff = 64 * c, nvc = std::min(64, nv - koff);
+        const bool last = c + 1 == nchunk;
+        const double2* cuc = last ? cu : cu + 3;
+        const double2* Vc = V + (long long)koff * ldv;
+        const int nvw = (nvc + 3) / 4;
+        const int nb = nvw >= 3 ? std::max(1, nblocks / 2) : nblocks;   // as in the reduction
 #define SG_DU(NVW_, UNR_)                                                                                        \
     if (nvw <= NVW_) {                                                                                           \
-        hipLaunchKernelGGL((k_dcgs_update<NVW_, UNR_>), dim3(nb), dim3(RB), 0, st, n, nv, V, ldv, u, w, cv, cw, cu); \
+        hipLaunchKernelGGL((k_dcgs_update<NVW_, UNR_>), dim3(nb), dim3(RB), 0, st, n, nvc, Vc, ldv, u, w, cv + koff, \
+                           cw + koff, cuc);                                                                      \
     } else
-    SG_DU(1, 1) SG_DU(2, 1) SG_DU(4, 2) SG_DU(8, 2) SG_DU(16, 2) {
-        return fail(SG_EINVAL, "delayed CGS2: more than 64 basis vectors");
-    }
+        SG_DU(1, 1) SG_DU(2, 1) SG_DU(4, 2) SG_DU(8, 2) SG_DU(16, 2) {
+            return fail(SG_EINVAL, "delayed CGS2: more than 64 basis vectors per chunk");
+        }
 #undef SG_DU
-    SG_HIP(hipGetLastError());
+        SG_HIP(hipGetLastError());
+    }
     return SG_OK;
 }
 

@@ -637,6 +637,39 @@ def test_config3_forms_full_size():
         op.close()
 
 
+@pytest.mark.parametrize("key,restart", [("2d_n37_s2_r4", 200), ("c1_1d", 150)])
+def test_delayed_cgs2_beyond_64_vectors(key, restart):
+    """More than 64 basis vectors in a cycle (reduction over chunks of 64 vectors in one
+    launch, update chunk by chunk), unpreconditioned, so that ||A|| (about 1e4 and 2e5 here)
+    would make unnormalised candidates overflow within a cycle: the delayed CGS2 against the
+    oracle's modified Gram-Schmidt GMRES.  The first cycle runs past 64 vectors, the last
+    cycle's basis is orthonormal to 1e-12, the iteration counts agree within 2 + 1 % (the restarted
+    runs are long: 560 and about 2000 iterations), the solution reaches the 1e-8 true
+    residual (oracle's matrix) and matches the direct solution.  (The two-pass CGS2 driver
+    keeps its candidates unnormalised and stops with SG_ENONFINITE on these runs.)"""
+    inst = SMALL[key]()
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    try:
+        b = op.rhs(inst.f)
+        xd_, id_ = op.gmres(b, restart=restart, maxit=20000, pc="none", tol=1e-8)
+        V = op.last_basis()
+        k = V.shape[0]
+        G = (V.conj() @ V.T).cpu().numpy()
+        orth = float(np.max(np.abs(G - np.eye(k))))
+        _, io = krylov.gmres(lambda v: S.A @ v, S.b, None, restart=restart, tol=1e-8, maxit=20000)
+        print("%s m=%d: dcgs2 %d its (last basis %d, orth %.2e), oracle %d" % (
+            key, restart, id_["iters"], k, orth, io.iters), flush=True)
+        assert id_["converged"] == 1
+        assert min(id_["iters"], restart) > 64   # the first cycle ran past 64 vectors
+        assert k >= 2 and orth <= 1e-12
+        assert abs(id_["iters"] - io.iters) <= 2 + 0.01 * io.iters
+        xd = reference_solution(key, S)
+        _check_solution(S, to_host(xd_), 1e-8, xd)
+    finally:
+        op.close()
+
+
 @pytest.mark.parametrize("key,restart", [("2d_n150_s3_r3", 10), ("2d_n37_s2_r4", 40), ("c1_1d", 30)])
 def test_delayed_cgs2_orthogonality_and_counts(key, restart):
     """Delayed CGS2 (the default) against the two-pass CGS2 of the same step: the Arnoldi
