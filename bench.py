@@ -248,8 +248,16 @@ def batched_pipelined(insts, chunk, threads, log):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ops, iters, rc_all = [], [], 0
+    setup_ms = []
+
+    def timed_setup(inst):
+        ts = time.perf_counter()
+        op = sg.SG.from_instance(inst)
+        setup_ms.append((time.perf_counter() - ts) * 1e3)
+        return op
+
     with cf.ThreadPoolExecutor(max_workers=max(1, threads - 1)) as ex:
-        futs = [ex.submit(sg.SG.from_instance, inst) for inst in insts]
+        futs = [ex.submit(timed_setup, inst) for inst in insts]
         t_wait = t_solve = 0.0
         with torch.cuda.stream(stream):
             for c0 in range(0, len(insts), chunk):
@@ -270,9 +278,11 @@ def batched_pipelined(insts, chunk, threads, log):
     for op in ops:
         op.close()
     log("batched with setup overlapped (%d host threads, chunks of %d): %.3f s (%.1f solves/s), rc %d; "
-        "waiting for setups %.3f s, in the solves %.3f s" % (threads - 1, chunk, t, len(insts) / t, rc_all, t_wait, t_solve))
+        "waiting for setups %.3f s, in the solves %.3f s; one setup %.1f ms median, %.1f ms max"
+        % (threads - 1, chunk, t, len(insts) / t, rc_all, t_wait, t_solve, np.median(setup_ms), np.max(setup_ms)))
     return {"s": t, "solves_per_s": len(insts) / t, "chunk": chunk, "host_threads": threads - 1,
-            "wait_setup_s": t_wait, "solve_s": t_solve,
+            "wait_setup_s": t_wait, "solve_s": t_solve, "setup_ms_median": float(np.median(setup_ms)),
+            "setup_ms_max": float(np.max(setup_ms)),
             "all_converged": bool(rc_all == 0), "iters_mean": float(np.mean(iters))}
 
 

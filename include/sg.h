@@ -122,7 +122,10 @@ typedef struct {
  * (host FP64, validated), then upload to the current device.  *out owns all of it.
  * Shapes: every (s, degree) with Q·66·16 + |Γ₂|·512 <= 160 KiB (|Γ₂| = 1+2s+s(s-1)/2, the
  * LDS tile of the generic operator kernel), and beyond that the shapes with a specialised
- * kernel (2D: s = 3 up to degree 8); any other shape returns SG_EINVAL here. */
+ * kernel (2D: s = 3 up to degree 8); any other shape returns SG_EINVAL here.
+ * The uploads go through a non-blocking stream that the call creates for itself and are
+ * complete when it returns (stream is not used), so setups may run in host threads beside
+ * solves on other streams without waiting for them. */
 int  sg_setup(const sg_problem* prob, hipStream_t stream, sg_handle* out);
 void sg_destroy(sg_handle h);
 

@@ -77,9 +77,7 @@ int sg_rhs(sg_handle h, const double* f_host, sg_c64* b_dev, hipStream_t stream)
         if (!h || !f_host || !b_dev) return fail(SG_EINVAL, "null argument");
         Ctx* c = ctx(h);
         if (int rc = guard_device(c)) return rc;
-        std::vector<double> w(c->P);
-        if (hipMemcpy(w.data(), c->d_w, c->P * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-            return fail(SG_EHIP, "weight download failed");
+        const std::vector<double>& w = c->w_host;
         std::vector<double2> b0(c->P);
         for (long long i = 0; i < c->P; ++i) b0[i] = make_double2(w[i] * f_host[i], 0.0);
         SG_HIP(hipMemsetAsync(b_dev, 0, (size_t)c->nvec * sizeof(double2), stream));

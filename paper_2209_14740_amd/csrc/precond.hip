@@ -17,6 +17,10 @@
 //   F32     A rounded to FP32 on load, v_mfma_f32_16x16x4f32, FP32 accumulation;
 //   BF16X3  A and B split into bf16 hi + lo, C += Ahi·Bhi + Ahi·Blo + Alo·Bhi with
 //           v_mfma_f32_16x16x32_bf16, FP32 accumulation.
+// In the two reduced-precision forms the intermediate of steps (1)-(3) is stored in FP32
+// (the forward transform writes FP32, the sweep runs in FP32 with the FP64 factors rounded
+// as they are loaded, the inverse transform reads FP32): the transforms round their A
+// operand to FP32 in any case, and the sweep and the transforms move half the bytes.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -72,8 +76,9 @@ namespace {
 // One BM×BN output tile (BM = 32·WM, BN = 32·WN) by four waves in a 2×2 layout, each wave
 // owning WM×WN blocks of 16×16.  Global → register prefetch of the next K step overlaps
 // the MFMAs of the current one.
-template <int MODE, int WM, int WN>
+template <int MODE, int WM, int WN, int IO = GEMM_IO_F64>
 __device__ __forceinline__ void gemm_tile(const GemmTask& g, int tile, Lds<MODE, 32 * WM, 32 * WN>& sm) {
+    static_assert(MODE != MODE_F64 || IO == GEMM_IO_F64, "FP64 transforms read and write FP64");
     constexpr int BM = 32 * WM, BN = 32 * WN;
     constexpr int PAD = Lds<MODE, BM, BN>::PAD;
     const double* __restrict__ A = g.A;
@@ -94,7 +99,8 @@ __device__ __forceinline__ void gemm_tile(const GemmTask& g, int tile, Lds<MODE,
 
     // global → register staging: the A tile is BM×32 doubles = 16·BM double2
     constexpr int PA = BM / 16, PB64 = BN / 16, PB32 = BN / 32, PB16 = BN / 64 > 0 ? BN / 64 : 1;
-    double2 ra[PA];
+    using ra_t = typename std::conditional<IO == GEMM_IO_A32, float2, double2>::type;
+    ra_t ra[PA];
     double2 rb64[MODE == MODE_F64 ? PB64 : 1];
     float4 rb32[MODE == MODE_F32 ? PB32 : 1];
     uint4 rbh[PB16], rbl[PB16];
@@ -104,8 +110,13 @@ __device__ __forceinline__ void gemm_tile(const GemmTask& g, int tile, Lds<MODE,
         for (int p = 0; p < PA; ++p) {
             const int idx = p * 256 + tid, row = idx >> 4, k = (idx & 15) * 2;
             const int gm = m0 + row, gk = k0 + k;
-            ra[p] = (gm < M && gk < Kc) ? *reinterpret_cast<const double2*>(A + (long long)gm * lda + gk)
-                                        : make_double2(0.0, 0.0);
+            ra[p] = ra_t{0, 0};
+            if (gm < M && gk < Kc) {
+                if constexpr (IO == GEMM_IO_A32)   // FP32 intermediate
+                    ra[p] = *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(A) + (long long)gm * lda + gk);
+                else
+                    ra[p] = *reinterpret_cast<const double2*>(A + (long long)gm * lda + gk);
+            }
         }
         if constexpr (MODE == MODE_F64) {
             const double* B = reinterpret_cast<const double*>(g.Bt0);
@@ -260,7 +271,12 @@ __device__ __forceinline__ void gemm_tile(const GemmTask& g, int tile, Lds<MODE,
             for (int v = 0; v < 4; ++v) {
                 const int rl = (MODE == MODE_F64) ? (lq + 4 * v) : (lq * 4 + v);
                 const int row = m0 + wm * (16 * WM) + i * 16 + rl;
-                if (row < M) C[(long long)row * ldc + col] = (double)acc[i][j][v];
+                if (row < M) {
+                    if constexpr (IO == GEMM_IO_C32)
+                        reinterpret_cast<float*>(C)[(long long)row * ldc + col] = (float)acc[i][j][v];
+                    else
+                        C[(long long)row * ldc + col] = (double)acc[i][j][v];
+                }
             }
         }
 }
@@ -283,8 +299,9 @@ struct Lds3 {
     e_t br[BN * PAD], bi[BN * PAD];
 };
 
-template <int MODE, int WM, int WN>
+template <int MODE, int WM, int WN, int IO = GEMM_IO_F64>
 __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<MODE, 32 * WM, 32 * WN>& sm) {
+    static_assert(MODE != MODE_F64 || IO == GEMM_IO_F64, "FP64 transforms read and write FP64");
     constexpr int BM = 32 * WM, BN = 32 * WN;
     constexpr int PAD = Lds3<MODE, BM, BN>::PAD;
     using e_t = typename Lds3<MODE, BM, BN>::e_t;
@@ -310,15 +327,22 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<MO
     // staging: A tile BM × BK3 complex (BM·BK3/256 double2 per thread); B planes BN × BK3
     // doubles each, loaded as double2 pairs along k (BN·BK3/512 pairs per thread)
     constexpr int PA = BM * BK3 / 256, PB = BN * BK3 / 512, HK = BK3 / 2;
-    double2 ra[PA];
+    using ra_t = typename std::conditional<IO == GEMM_IO_A32, float2, double2>::type;
+    ra_t ra[PA];
     e2_t rbr[PB], rbi[PB];
     auto load_tiles = [&](int k0) {
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
             const int idx = p * 256 + tid, row = idx / BK3, k = idx % BK3;
             const int gm = m0 + row, gk = k0 + k;
-            ra[p] = (gm < M && gk < K) ? *reinterpret_cast<const double2*>(A + (long long)gm * lda + 2 * gk)
-                                       : make_double2(0.0, 0.0);
+            ra[p] = ra_t{0, 0};
+            if (gm < M && gk < K) {
+                if constexpr (IO == GEMM_IO_A32)   // FP32 intermediate
+                    ra[p] = *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(A) + (long long)gm * lda +
+                                                             2 * gk);
+                else
+                    ra[p] = *reinterpret_cast<const double2*>(A + (long long)gm * lda + 2 * gk);
+            }
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
@@ -405,30 +429,34 @@ __device__ __forceinline__ void gemm3m_tile(const GemmTask& g, int tile, Lds3<MO
                     const double q1 = (double)p1[i][j][v], q2 = (double)p2[i][j][v], q3 = (double)p3[i][j][v];
                     const double re = q1 - q2;
                     const double im = q3 - q1 - q2;
-                    *reinterpret_cast<double2*>(C + (long long)row * g.ldc + 2 * col) = make_double2(re, im);
+                    if constexpr (IO == GEMM_IO_C32)
+                        *reinterpret_cast<float2*>(reinterpret_cast<float*>(C) + (long long)row * g.ldc + 2 * col) =
+                            make_float2((float)re, (float)im);
+                    else
+                        *reinterpret_cast<double2*>(C + (long long)row * g.ldc + 2 * col) = make_double2(re, im);
                 }
             }
         }
 }
 
-template <int MODE, int WM, int WN>
+template <int MODE, int WM, int WN, int IO>
 __global__ __launch_bounds__(256) void k_gemm3m(GemmTask g) {
     __shared__ Lds3<MODE, 32 * WM, 32 * WN> sm;
     const int per = gridDim.x / 8;
     const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= g.tiles_m * g.tiles_n) return;
-    gemm3m_tile<MODE, WM, WN>(g, tile, sm);
+    gemm3m_tile<MODE, WM, WN, IO>(g, tile, sm);
 }
 
 // Single problem; blocks are dispatched round-robin over the 8 XCDs, so the tile index is
 // remapped to give each XCD a contiguous band of tiles (shared A rows and B in its L2).
-template <int MODE, int WM, int WN>
+template <int MODE, int WM, int WN, int IO>
 __global__ __launch_bounds__(256) void k_gemm(GemmTask g) {
     __shared__ Lds<MODE, 32 * WM, 32 * WN> sm;
     const int per = gridDim.x / 8;
     const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= g.tiles_m * g.tiles_n) return;
-    gemm_tile<MODE, WM, WN>(g, tile, sm);
+    gemm_tile<MODE, WM, WN, IO>(g, tile, sm);
 }
 
 // Index of the task owning virtual block v: the largest t with start[t] <= v.
@@ -569,14 +597,36 @@ __device__ __forceinline__ int after(int i, double v) {
 __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {   // a*b + c
     return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
+// The same in FP32, for the sweep over the FP32 intermediate of the reduced-precision forms
+// (the factors stay FP64 in memory and are rounded as they are loaded).
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 csel(bool c, float2 a, float2 b) {
+    return make_float2(c ? a.x : b.x, c ? a.y : b.y);
+}
+__device__ __forceinline__ int after(int i, float v) {
+    asm volatile("" : "+v"(i) : "v"(v));
+    return i;
+}
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
+    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
+template <typename T2>
+__device__ __forceinline__ T2 fac(const double2& v);
+template <>
+__device__ __forceinline__ double2 fac<double2>(const double2& v) { return v; }
+template <>
+__device__ __forceinline__ float2 fac<float2>(const double2& v) { return make_float2((float)v.x, (float)v.y); }
 
 // LDS of the segment joins, one scan round at a time.  The propagators depend on the system
 // only, the carried values also on the right-hand side: the forward scan uses planes 0
 // (propagator) and 1..NR (values), the backward one planes 0..3 (2×2 propagator) and
 // 4..4+2NR-1 (2-vector values).
-template <int NR>
+template <int NR, typename T2>
 struct TriLds {
-    double2 p[4 + 2 * NR][256];
+    T2 p[4 + 2 * NR][256];
 };
 
 // Block → (systems, right-hand sides).  With at least SYS systems per right-hand side a
@@ -590,10 +640,10 @@ __host__ __device__ inline long long tri_blocks(int na, int nq, int K, int NR) {
     return ((long long)na * nq + SYS - 1) / SYS;
 }
 
-template <int SEGL, int NR>
-__device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const TriFactors& f, int len, int na,
+template <int SEGL, int NR, typename T2>
+__device__ __forceinline__ void tri_seg_block(T2* __restrict__ X, const TriFactors& f, int len, int na,
                                               int nq, long long se, long long sa, long long sq, int fa, int blk,
-                                              TriLds<NR>& sm) {
+                                              TriLds<NR, T2>& sm) {
     const int K = f.K, L = f.L, SYS = 256 / K;
     const int tid = threadIdx.x, k = tid / SYS, sl = tid - k * SYS;
     int a, q0;
@@ -611,7 +661,7 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     }
     if (!valid) a = q0 = 0;   // in-range reads; nothing is stored
     bool qok[NR];
-    double2* x[NR];
+    T2* x[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         qok[r] = valid && q0 + r < nq;
@@ -624,10 +674,10 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     const double2* __restrict__ u1p = f.u1p + a * fa;
     const double2* __restrict__ u2p = f.u2p + a * fa;
     const int s0 = k * L, e0 = min(s0 + L, len);
-    const double2 zero = make_double2(0.0, 0.0);
-    const double2 ph = f.phi[(long long)k * fs + a * fa];
+    const T2 zero = T2{0, 0};
+    const T2 ph = fac<T2>(f.phi[(long long)k * fs + a * fa]);
     const uint32_t pm = f.pivm[(long long)k * fs + a * fa];
-    double2 b[NR][SEGL + 1];
+    T2 b[NR][SEGL + 1];
 #pragma unroll
     for (int u = 0; u <= SEGL; ++u) {
         const int i = s0 + u;
@@ -645,29 +695,29 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     auto rdl = [&](int i) { return (long long)min(i, ldl) * fs; };    // row i of dl, clamped
     auto rrow = [&](int i) { return (long long)min(i, lrow) * fs; };  // row i of the others
     // forward, local run (segment 0 starts from b_0, the others from zero)
-    double2 cur[NR];
+    T2 cur[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) cur[r] = csel(k == 0, b[r][0], zero);
-    double2 pl[PF], pd[PF];
+    T2 pl[PF], pd[PF];
 #pragma unroll
-    for (int d = 0; d < PF; ++d) pl[d] = dl[rdl(s0 + d)];
+    for (int d = 0; d < PF; ++d) pl[d] = fac<T2>(dl[rdl(s0 + d)]);
 #pragma unroll
     for (int u = 0; u < SEGL; ++u) {
         const int i = s0 + u;
-        const double2 l = pl[u % PF];
-        if (u + PF < SEGL) pl[u % PF] = dl[rdl(after(s0 + u + PF, cur[0].x))];
+        const T2 l = pl[u % PF];
+        if (u + PF < SEGL) pl[u % PF] = fac<T2>(dl[rdl(after(s0 + u + PF, cur[0].x))]);
         if (i < e0 && i <= len - 2) {
             const bool pv = (pm >> u) & 1u;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                const double2 nb = b[r][u + 1];
+                const T2 nb = b[r][u + 1];
                 cur[r] = csub(csel(pv, cur[r], nb), cmul(l, csel(pv, nb, cur[r])));
             }
         }
     }
     // inclusive scan over the segments of the affine maps c -> φ_k c + t_k (segment 0's
     // map is constant): afterwards T is the exact value leaving segment k
-    double2 P = csel(k == 0, zero, ph), T[NR];
+    T2 P = csel(k == 0, zero, ph), T[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) T[r] = cur[r];
     for (int d = 1; d < K; d <<= 1) {
@@ -676,7 +726,7 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
         for (int r = 0; r < NR; ++r) sm.p[1 + r][tid] = T[r];
         __syncthreads();
         if (k >= d) {
-            const double2 Pp = sm.p[0][tid - d * SYS];
+            const T2 Pp = sm.p[0][tid - d * SYS];
 #pragma unroll
             for (int r = 0; r < NR; ++r) T[r] = cfma(P, sm.p[1 + r][tid - d * SYS], T[r]);
             P = cmul(P, Pp);
@@ -690,23 +740,23 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     for (int r = 0; r < NR; ++r) cur[r] = csel(k == 0, b[r][0], sm.p[1 + r][max(tid - SYS, 0)]);
 #pragma unroll
     for (int d = 0; d < PF; ++d) {
-        pl[d] = dl[rdl(after(s0 + d, cur[0].x))];
-        pd[d] = dinv[rrow(after(s0 + d, cur[0].x))];
+        pl[d] = fac<T2>(dl[rdl(after(s0 + d, cur[0].x))]);
+        pd[d] = fac<T2>(dinv[rrow(after(s0 + d, cur[0].x))]);
     }
 #pragma unroll
     for (int u = 0; u < SEGL; ++u) {
         const int i = s0 + u;
-        const double2 l = pl[u % PF], di = pd[u % PF];
+        const T2 l = pl[u % PF], di = pd[u % PF];
         if (u + PF < SEGL) {
-            pl[u % PF] = dl[rdl(after(s0 + u + PF, cur[0].x))];
-            pd[u % PF] = dinv[rrow(after(s0 + u + PF, cur[0].x))];
+            pl[u % PF] = fac<T2>(dl[rdl(after(s0 + u + PF, cur[0].x))]);
+            pd[u % PF] = fac<T2>(dinv[rrow(after(s0 + u + PF, cur[0].x))]);
         }
         if (i < e0) {
             if (i <= len - 2) {
                 const bool pv = (pm >> u) & 1u;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
-                    const double2 nb = b[r][u + 1];
+                    const T2 nb = b[r][u + 1];
                     b[r][u] = cmul(csel(pv, nb, cur[r]), di);
                     cur[r] = csub(csel(pv, cur[r], nb), cmul(l, csel(pv, nb, cur[r])));
                 }
@@ -718,27 +768,27 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     }
     // backward, local run with a zero entering state
     const double2* ps = f.psi + ((long long)k * fs + a * fa) * 4;
-    double2 M00 = ps[0], M01 = ps[1], M10 = ps[2], M11 = ps[3];
-    double2 x1[NR], x2[NR];
+    T2 M00 = fac<T2>(ps[0]), M01 = fac<T2>(ps[1]), M10 = fac<T2>(ps[2]), M11 = fac<T2>(ps[3]);
+    T2 x1[NR], x2[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) x1[r] = x2[r] = zero;
 #pragma unroll
     for (int d = 0; d < PF; ++d) {
-        pl[d] = u1p[rrow(after(s0 + SEGL - 1 - d, b[0][0].x))];
-        pd[d] = u2p[rrow(after(s0 + SEGL - 1 - d, b[0][0].x))];
+        pl[d] = fac<T2>(u1p[rrow(after(s0 + SEGL - 1 - d, b[0][0].x))]);
+        pd[d] = fac<T2>(u2p[rrow(after(s0 + SEGL - 1 - d, b[0][0].x))]);
     }
 #pragma unroll
     for (int u = SEGL - 1; u >= 0; --u) {
         const int i = s0 + u, slot = (SEGL - 1 - u) % PF;
-        const double2 w1 = pl[slot], w2 = pd[slot];
+        const T2 w1 = pl[slot], w2 = pd[slot];
         if (u - PF >= 0) {
-            pl[slot] = u1p[rrow(after(s0 + u - PF, x1[0].x))];
-            pd[slot] = u2p[rrow(after(s0 + u - PF, x1[0].x))];
+            pl[slot] = fac<T2>(u1p[rrow(after(s0 + u - PF, x1[0].x))]);
+            pd[slot] = fac<T2>(u2p[rrow(after(s0 + u - PF, x1[0].x))]);
         }
         if (i < e0) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                const double2 xi = csub(csub(b[r][u], cmul(w1, x1[r])), cmul(w2, x2[r]));
+                const T2 xi = csub(csub(b[r][u], cmul(w1, x1[r])), cmul(w2, x2[r]));
                 x2[r] = x1[r];
                 x1[r] = xi;
             }
@@ -747,7 +797,7 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     // suffix scan of the affine maps G -> Ψ_k G + g_k (the last segment's map is
     // constant): afterwards (V0, V1) is the exact state at the start of segment k
     if (k == K - 1) M00 = M01 = M10 = M11 = zero;
-    double2 V0[NR], V1[NR];
+    T2 V0[NR], V1[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         V0[r] = x1[r];
@@ -767,15 +817,15 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
         __syncthreads();
         if (k + d < K) {
             const int o = tid + d * SYS;
-            const double2 N00 = sm.p[0][o], N01 = sm.p[1][o], N10 = sm.p[2][o], N11 = sm.p[3][o];
+            const T2 N00 = sm.p[0][o], N01 = sm.p[1][o], N10 = sm.p[2][o], N11 = sm.p[3][o];
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                const double2 W0 = sm.p[4 + 2 * r][o], W1 = sm.p[5 + 2 * r][o];
+                const T2 W0 = sm.p[4 + 2 * r][o], W1 = sm.p[5 + 2 * r][o];
                 V0[r] = cfma(M00, W0, cfma(M01, W1, V0[r]));
                 V1[r] = cfma(M10, W0, cfma(M11, W1, V1[r]));
             }
-            const double2 R00 = cfma(M00, N00, cmul(M01, N10)), R01 = cfma(M00, N01, cmul(M01, N11));
-            const double2 R10 = cfma(M10, N00, cmul(M11, N10)), R11 = cfma(M10, N01, cmul(M11, N11));
+            const T2 R00 = cfma(M00, N00, cmul(M01, N10)), R01 = cfma(M00, N01, cmul(M01, N11));
+            const T2 R10 = cfma(M10, N00, cmul(M11, N10)), R11 = cfma(M10, N01, cmul(M11, N11));
             M00 = R00; M01 = R01; M10 = R10; M11 = R11;
         }
         __syncthreads();
@@ -794,21 +844,21 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
     }
 #pragma unroll
     for (int d = 0; d < PF; ++d) {
-        pl[d] = u1p[rrow(after(s0 + SEGL - 1 - d, x1[0].x))];
-        pd[d] = u2p[rrow(after(s0 + SEGL - 1 - d, x1[0].x))];
+        pl[d] = fac<T2>(u1p[rrow(after(s0 + SEGL - 1 - d, x1[0].x))]);
+        pd[d] = fac<T2>(u2p[rrow(after(s0 + SEGL - 1 - d, x1[0].x))]);
     }
 #pragma unroll
     for (int u = SEGL - 1; u >= 0; --u) {
         const int i = s0 + u, slot = (SEGL - 1 - u) % PF;
-        const double2 w1 = pl[slot], w2 = pd[slot];
+        const T2 w1 = pl[slot], w2 = pd[slot];
         if (u - PF >= 0) {
-            pl[slot] = u1p[rrow(after(s0 + u - PF, x1[0].x))];
-            pd[slot] = u2p[rrow(after(s0 + u - PF, x1[0].x))];
+            pl[slot] = fac<T2>(u1p[rrow(after(s0 + u - PF, x1[0].x))]);
+            pd[slot] = fac<T2>(u2p[rrow(after(s0 + u - PF, x1[0].x))]);
         }
         if (i < e0) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                const double2 xi = csub(csub(b[r][u], cmul(w1, x1[r])), cmul(w2, x2[r]));
+                const T2 xi = csub(csub(b[r][u], cmul(w1, x1[r])), cmul(w2, x2[r]));
                 if (qok[r]) x[r][(long long)i * se] = xi;
                 x2[r] = x1[r];
                 x1[r] = xi;
@@ -819,26 +869,26 @@ __device__ __forceinline__ void tri_seg_block(double2* __restrict__ X, const Tri
 
 // One block of 256 threads per SYS systems (× NR right-hand sides); the XCD remap keeps
 // consecutive virtual blocks (the right-hand sides of one set of systems) on one XCD.
-template <int SEGL, int NR>
-__global__ __launch_bounds__(256) void k_tri_seg(double2* __restrict__ X, TriFactors f, int len, int na, int nq,
+template <int SEGL, int NR, typename T2>
+__global__ __launch_bounds__(256) void k_tri_seg(T2* __restrict__ X, TriFactors f, int len, int na, int nq,
                                                  long long se, long long sa, long long sq, int fa, int total) {
-    __shared__ TriLds<NR> sm;
+    __shared__ TriLds<NR, T2> sm;
     const int per = gridDim.x / 8;
     const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (v >= total) return;
-    tri_seg_block<SEGL, NR>(X, f, len, na, nq, se, sa, sq, fa, v, sm);
+    tri_seg_block<SEGL, NR, T2>(X, f, len, na, nq, se, sa, sq, fa, v, sm);
 }
 
 template <int SEGL, int NR>
 __global__ __launch_bounds__(256) void k_tri_seg_grouped(const TriTask* __restrict__ tasks,
                                                          const int* __restrict__ start, int ntask, int total) {
-    __shared__ TriLds<NR> sm;
+    __shared__ TriLds<NR, double2> sm;
     const int per = gridDim.x / 8;
     const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (v >= total) return;
     const int t = find_task(start, ntask, v);
     const TriTask& g = tasks[t];
-    tri_seg_block<SEGL, NR>(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], sm);
+    tri_seg_block<SEGL, NR, double2>(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], sm);
 }
 
 static inline uint16_t host_bf16(float f) {
@@ -885,9 +935,9 @@ static int upload_planes(DenseB& d, int N, const std::vector<cplx>& B, int ld) {
     std::vector<float> hf(h.size());
     for (size_t i = 0; i < h.size(); ++i) hf[i] = (float)h[i];
     SG_HIP(hipMalloc(&d.p3, h.size() * sizeof(double)));
-    SG_HIP(hipMemcpy(d.p3, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (int rc_ = upload(d.p3, h.data(), h.size() * sizeof(double))) return rc_;
     SG_HIP(hipMalloc(&d.p3f, hf.size() * sizeof(float)));
-    SG_HIP(hipMemcpy(d.p3f, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (int rc_ = upload(d.p3f, hf.data(), hf.size() * sizeof(float))) return rc_;
     return SG_OK;
 }
 
@@ -904,10 +954,10 @@ static int upload_one(DenseB& d, const std::vector<double>& e) {
     SG_HIP(hipMalloc(&d.f32, cnt * sizeof(float)));
     SG_HIP(hipMalloc(&d.bf_hi, cnt * sizeof(uint16_t)));
     SG_HIP(hipMalloc(&d.bf_lo, cnt * sizeof(uint16_t)));
-    SG_HIP(hipMemcpy(d.f64, e.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(d.f32, f32.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(d.bf_hi, hi.data(), cnt * sizeof(uint16_t), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(d.bf_lo, lo.data(), cnt * sizeof(uint16_t), hipMemcpyHostToDevice));
+    if (int rc_ = upload(d.f64, e.data(), cnt * sizeof(double))) return rc_;
+    if (int rc_ = upload(d.f32, f32.data(), cnt * sizeof(float))) return rc_;
+    if (int rc_ = upload(d.bf_hi, hi.data(), cnt * sizeof(uint16_t))) return rc_;
+    if (int rc_ = upload(d.bf_lo, lo.data(), cnt * sizeof(uint16_t))) return rc_;
     return SG_OK;
 }
 
@@ -964,6 +1014,26 @@ GemmTask make_gemm_task(int precision, const double* A, long long lda, const Den
     return g;
 }
 
+// One transform, with the element types of A and C that g.io names (the FP32 intermediate
+// exists only in the reduced-precision forms).
+template <int MODE, int WM, int WN, bool M3>
+static void launch_single(const GemmTask& g, dim3 grid, hipStream_t st) {
+    if constexpr (MODE != MODE_F64) {
+        if (g.io == GEMM_IO_C32) {
+            if constexpr (M3) hipLaunchKernelGGL((k_gemm3m<MODE, WM, WN, GEMM_IO_C32>), grid, dim3(256), 0, st, g);
+            else hipLaunchKernelGGL((k_gemm<MODE, WM, WN, GEMM_IO_C32>), grid, dim3(256), 0, st, g);
+            return;
+        }
+        if (g.io == GEMM_IO_A32) {
+            if constexpr (M3) hipLaunchKernelGGL((k_gemm3m<MODE, WM, WN, GEMM_IO_A32>), grid, dim3(256), 0, st, g);
+            else hipLaunchKernelGGL((k_gemm<MODE, WM, WN, GEMM_IO_A32>), grid, dim3(256), 0, st, g);
+            return;
+        }
+    }
+    if constexpr (M3) hipLaunchKernelGGL((k_gemm3m<MODE, WM, WN, GEMM_IO_F64>), grid, dim3(256), 0, st, g);
+    else hipLaunchKernelGGL((k_gemm<MODE, WM, WN, GEMM_IO_F64>), grid, dim3(256), 0, st, g);
+}
+
 template <int MODE>
 static void launch_gemm_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks, const int* d_start, int ntask,
                             int total, hipStream_t st) {
@@ -972,7 +1042,7 @@ static void launch_gemm_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks,
 #define SG_GEMM_CFG(C_, WM_, WN_)                                                                          \
     case C_:                                                                                               \
         if (d_tasks) hipLaunchKernelGGL((k_gemm_grouped<MODE, WM_, WN_>), grid, blk, 0, st, d_tasks, d_start, ntask, total); \
-        else hipLaunchKernelGGL((k_gemm<MODE, WM_, WN_>), grid, blk, 0, st, g);                              \
+        else launch_single<MODE, WM_, WN_, false>(g, grid, st);                                              \
         break;
     switch (cfg) {
         SG_GEMM_CFG(0, 4, 4)
@@ -1000,7 +1070,7 @@ static void launch_gemm3m_cfg(int cfg, const GemmTask& g, const GemmTask* d_task
 #define SG_GEMM3(C_, WM_, WN_)                                                                              \
     case C_:                                                                                                \
         if (d_tasks) hipLaunchKernelGGL((k_gemm3m_grouped<MODE, WM_, WN_>), grid, blk, 0, st, d_tasks, d_start, ntask, total); \
-        else hipLaunchKernelGGL((k_gemm3m<MODE, WM_, WN_>), grid, blk, 0, st, g);                                    \
+        else launch_single<MODE, WM_, WN_, true>(g, grid, st);                                               \
         break;
     switch (cfg) {
         SG_GEMM3(5, 1, 1)
@@ -1047,9 +1117,10 @@ int gemm_cfg_for(int N, int M, int precision) {
 }
 
 static int launch_gemm(int precision, const double* A, long long lda, const DenseB& B, int N, double* C,
-                       long long ldc, int M, hipStream_t st) {
+                       long long ldc, int M, int io, hipStream_t st) {
     const int cfg = gemm_cfg_for(N, M, precision);
-    const GemmTask g = make_gemm_task(precision, A, lda, B, N, C, ldc, M, cfg);
+    GemmTask g = make_gemm_task(precision, A, lda, B, N, C, ldc, M, cfg);
+    g.io = io;
     // algorithmic flops: 8 real flops per complex multiply-add, 6 with the 3M form
     const double cmacs = (double)M * N * N;
     KScope ks(SG_K_GEMM, (gemm_cfg_3m(cfg) ? 6.0 : 8.0) * cmacs, st);
@@ -1067,6 +1138,10 @@ int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const i
 // at least two right-hand sides and segments of at most 8 rows (both in registers).
 bool tri_nr_ok(const TriFactors& f, int n, int Q, int dim) {
     return dim == 2 && f.K >= 1 && n >= 256 / f.K && Q >= 2 && f.L <= 8;
+}
+// In FP32 the rows of two right-hand sides fit in registers up to 16-row segments.
+static bool tri_nr_ok32(const TriFactors& f, int n, int Q, int dim) {
+    return dim == 2 && f.K >= 1 && n >= 256 / f.K && Q >= 2 && f.L <= 16;
 }
 
 TriTask make_tri_task(const TriFactors& f, double2* X, int n, int ld, int Q, int dim, int nr) {
@@ -1101,7 +1176,9 @@ int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, in
     return SG_OK;
 }
 
-static int launch_tri(const TriFactors& f, double2* X, int n, int ld, int Q, int dim, hipStream_t st) {
+// X holds double2 elements, or float2 ones when f32 (the FP32 intermediate of the
+// reduced-precision forms, which only the segmented kernel serves).
+static int launch_tri(const TriFactors& f, void* X, bool f32, int n, int ld, int Q, int dim, hipStream_t st) {
     int na, nq, fa;
     long long se, sa, sq;
     if (dim == 2) {
@@ -1112,30 +1189,41 @@ static int launch_tri(const TriFactors& f, double2* X, int n, int ld, int Q, int
     const long long nth = (long long)na * nq;
     const int blk = 64;
     // algorithmic: every element read and written once, factors read once
-    KScope ks(SG_K_TRI, 32.0 * na * (double)nq * n + 65.0 * f.nsys * (double)n, st);
+    KScope ks(SG_K_TRI, (f32 ? 16.0 : 32.0) * na * (double)nq * n + 65.0 * f.nsys * (double)n, st);
     if (f.L <= 32 && f.K >= 1) {
         // two right-hand sides per thread where the blocks hold whole sets of systems and the
-        // segments are short enough for both to stay in registers (8 rows: 166 registers;
-        // 16 rows would spill)
-        const int nr = tri_nr_ok(f, n, Q, dim) ? 2 : 1;
+        // segments are short enough for both to stay in registers (FP64, 8 rows: 166
+        // registers; 16 rows would spill)
+        const int nr = (f32 ? tri_nr_ok32(f, n, Q, dim) : tri_nr_ok(f, n, Q, dim)) ? 2 : 1;
         const long long total = tri_blocks(na, nq, f.K, nr);
         if (total > INT32_MAX - 8) return fail(SG_EINVAL, "grid too large for the tridiagonal sweep");
         const dim3 grid((unsigned)((total + 7) / 8 * 8));
-#define SG_TRI(SEGL_, NR_) \
-    hipLaunchKernelGGL((k_tri_seg<SEGL_, NR_>), grid, dim3(256), 0, st, X, f, n, na, nq, se, sa, sq, fa, (int)total)
-        if (nr == 2) {
-            SG_TRI(8, 2);
+#define SG_TRI(SEGL_, NR_, T2_)                                                                                    \
+    hipLaunchKernelGGL((k_tri_seg<SEGL_, NR_, T2_>), grid, dim3(256), 0, st, static_cast<T2_*>(X), f, n, na, nq, se, \
+                       sa, sq, fa, (int)total)
+        if (f32) {
+            if (nr == 2) {
+                if (f.L <= 8) SG_TRI(8, 2, float2);
+                else SG_TRI(16, 2, float2);
+            } else {
+                if (f.L <= 8) SG_TRI(8, 1, float2);
+                else if (f.L <= 16) SG_TRI(16, 1, float2);
+                else SG_TRI(32, 1, float2);
+            }
+        } else if (nr == 2) {
+            SG_TRI(8, 2, double2);
         } else {
-            if (f.L <= 8) SG_TRI(8, 1);
-            else if (f.L <= 16) SG_TRI(16, 1);
-            else SG_TRI(32, 1);
+            if (f.L <= 8) SG_TRI(8, 1, double2);
+            else if (f.L <= 16) SG_TRI(16, 1, double2);
+            else SG_TRI(32, 1, double2);
         }
 #undef SG_TRI
         SG_HIP(hipGetLastError());
         return SG_OK;
     }
-    hipLaunchKernelGGL(k_tri, dim3((unsigned)((nth + blk - 1) / blk)), dim3(blk), 0, st, X, f, n, na, nq, se, sa,
-                       sq, fa);
+    if (f32) return fail(SG_EINVAL, "internal: the FP32 sweep needs the segmented factors");
+    hipLaunchKernelGGL(k_tri, dim3((unsigned)((nth + blk - 1) / blk)), dim3(blk), 0, st, static_cast<double2*>(X), f,
+                       n, na, nq, se, sa, sq, fa);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
@@ -1156,17 +1244,20 @@ int launch_precond(Ctx* c, int pc, int precision, const double2* r, double2* z, 
     const int n = c->n;
     if (c->dim == 1) {
         if (r != z) SG_HIP(hipMemcpyAsync(z, r, (size_t)c->nvec * sizeof(double2), hipMemcpyDeviceToDevice, st));
-        return launch_tri(f, z, n, n, c->Q, 1, st);
+        return launch_tri(f, z, false, n, n, c->Q, 1, st);
     }
     const int M = c->Q * n;
     double2* t = c->d_tmp_pc;
+    // The reduced-precision forms keep the intermediate W (transform output, sweep, transform
+    // input) in FP32: the transforms round it to FP32 anyway, and half the bytes move.
+    const bool t32 = precision != SG_PREC_F64 && f.L <= 32 && f.K >= 1;
     int rc = launch_gemm(precision, reinterpret_cast<const double*>(r), n, c->fwd, n, reinterpret_cast<double*>(t),
-                         c->tld, M, st);
+                         c->tld, M, t32 ? GEMM_IO_C32 : GEMM_IO_F64, st);
     if (rc) return rc;
-    rc = launch_tri(f, t, n, c->tld, c->Q, 2, st);
+    rc = launch_tri(f, t, t32, n, c->tld, c->Q, 2, st);
     if (rc) return rc;
     return launch_gemm(precision, reinterpret_cast<const double*>(t), c->tld, c->inv, n, reinterpret_cast<double*>(z),
-                       n, M, st);
+                       n, M, t32 ? GEMM_IO_A32 : GEMM_IO_F64, st);
 }
 
 }  // namespace sgi

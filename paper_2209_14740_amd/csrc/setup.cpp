@@ -433,22 +433,22 @@ static int build_tri(int n, double h, double kbar, const std::vector<cplx>& sig,
     SG_HIP(hipMalloc(&tf.u2p, hu2p.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.phi, hphi.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.psi, hpsi.size() * sizeof(double2)));
-    SG_HIP(hipMemcpy(tf.u1p, hu1p.data(), hu1p.size() * sizeof(double2), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(tf.u2p, hu2p.data(), hu2p.size() * sizeof(double2), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(tf.phi, hphi.data(), hphi.size() * sizeof(double2), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(tf.psi, hpsi.data(), hpsi.size() * sizeof(double2), hipMemcpyHostToDevice));
+    if (int rc_ = upload(tf.u1p, hu1p.data(), hu1p.size() * sizeof(double2))) return rc_;
+    if (int rc_ = upload(tf.u2p, hu2p.data(), hu2p.size() * sizeof(double2))) return rc_;
+    if (int rc_ = upload(tf.phi, hphi.data(), hphi.size() * sizeof(double2))) return rc_;
+    if (int rc_ = upload(tf.psi, hpsi.data(), hpsi.size() * sizeof(double2))) return rc_;
     SG_HIP(hipMalloc(&tf.pivm, hpm.size() * sizeof(uint32_t)));
-    SG_HIP(hipMemcpy(tf.pivm, hpm.data(), hpm.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (int rc_ = upload(tf.pivm, hpm.data(), hpm.size() * sizeof(uint32_t))) return rc_;
     SG_HIP(hipMalloc(&tf.dl, hdl.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.dinv, hdi.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.du1, hu1.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.du2, hu2.size() * sizeof(double2)));
     SG_HIP(hipMalloc(&tf.piv, hp.size()));
-    SG_HIP(hipMemcpy(tf.dl, hdl.data(), hdl.size() * sizeof(double2), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(tf.dinv, hdi.data(), hdi.size() * sizeof(double2), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(tf.du1, hu1.data(), hu1.size() * sizeof(double2), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(tf.du2, hu2.data(), hu2.size() * sizeof(double2), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(tf.piv, hp.data(), hp.size(), hipMemcpyHostToDevice));
+    if (int rc_ = upload(tf.dl, hdl.data(), hdl.size() * sizeof(double2))) return rc_;
+    if (int rc_ = upload(tf.dinv, hdi.data(), hdi.size() * sizeof(double2))) return rc_;
+    if (int rc_ = upload(tf.du1, hu1.data(), hu1.size() * sizeof(double2))) return rc_;
+    if (int rc_ = upload(tf.du2, hu2.data(), hu2.size() * sizeof(double2))) return rc_;
+    if (int rc_ = upload(tf.piv, hp.data(), hp.size())) return rc_;
     return SG_OK;
 }
 
@@ -510,8 +510,38 @@ static std::atomic<double> g_eigen_cond_limit{1e4};
 double eigen_cond_limit() { return g_eigen_cond_limit.load(); }
 void set_eigen_cond_limit(double v) { g_eigen_cond_limit.store(v); }
 
+static thread_local hipStream_t t_setup_stream = nullptr;
+
+SetupStream::SetupStream() {
+    rc = SG_OK;
+    if (hipStreamCreateWithFlags(&t_setup_stream, hipStreamNonBlocking) != hipSuccess) {
+        t_setup_stream = nullptr;
+        rc = fail(SG_EHIP, "could not create the setup stream");
+    }
+}
+SetupStream::~SetupStream() {
+    if (t_setup_stream) (void)hipStreamDestroy(t_setup_stream);
+    t_setup_stream = nullptr;
+}
+
+int upload(void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return SG_OK;
+    SG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, t_setup_stream));
+    SG_HIP(hipStreamSynchronize(t_setup_stream));   // src may be freed when this returns
+    return SG_OK;
+}
+
+int upload_zero(void* dst, size_t bytes) {
+    if (bytes == 0) return SG_OK;
+    SG_HIP(hipMemsetAsync(dst, 0, bytes, t_setup_stream));
+    SG_HIP(hipStreamSynchronize(t_setup_stream));
+    return SG_OK;
+}
+
 int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     auto t0 = std::chrono::steady_clock::now();
+    SetupStream setup_stream;
+    if (setup_stream.rc) return setup_stream.rc;
     if (!p || !out) return fail(SG_EINVAL, "null argument");
     if (p->dim != 1 && p->dim != 2) return fail(SG_EINVAL, "dim must be 1 or 2");
     if (p->bc != SG_BC_ABSORBING) return fail(SG_EINVAL, "only absorbing boundary conditions are supported");
@@ -634,21 +664,21 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     SG_HIP(hipMalloc(&c->d_prog, prog.size() * sizeof(int)));
     SG_HIP(hipMalloc(&c->d_vals, std::max<size_t>(vals.size(), 1) * sizeof(double)));
     SG_HIP(hipMalloc(&c->d_w, w.size() * sizeof(double)));
-    SG_HIP(hipMemcpy(c->d_D2, D2.data(), D2.size() * sizeof(double), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(c->d_D1, D1.data(), D1.size() * sizeof(double), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(c->d_prog, prog.data(), prog.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (int rc_ = upload(c->d_D2, D2.data(), D2.size() * sizeof(double))) return rc_;
+    if (int rc_ = upload(c->d_D1, D1.data(), D1.size() * sizeof(double))) return rc_;
+    if (int rc_ = upload(c->d_prog, prog.data(), prog.size() * sizeof(int))) return rc_;
     if (!vals.empty())
-        SG_HIP(hipMemcpy(c->d_vals, vals.data(), vals.size() * sizeof(double), hipMemcpyHostToDevice));
-    SG_HIP(hipMemcpy(c->d_w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (int rc_ = upload(c->d_vals, vals.data(), vals.size() * sizeof(double))) return rc_;
+    if (int rc_ = upload(c->d_w, w.data(), w.size() * sizeof(double))) return rc_;
+    c->w_host = w;
     SG_HIP(hipMalloc(&c->d_kf, (size_t)s * P * sizeof(double)));
-    SG_HIP(hipMemcpy(c->d_kf, p->k_fields + P, (size_t)s * P * sizeof(double), hipMemcpyHostToDevice));
+    if (int rc_ = upload(c->d_kf, p->k_fields + P, (size_t)s * P * sizeof(double))) return rc_;
 
     if (c->vmean) {
         SG_HIP(hipMalloc(&c->d_k0, (size_t)P * sizeof(double)));
-        SG_HIP(hipMemcpy(c->d_k0, p->k_fields, (size_t)P * sizeof(double), hipMemcpyHostToDevice));
+        if (int rc_ = upload(c->d_k0, p->k_fields, (size_t)P * sizeof(double))) return rc_;
         int rc = build_line_factors(c.get(), p->k_fields);
         if (rc) return rc;
-        SG_HIP(hipStreamSynchronize(nullptr));
         c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         *out = c.release();
         return SG_OK;
@@ -675,7 +705,6 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
             std::vector<double> k0(P, kb);
             rc = build_line_factors(c.get(), k0.data());
             if (rc) return rc;
-            SG_HIP(hipStreamSynchronize(nullptr));
             c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             *out = c.release();
             return SG_OK;
@@ -694,10 +723,6 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     // transforms' row pieces are whole cache lines
     c->tld = c->dim == 2 ? (n + 7) / 8 * 8 : n;
     SG_HIP(hipMalloc(&c->d_tmp_pc, (c->dim == 2 ? (size_t)c->Q * n * c->tld : (size_t)c->nvec) * sizeof(double2)));
-    // setup issues only allocations, synchronous copies and null-stream memsets: waiting for
-    // the null stream is enough (a device-wide wait would also wait for solves that other
-    // threads run on their own streams meanwhile)
-    SG_HIP(hipStreamSynchronize(nullptr));
     c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = c.release();
     return SG_OK;

@@ -26,6 +26,18 @@ int fail(int code, const std::string& msg);
             return ::sgi::fail(SG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Host→device uploads of a setup.  They go through a non-blocking stream that SetupStream
+// creates for the calling thread's setup (the null stream outside one) and each is complete
+// when the call returns, so a setup neither queues behind nor waits for solves that other
+// threads run meanwhile (synchronous copies on the null stream can do both).
+struct SetupStream {
+    SetupStream();
+    ~SetupStream();
+    int rc;   // SG_OK, or the error of creating the stream
+};
+int upload(void* dst, const void* src, size_t bytes);
+int upload_zero(void* dst, size_t bytes);
+
 // Coupling program of the matrix-free operator.  For output block i the pairs
 // [pair_ptr[i], pair_ptr[i+1]) list the input blocks j with a nonzero coupling; pair p
 // owns terms [term_ptr[p], term_ptr[p+1]) = (field index γ, triple-product value G_γ[i,j]).
@@ -76,7 +88,13 @@ struct GemmTask {
     double* C;
     long long lda, ldb, ldc;
     int M, Nc, Kc, tiles_m, tiles_n;
+    // element types of A and C in the FP32 and BF16x3 forms (FP64 ignores it): GEMM_IO_F64
+    // both FP64; GEMM_IO_C32 C stored as FP32 (the forward transform into the FP32
+    // intermediate); GEMM_IO_A32 A read as FP32 (the inverse transform out of it).  A and C
+    // keep their FP64 pointer types; lda and ldc count elements of the stored type.
+    int io = 0;
 };
+enum { GEMM_IO_F64 = 0, GEMM_IO_C32 = 1, GEMM_IO_A32 = 2 };
 // GEMM tile shapes: the expanded real form (BM × BN real columns, every precision) 0:
 // 128×128, 1: 64×128, 2: 64×64, 3: 64×32, 4: 32×64, 9: 64×256, 10: 128×256 (FP32 / BF16x3);
 // the 3M complex form (BM × BN complex columns, FP64 and FP32) 5: 32×32, 6: 64×32, 7: 32×64,
@@ -212,6 +230,7 @@ struct Ctx {
     int kvals_off = 0, bvals_off = 0;
     int out_order_off = 0;             // output block order (load balance)
     double* d_w = nullptr;             // node weights w (n^dim)
+    std::vector<double> w_host;        // the same on the host (right-hand sides)
     double* d_kf = nullptr;            // k_1..k_s at the nodes ([s][P])
 
     // mean-block fast diagonalisation (x direction) and y-direction tridiagonal factors
