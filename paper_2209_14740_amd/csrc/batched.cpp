@@ -338,6 +338,12 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
     if (pc == SG_PC_NONE) tri_nr = 1;
     for (int i = 0; i < count && tri_nr == 2; ++i)
         if (!tri_nr_ok(ctx[i]->tri[pc == SG_PC_MEAN ? 0 : 1], ctx[i]->n, ctx[i]->Q, ctx[i]->dim)) tri_nr = 1;
+    // the reduced-precision forms keep the 2D transform intermediate in FP32, as sg_precond does
+    const bool t32 = prec != SG_PREC_F64;
+    int tri_nr32 = pc == SG_PC_NONE ? 1 : 2;
+    for (int i = 0; i < count && tri_nr32 == 2; ++i)
+        if (ctx[i]->dim == 2 && !tri_nr_ok32(ctx[i]->tri[pc == SG_PC_MEAN ? 0 : 1], ctx[i]->n, ctx[i]->Q, 2))
+            tri_nr32 = 1;
     hipEvent_t step_done = nullptr;
     SG_HIP(hipEventCreateWithFlags(&step_done, hipEventDisableTiming));
     struct FreeE {
@@ -351,7 +357,7 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
     Group<VecTask> g_copy, g_lin, g_pcopy, g_xupd, g_res, g_norm, g_nred;
     Group<ApplyArgs> g_apply;
     std::map<std::pair<int, int>, Group<ApplyArgs>> g_spec;
-    Group<TriTask> g_tri;
+    Group<TriTask> g_tri, g_tri32;
     std::vector<Group<GemmTask>> g_fwd(SG_GEMM_NCFG), g_inv(SG_GEMM_NCFG);
     Group<DcgsTask> g_dred, g_dsum, g_dfin, g_dupd;
     std::vector<double2> y_tab((size_t)S * (m + 1));
@@ -412,6 +418,7 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
         g_apply.clear();
         for (auto& kv : g_spec) kv.second.clear();
         g_tri.clear();
+        g_tri32.clear();
         for (auto& gg : g_fwd) gg.clear();
         for (auto& gg : g_inv) gg.clear();
         for (auto* gp : {&g_dred, &g_dsum, &g_dfin, &g_dupd}) gp->clear();
@@ -520,11 +527,13 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
                                                      reinterpret_cast<double*>(c->d_tmp_pc), c->tld, M, cfg);
                         GemmTask gi = make_gemm_task(prec, reinterpret_cast<const double*>(c->d_tmp_pc), c->tld, c->inv,
                                                      c->n, reinterpret_cast<double*>(zj), c->n, M, cfg);
+                        gf.io = t32 ? GEMM_IO_C32 : GEMM_IO_F64;
+                        gi.io = t32 ? GEMM_IO_A32 : GEMM_IO_F64;
                         const double fl = (gemm_cfg_3m(cfg) ? 6.0 : 8.0) * M * (double)c->n * c->n;
                         g_fwd[cfg].add(gf, gf.tiles_m * gf.tiles_n, fl);
                         g_inv[cfg].add(gi, gi.tiles_m * gi.tiles_n, fl);
-                        TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->tld, c->Q, 2, tri_nr);
-                        g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
+                        TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->tld, c->Q, 2, t32 ? tri_nr32 : tri_nr);
+                        (t32 ? g_tri32 : g_tri).add(tt, tt.nblocks, (t32 ? 16.0 : 32.0) * n + 65.0 * f.nsys * c->n);
                     }
                 }
                 add_apply(c, zj, uj + n);
@@ -554,6 +563,7 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
         stg.put_group(g_apply);
         for (auto& kv : g_spec) stg.put_group(kv.second);
         stg.put_group(g_tri);
+        stg.put_group(g_tri32);
         for (auto& gg : g_fwd) stg.put_group(gg);
         for (auto& gg : g_inv) stg.put_group(gg);
         for (auto* gp : {&g_dred, &g_dsum, &g_dfin, &g_dupd}) stg.put_group(*gp);
@@ -572,17 +582,23 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
                                        g_pcopy.work, stream)))
             return rc;
         for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg)
-            if ((rc = launch_gemm_grouped(prec, cfg, stg.dtasks(g_fwd[cfg]), stg.dstart(g_fwd[cfg]), g_fwd[cfg].n(),
-                                          g_fwd[cfg].total(), g_fwd[cfg].work, stream)))
+            if ((rc = launch_gemm_grouped(prec, cfg, t32 ? GEMM_IO_C32 : GEMM_IO_F64, stg.dtasks(g_fwd[cfg]),
+                                          stg.dstart(g_fwd[cfg]), g_fwd[cfg].n(), g_fwd[cfg].total(), g_fwd[cfg].work,
+                                          stream)))
                 return rc;
-        int max_seg = 0;
+        int max_seg = 0, max_seg32 = 0;
         for (const TriTask& tt : g_tri.tasks) max_seg = std::max(max_seg, tt.f.L);
+        for (const TriTask& tt : g_tri32.tasks) max_seg32 = std::max(max_seg32, tt.f.L);
         if ((rc = launch_tri_grouped(stg.dtasks(g_tri), stg.dstart(g_tri), g_tri.n(), g_tri.total(), max_seg, tri_nr,
-                                     g_tri.work, stream)))
+                                     false, g_tri.work, stream)))
+            return rc;
+        if ((rc = launch_tri_grouped(stg.dtasks(g_tri32), stg.dstart(g_tri32), g_tri32.n(), g_tri32.total(), max_seg32,
+                                     tri_nr32, true, g_tri32.work, stream)))
             return rc;
         for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg)
-            if ((rc = launch_gemm_grouped(prec, cfg, stg.dtasks(g_inv[cfg]), stg.dstart(g_inv[cfg]), g_inv[cfg].n(),
-                                          g_inv[cfg].total(), g_inv[cfg].work, stream)))
+            if ((rc = launch_gemm_grouped(prec, cfg, t32 ? GEMM_IO_A32 : GEMM_IO_F64, stg.dtasks(g_inv[cfg]),
+                                          stg.dstart(g_inv[cfg]), g_inv[cfg].n(), g_inv[cfg].total(), g_inv[cfg].work,
+                                          stream)))
                 return rc;
         if ((rc = launch_axpby_grouped(stg.dtasks(g_xupd), stg.dstart(g_xupd), g_xupd.n(), g_xupd.total(), g_xupd.work,
                                        stream)))
@@ -823,6 +839,12 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
     if (pc == SG_PC_NONE) tri_nr = 1;
     for (int i = 0; i < count && tri_nr == 2; ++i)
         if (!tri_nr_ok(ctx[i]->tri[pc == SG_PC_MEAN ? 0 : 1], ctx[i]->n, ctx[i]->Q, ctx[i]->dim)) tri_nr = 1;
+    // the reduced-precision forms keep the 2D transform intermediate in FP32, as sg_precond does
+    const bool t32 = prec != SG_PREC_F64;
+    int tri_nr32 = pc == SG_PC_NONE ? 1 : 2;
+    for (int i = 0; i < count && tri_nr32 == 2; ++i)
+        if (ctx[i]->dim == 2 && !tri_nr_ok32(ctx[i]->tri[pc == SG_PC_MEAN ? 0 : 1], ctx[i]->n, ctx[i]->Q, 2))
+            tri_nr32 = 1;
     hipEvent_t step_done = nullptr;   // the host polls it at the end of every lockstep step
     SG_HIP(hipEventCreateWithFlags(&step_done, hipEventDisableTiming));
     struct FreeE {
@@ -838,7 +860,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
     Group<VecTask> g_copy, g_lin, g_xupd, g_res, g_mdot, g_red1, g_upd1, g_red2, g_updn, g_redn, g_pcopy;
     Group<ApplyArgs> g_apply;                                  // generic operator
     std::map<std::pair<int, int>, Group<ApplyArgs>> g_spec;   // shape-specialised operator per (s, r)
-    Group<TriTask> g_tri;
+    Group<TriTask> g_tri, g_tri32;
     std::vector<Group<GemmTask>> g_fwd(SG_GEMM_NCFG), g_inv(SG_GEMM_NCFG);
     std::vector<double> hscale_tab((size_t)S * (m + 2), 1.0);
     std::vector<double2> y_tab((size_t)S * (m + 1));
@@ -901,6 +923,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         g_apply.clear();
         for (auto& kv : g_spec) kv.second.clear();
         g_tri.clear();
+        g_tri32.clear();
         for (auto& gg : g_fwd) gg.clear();
         for (auto& gg : g_inv) gg.clear();
         stg.reset();
@@ -984,11 +1007,13 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                                              reinterpret_cast<double*>(c->d_tmp_pc), c->tld, M, cfg);
                 GemmTask gi = make_gemm_task(prec, reinterpret_cast<const double*>(c->d_tmp_pc), c->tld, c->inv, c->n,
                                              reinterpret_cast<double*>(s.zt), c->n, M, cfg);
+                gf.io = t32 ? GEMM_IO_C32 : GEMM_IO_F64;
+                gi.io = t32 ? GEMM_IO_A32 : GEMM_IO_F64;
                 const double fl = (gemm_cfg_3m(cfg) ? 6.0 : 8.0) * M * (double)c->n * c->n;
                 g_fwd[cfg].add(gf, gf.tiles_m * gf.tiles_n, fl);
                 g_inv[cfg].add(gi, gi.tiles_m * gi.tiles_n, fl);
-                TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->tld, c->Q, 2, tri_nr);
-                g_tri.add(tt, tt.nblocks, 32.0 * n + 65.0 * f.nsys * c->n);
+                TriTask tt = make_tri_task(f, c->d_tmp_pc, c->n, c->tld, c->Q, 2, t32 ? tri_nr32 : tri_nr);
+                (t32 ? g_tri32 : g_tri).add(tt, tt.nblocks, (t32 ? 16.0 : 32.0) * n + 65.0 * f.nsys * c->n);
             }
         }
         size_t lds = 0;
@@ -1074,6 +1099,7 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
         stg.put_group(g_apply);
         for (auto& kv : g_spec) stg.put_group(kv.second);
         stg.put_group(g_tri);
+        stg.put_group(g_tri32);
         for (auto& gg : g_fwd) stg.put_group(gg);
         for (auto& gg : g_inv) stg.put_group(gg);
         if (stg.used > stg.cap || stg.dev != dev_before) return fail(SG_EINVAL, "batched solve: staging overflow");
@@ -1091,17 +1117,23 @@ int run_gmres_batched(int count, Ctx* const* ctx, const double2* const* b, doubl
                                        g_pcopy.work, stream)))
             return rc;
         for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg)
-            if ((rc = launch_gemm_grouped(prec, cfg, stg.dtasks(g_fwd[cfg]), stg.dstart(g_fwd[cfg]), g_fwd[cfg].n(),
-                                          g_fwd[cfg].total(), g_fwd[cfg].work, stream)))
+            if ((rc = launch_gemm_grouped(prec, cfg, t32 ? GEMM_IO_C32 : GEMM_IO_F64, stg.dtasks(g_fwd[cfg]),
+                                          stg.dstart(g_fwd[cfg]), g_fwd[cfg].n(), g_fwd[cfg].total(), g_fwd[cfg].work,
+                                          stream)))
                 return rc;
-        int max_seg = 0;
+        int max_seg = 0, max_seg32 = 0;
         for (const TriTask& tt : g_tri.tasks) max_seg = std::max(max_seg, tt.f.L);
+        for (const TriTask& tt : g_tri32.tasks) max_seg32 = std::max(max_seg32, tt.f.L);
         if ((rc = launch_tri_grouped(stg.dtasks(g_tri), stg.dstart(g_tri), g_tri.n(), g_tri.total(), max_seg, tri_nr,
-                                     g_tri.work, stream)))
+                                     false, g_tri.work, stream)))
+            return rc;
+        if ((rc = launch_tri_grouped(stg.dtasks(g_tri32), stg.dstart(g_tri32), g_tri32.n(), g_tri32.total(), max_seg32,
+                                     tri_nr32, true, g_tri32.work, stream)))
             return rc;
         for (int cfg = 0; cfg < SG_GEMM_NCFG; ++cfg)
-            if ((rc = launch_gemm_grouped(prec, cfg, stg.dtasks(g_inv[cfg]), stg.dstart(g_inv[cfg]), g_inv[cfg].n(),
-                                          g_inv[cfg].total(), g_inv[cfg].work, stream)))
+            if ((rc = launch_gemm_grouped(prec, cfg, t32 ? GEMM_IO_A32 : GEMM_IO_F64, stg.dtasks(g_inv[cfg]),
+                                          stg.dstart(g_inv[cfg]), g_inv[cfg].n(), g_inv[cfg].total(), g_inv[cfg].work,
+                                          stream)))
                 return rc;
         if ((rc = launch_axpby_grouped(stg.dtasks(g_xupd), stg.dstart(g_xupd), g_xupd.n(), g_xupd.total(), g_xupd.work,
                                        stream)))
@@ -1367,16 +1399,22 @@ int autotune(int count, Ctx* const* ctx, int precision, int reps, double* ms_out
                 double* tmp = reinterpret_cast<double*>(hs[g]->d_tmp_pc);
                 tasks[g] = make_gemm_task(precision, io, n, hs[g]->fwd, n, tmp, hs[g]->tld, Q * n, cfg);
                 tasks[G + g] = make_gemm_task(precision, tmp, hs[g]->tld, hs[g]->inv, n, io, n, Q * n, cfg);
+                if (precision != SG_PREC_F64) {   // the FP32 intermediate of the reduced-precision forms
+                    tasks[g].io = GEMM_IO_C32;
+                    tasks[G + g].io = GEMM_IO_A32;
+                }
                 start[g + 1] = start[g] + tasks[g].tiles_m * tasks[g].tiles_n;
                 start[G + 1 + g + 1] = start[G + 1 + g] + tasks[G + g].tiles_m * tasks[G + g].tiles_n;
             }
             SG_HIP(hipMemcpyAsync(d_tasks, tasks.data(), 2 * G * sizeof(GemmTask), hipMemcpyHostToDevice, stream));
             SG_HIP(hipMemcpyAsync(d_start, start.data(), 2 * (G + 1) * sizeof(int), hipMemcpyHostToDevice, stream));
             auto both = [&]() {
-                int rc = launch_gemm_grouped(precision, cfg, d_tasks, d_start, G, start[G], 0.0, stream);
+                const bool r32 = precision != SG_PREC_F64;
+                int rc = launch_gemm_grouped(precision, cfg, r32 ? GEMM_IO_C32 : GEMM_IO_F64, d_tasks, d_start, G,
+                                             start[G], 0.0, stream);
                 if (rc) return rc;
-                return launch_gemm_grouped(precision, cfg, d_tasks + G, d_start + G + 1, G, start[2 * G + 1], 0.0,
-                                           stream);
+                return launch_gemm_grouped(precision, cfg, r32 ? GEMM_IO_A32 : GEMM_IO_F64, d_tasks + G,
+                                           d_start + G + 1, G, start[2 * G + 1], 0.0, stream);
             };
             int rc = both();
             if (rc) return rc;

@@ -472,7 +472,8 @@ __device__ __forceinline__ int find_task(const int* __restrict__ start, int ntas
 
 // Many problems in one launch: task t owns tiles [start[t], start[t+1]) of the
 // concatenated tile list; the XCD remap keeps each problem's tiles on few XCDs.
-template <int MODE, int WM, int WN>
+// (IO: the element types of A and C, the same for every task of one launch.)
+template <int MODE, int WM, int WN, int IO>
 __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict__ tasks,
                                                       const int* __restrict__ start, int ntask, int total) {
     __shared__ Lds<MODE, 32 * WM, 32 * WN> sm;
@@ -481,10 +482,10 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
     if (v >= total) return;
     const int t = find_task(start, ntask, v);
     const GemmTask g = tasks[t];
-    gemm_tile<MODE, WM, WN>(g, v - start[t], sm);
+    gemm_tile<MODE, WM, WN, IO>(g, v - start[t], sm);
 }
 
-template <int MODE, int WM, int WN>
+template <int MODE, int WM, int WN, int IO>
 __global__ __launch_bounds__(256) void k_gemm3m_grouped(const GemmTask* __restrict__ tasks,
                                                         const int* __restrict__ start, int ntask, int total) {
     __shared__ Lds3<MODE, 32 * WM, 32 * WN> sm;
@@ -493,7 +494,7 @@ __global__ __launch_bounds__(256) void k_gemm3m_grouped(const GemmTask* __restri
     if (v >= total) return;
     const int t = find_task(start, ntask, v);
     const GemmTask g = tasks[t];
-    gemm3m_tile<MODE, WM, WN>(g, v - start[t], sm);
+    gemm3m_tile<MODE, WM, WN, IO>(g, v - start[t], sm);
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -879,16 +880,18 @@ __global__ __launch_bounds__(256) void k_tri_seg(T2* __restrict__ X, TriFactors 
     tri_seg_block<SEGL, NR, T2>(X, f, len, na, nq, se, sa, sq, fa, v, sm);
 }
 
-template <int SEGL, int NR>
+// (T2: float2 when every task's X is an FP32 intermediate.)
+template <int SEGL, int NR, typename T2>
 __global__ __launch_bounds__(256) void k_tri_seg_grouped(const TriTask* __restrict__ tasks,
                                                          const int* __restrict__ start, int ntask, int total) {
-    __shared__ TriLds<NR, double2> sm;
+    __shared__ TriLds<NR, T2> sm;
     const int per = gridDim.x / 8;
     const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (v >= total) return;
     const int t = find_task(start, ntask, v);
     const TriTask& g = tasks[t];
-    tri_seg_block<SEGL, NR, double2>(g.X, g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa, v - start[t], sm);
+    tri_seg_block<SEGL, NR, T2>(reinterpret_cast<T2*>(g.X), g.f, g.len, g.na, g.nq, g.se, g.sa, g.sq, g.fa,
+                                v - start[t], sm);
 }
 
 static inline uint16_t host_bf16(float f) {
@@ -1034,6 +1037,27 @@ static void launch_single(const GemmTask& g, dim3 grid, hipStream_t st) {
     else hipLaunchKernelGGL((k_gemm<MODE, WM, WN, GEMM_IO_F64>), grid, dim3(256), 0, st, g);
 }
 
+// Many transforms of one tile shape and one pair of element types (io) in one launch.
+template <int MODE, int WM, int WN, bool M3>
+static void launch_grouped(int io, dim3 grid, hipStream_t st, const GemmTask* d_tasks, const int* d_start, int ntask,
+                           int total) {
+#define SG_GROUPED(IO_)                                                                                         \
+    do {                                                                                                        \
+        if constexpr (M3)                                                                                       \
+            hipLaunchKernelGGL((k_gemm3m_grouped<MODE, WM, WN, IO_>), grid, dim3(256), 0, st, d_tasks, d_start,   \
+                               ntask, total);                                                                   \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_gemm_grouped<MODE, WM, WN, IO_>), grid, dim3(256), 0, st, d_tasks, d_start,     \
+                               ntask, total);                                                                   \
+    } while (0)
+    if constexpr (MODE != MODE_F64) {
+        if (io == GEMM_IO_C32) { SG_GROUPED(GEMM_IO_C32); return; }
+        if (io == GEMM_IO_A32) { SG_GROUPED(GEMM_IO_A32); return; }
+    }
+    SG_GROUPED(GEMM_IO_F64);
+#undef SG_GROUPED
+}
+
 template <int MODE>
 static void launch_gemm_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks, const int* d_start, int ntask,
                             int total, hipStream_t st) {
@@ -1041,7 +1065,7 @@ static void launch_gemm_cfg(int cfg, const GemmTask& g, const GemmTask* d_tasks,
     const dim3 grid(((nt + 7) / 8) * 8), blk(256);
 #define SG_GEMM_CFG(C_, WM_, WN_)                                                                          \
     case C_:                                                                                               \
-        if (d_tasks) hipLaunchKernelGGL((k_gemm_grouped<MODE, WM_, WN_>), grid, blk, 0, st, d_tasks, d_start, ntask, total); \
+        if (d_tasks) launch_grouped<MODE, WM_, WN_, false>(g.io, grid, st, d_tasks, d_start, ntask, total);  \
         else launch_single<MODE, WM_, WN_, false>(g, grid, st);                                              \
         break;
     switch (cfg) {
@@ -1069,7 +1093,7 @@ static void launch_gemm3m_cfg(int cfg, const GemmTask& g, const GemmTask* d_task
     const dim3 grid(((nt + 7) / 8) * 8), blk(256);
 #define SG_GEMM3(C_, WM_, WN_)                                                                              \
     case C_:                                                                                                \
-        if (d_tasks) hipLaunchKernelGGL((k_gemm3m_grouped<MODE, WM_, WN_>), grid, blk, 0, st, d_tasks, d_start, ntask, total); \
+        if (d_tasks) launch_grouped<MODE, WM_, WN_, true>(g.io, grid, st, d_tasks, d_start, ntask, total);   \
         else launch_single<MODE, WM_, WN_, true>(g, grid, st);                                               \
         break;
     switch (cfg) {
@@ -1127,11 +1151,14 @@ static int launch_gemm(int precision, const double* A, long long lda, const Dens
     return dispatch_gemm(precision, cfg, g, nullptr, nullptr, 0, 0, st);
 }
 
-int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const int* d_start, int ntask, int total,
-                        double flops, hipStream_t st) {
+int launch_gemm_grouped(int precision, int cfg, int io, const GemmTask* d_tasks, const int* d_start, int ntask,
+                        int total, double flops, hipStream_t st) {
     if (ntask <= 0 || total <= 0) return SG_OK;
+    if (precision == SG_PREC_F64 && io != GEMM_IO_F64) return fail(SG_EINVAL, "FP64 transforms read and write FP64");
     KScope ks(SG_K_GEMM, flops, st);
-    return dispatch_gemm(precision, cfg, GemmTask{}, d_tasks, d_start, ntask, total, st);
+    GemmTask g{};
+    g.io = io;
+    return dispatch_gemm(precision, cfg, g, d_tasks, d_start, ntask, total, st);
 }
 
 // Two right-hand sides per thread need whole sets of systems per block (2D, n >= 256/K),
@@ -1140,7 +1167,7 @@ bool tri_nr_ok(const TriFactors& f, int n, int Q, int dim) {
     return dim == 2 && f.K >= 1 && n >= 256 / f.K && Q >= 2 && f.L <= 8;
 }
 // In FP32 the rows of two right-hand sides fit in registers up to 16-row segments.
-static bool tri_nr_ok32(const TriFactors& f, int n, int Q, int dim) {
+bool tri_nr_ok32(const TriFactors& f, int n, int Q, int dim) {
     return dim == 2 && f.K >= 1 && n >= 256 / f.K && Q >= 2 && f.L <= 16;
 }
 
@@ -1159,18 +1186,26 @@ TriTask make_tri_task(const TriFactors& f, double2* X, int n, int ld, int Q, int
 }
 
 int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, int max_seg, int nr,
-                       double bytes, hipStream_t st) {
+                       bool f32, double bytes, hipStream_t st) {
     if (ntask <= 0 || total <= 0) return SG_OK;
     if (max_seg > 32) return fail(SG_EINVAL, "grid too large for the grouped tridiagonal sweep");
-    if (nr == 2 && max_seg > 8) return fail(SG_EINVAL, "two right-hand sides per thread need segments of <= 8 rows");
+    if (nr == 2 && max_seg > (f32 ? 16 : 8))
+        return fail(SG_EINVAL, "two right-hand sides per thread need segments of <= 8 rows (16 in FP32)");
     KScope ks(SG_K_TRI, bytes, st);
     const dim3 grid((unsigned)((total + 7) / 8 * 8));
-#define SG_TRIG(SEGL_, NR_) \
-    hipLaunchKernelGGL((k_tri_seg_grouped<SEGL_, NR_>), grid, dim3(256), 0, st, d_tasks, d_start, ntask, total)
-    if (nr == 2) SG_TRIG(8, 2);
-    else if (max_seg <= 8) SG_TRIG(8, 1);
-    else if (max_seg <= 16) SG_TRIG(16, 1);
-    else SG_TRIG(32, 1);
+#define SG_TRIG(SEGL_, NR_, T2_) \
+    hipLaunchKernelGGL((k_tri_seg_grouped<SEGL_, NR_, T2_>), grid, dim3(256), 0, st, d_tasks, d_start, ntask, total)
+    if (f32) {
+        if (nr == 2) {
+            if (max_seg <= 8) SG_TRIG(8, 2, float2);
+            else SG_TRIG(16, 2, float2);
+        } else if (max_seg <= 8) SG_TRIG(8, 1, float2);
+        else if (max_seg <= 16) SG_TRIG(16, 1, float2);
+        else SG_TRIG(32, 1, float2);
+    } else if (nr == 2) SG_TRIG(8, 2, double2);
+    else if (max_seg <= 8) SG_TRIG(8, 1, double2);
+    else if (max_seg <= 16) SG_TRIG(16, 1, double2);
+    else SG_TRIG(32, 1, double2);
 #undef SG_TRIG
     SG_HIP(hipGetLastError());
     return SG_OK;

@@ -296,14 +296,17 @@ int gemm_cfg_for(int N, int M, int precision);
 // lda, ldc: row lengths of A and C in complex elements
 GemmTask make_gemm_task(int precision, const double* A, long long lda, const DenseB& B, int N, double* C,
                         long long ldc, int M, int cfg);
-int launch_gemm_grouped(int precision, int cfg, const GemmTask* d_tasks, const int* d_start, int ntask, int total,
-                        double flops, hipStream_t st);
+// io: GEMM_IO_*, the same for every task of the launch
+int launch_gemm_grouped(int precision, int cfg, int io, const GemmTask* d_tasks, const int* d_start, int ntask,
+                        int total, double flops, hipStream_t st);
 // ld: row length of X in complex elements (2D; the 1D layout is contiguous); nr: right-hand
 // sides per thread (2 only where tri_nr_ok holds), the same for every task of one launch
 TriTask make_tri_task(const TriFactors& f, double2* X, int n, int ld, int Q, int dim, int nr = 1);
 bool tri_nr_ok(const TriFactors& f, int n, int Q, int dim);
+bool tri_nr_ok32(const TriFactors& f, int n, int Q, int dim);   // the same for an FP32 intermediate
+// f32: every task's X is an FP32 (float2) intermediate
 int launch_tri_grouped(const TriTask* d_tasks, const int* d_start, int ntask, int total, int max_seg, int nr,
-                       double bytes, hipStream_t st);
+                       bool f32, double bytes, hipStream_t st);
 
 // krylov.hip
 int ensure_workspace(Ctx* c, int m, bool flexible);
