@@ -35,7 +35,7 @@ KIND = {0: "sg_apply", 1: "fd_gemm", 2: "tri_sweep", 3: "cgs2_multidot", 4: "cgs
 # scaled by the same counters on a copy kernel of known size.  Valid only for the kernel
 # source it was measured on (sha256 of the file below) and the tile shape the autotuner
 # chose then; otherwise reported as null.
-TRAFFIC = {"fd_gemm": {"bytes": 82.79e6, "file": "precond.hip", "src": "3443120cf9be8071", "tile": 5}}
+TRAFFIC = {"fd_gemm": {"bytes": 82.81e6, "file": "precond.hip", "src": "97723ed64cf9b425", "tile": 5}}
 
 
 def _src_hash(name):
@@ -127,7 +127,7 @@ def matvec_bandwidth(inst, reps):
     return out
 
 
-def batched_config4(count, log):
+def batched_config4(count, log, one_at_a_time=True):
     """Batched form: `count` seeded instances (N∈{63,127,255}, Q∈{3..70}) solved by one
     sg_gmres_batched call (A_0-GMRES(30) to 1e-8, FP64 outer, FP32 preconditioner,
     autotuned GEMM tiles).  Setup (host eigenfactors + uploads) runs in host threads and
@@ -194,7 +194,7 @@ def batched_config4(count, log):
     # memory together).  The batched solver's cached arena is handed back first.
     sg.batched_release()
     t_seq = [0.0, 0.0]
-    for w0 in range(0, count, 64):
+    for w0 in range(0, count if one_at_a_time else 0, 64):
         win = list(zip(ops, bs, xs))[w0:w0 + 64]
         for k in range(2):
             torch.cuda.synchronize()
@@ -205,8 +205,11 @@ def batched_config4(count, log):
             t_seq[k] += time.perf_counter() - t0
         for op, _, _ in win:
             op.close()
-    log("one at a time: %.3f s with workspace allocation, %.3f s steady (%.1f solves/s)"
-        % (t_seq[0], t_seq[1], count / t_seq[1]))
+    if one_at_a_time:
+        log("one at a time: %.3f s with workspace allocation, %.3f s steady (%.1f solves/s)"
+            % (t_seq[0], t_seq[1], count / t_seq[1]))
+    else:   # kernel-trace runs: the batch legs only
+        t_seq = [float("nan")] * 2
     its = np.array([i["iters"] for i in infos])
     rel = np.array([i["relres_true"] for i in infos])
     out = {"workload": "%d seeded instances, N in {63,127,255}, kbar~U[5,30], sigma=0.1 kbar, s in 1..4, "
@@ -644,6 +647,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one elementwise copy kernel of 1 GiB in and 1 GiB out first (HBM counter "
                          "calibration under rocprofv3 --pmc)")
+    ap.add_argument("--batched-no-single", action="store_true",
+                    help="with --batched-only: skip the one-at-a-time comparison (kernel-trace runs of the "
+                         "batch legs alone)")
     ap.add_argument("--learned-pairs", type=int, default=8192)
     ap.add_argument("--learned-eval", type=int, default=64)
     ap.add_argument("--learned-only", action="store_true",
@@ -677,7 +683,7 @@ def main():
         print(json.dumps({"degree_sweep": degree_sweep(log)}))
         return
     if args.batched_only:
-        print(json.dumps({"batched": batched_config4(args.batched_count, log)}))
+        print(json.dumps({"batched": batched_config4(args.batched_count, log, not args.batched_no_single)}))
         return
     if args.learned_only:
         print(json.dumps({"learned": learned_config5(args.learned_pairs, args.learned_eval, log)}))
