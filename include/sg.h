@@ -183,9 +183,11 @@ int  sg_set_operator_shift(sg_handle h, double beta);
 
 /* z = P^{-1} r for P = A_0 or M_0 (pc = SG_PC_MEAN / SG_PC_CSL_MEAN) by fast
  * diagonalisation of the mean block (Section 5; Section 6.3 block reuse), in the given
- * precision; SG_PC_NONE copies.  With a spatially varying mean (k_mean = 0 at setup) the
- * block solve is the line block LU, FP64 only (another precision: SG_EINVAL).  r and z may
- * alias. */
+ * precision; SG_PC_NONE copies.  SG_PREC_F32 / SG_PREC_BF16X3 (2D): the transforms in that
+ * precision with FP32 accumulation, their intermediate and the tridiagonal sweep in FP32
+ * (the factors are FP64 and rounded as they are read); r and z stay FP64.  1D: the sweep is
+ * FP64 in every precision.  With a spatially varying mean (k_mean = 0 at setup) the block
+ * solve is the line block LU, FP64 only (another precision: SG_EINVAL).  r and z may alias. */
 int  sg_precond(sg_handle h, int pc, int precision, const sg_c64* r, sg_c64* z, hipStream_t stream);
 
 /* Restarted GMRES(m), right-preconditioned (eq. preconditioned_2d) or, with opts->side = 1,
