@@ -213,6 +213,7 @@ def test_apply_parity_small(key):
     y = to_host(op.apply(to_dev(x)))
     ref = S.A @ x
     bound = abs(S.A) @ np.abs(x)
+    print("apply parity", key, "max err / row bound %.2e" % np.max(np.abs(y - ref) / bound), flush=True)
     assert np.all(np.abs(y - ref) <= 1e-12 * bound + 1e-300), np.max(np.abs(y - ref) / bound)
 
 
@@ -242,6 +243,7 @@ def test_apply_parity_full_size_sampled(which):
     pts = np.array(sorted(pts))
     ref = assemble.apply_at_points(inst, x, pts)
     scale = np.max(np.abs(ref))
+    print("apply full", which, "max err / max row %.2e" % (np.max(np.abs(y[:, pts] - ref)) / scale), flush=True)
     assert np.max(np.abs(y[:, pts] - ref)) <= 1e-12 * scale
 
 
@@ -258,6 +260,7 @@ def test_precond_parity_f64(key, pc):
     ref = P(r)
     z = to_host(op.precond(to_dev(r), pc=pc, precision="f64"))
     err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+    print("precond f64", key, pc, "rel err %.2e" % err, flush=True)
     assert err <= 1e-9, err
 
 
@@ -343,6 +346,9 @@ def test_cgs2_parity():
     wd = to_dev(w)
     h = sg.cgs2(to_dev(V), wd)
     out = to_host(wd)
+    print("cgs2: coefficients %.2e, norm %.2e (of |w|), unit norm %.2e, orthogonality %.2e" % (
+        np.max(np.abs(h[:nv] - ref_h)) / np.linalg.norm(w), abs(h[nv] - np.linalg.norm(wperp)) / np.linalg.norm(w),
+        abs(np.linalg.norm(out) - 1.0), np.max(np.abs(V.conj() @ out))), flush=True)
     assert np.max(np.abs(h[:nv] - ref_h)) <= 1e-13 * np.linalg.norm(w)
     assert abs(h[nv] - np.linalg.norm(wperp)) <= 1e-13 * np.linalg.norm(w)
     assert abs(np.linalg.norm(out) - 1.0) <= 1e-14
@@ -373,9 +379,11 @@ def test_norm_parity():
 
 def _check_solution(S, x, tol, xd=None):
     relres = np.linalg.norm(S.b - S.A @ x) / np.linalg.norm(S.b)
+    print("solution: true relres %.2e (tol %.0e)" % (relres, tol), flush=True)
     assert relres <= tol * 1.0000001, relres
     if xd is not None:
         err = np.max(np.abs(x - xd)) / np.max(np.abs(xd))
+        print("solution: max rel err vs oracle %.2e" % err, flush=True)
         assert err <= 1e-6, err
 
 
@@ -597,6 +605,7 @@ def test_precond_f64_tile_shapes(key, tile):
         ref = precond.mean_value(S)(r)
         z = to_host(op.precond(to_dev(r), pc="mean", precision="f64"))
         err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+        print("f64 tile", key, tile, "rel err %.2e" % err, flush=True)
         assert err <= 1e-9, err
     finally:
         sg.tune_set(op.n, op.Q, "f64", "128x128")
