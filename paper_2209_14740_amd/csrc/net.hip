@@ -119,19 +119,20 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, in
     }
 }
 
-// 3×3 convolution with the input tile in LDS.  The block's CONV_PIX pixels (row-major from
-// P0; 4 waves × CONV_NF fragments of 16) with their one-pixel halo are staged once per
+// 3×3 convolution with the input tile in LDS.  The block's PIX = 64·NF pixels (row-major
+// from P0; 4 waves × NF fragments of 16) with their one-pixel halo are staged once per
 // 32-channel chunk: rows r0-1 .. r1+1 and, when the pixels lie in one row, the columns
-// x0-1 .. x0+CONV_PIX, else whole rows -1 .. W (out of the image: zeros).  The nine taps
-// then read their operands from LDS instead of re-reading the input from the caches nine
-// times.  (Four fragments per wave measured slower: 50 KB of LDS leaves three blocks per
-// CU.)  Output as in k_conv.
-constexpr int CONV_NF = 2, CONV_PIX = 64 * CONV_NF;
+// x0-1 .. x0+PIX, else whole rows -1 .. W (out of the image: zeros).  The nine taps then
+// read their operands from LDS instead of re-reading the input from the caches nine times.
+// NF and the output channels per block (16·NC) are chosen per layer by the launcher: the
+// coarse tiles (NF = 2) for the large layers, the fine ones where the coarse grid would
+// leave CUs idle (the 128² and 64² levels at batch 1).  (Four fragments per wave measured
+// slower: 50 KB of LDS leaves three blocks per CU.)  Output as in k_conv.
 constexpr int CONV_TILE_PIX = 640;   // LDS pixels per chunk (40 KB)
 
-__host__ __device__ inline void conv_tile_shape(int P0, int H, int W, int* r0, int* rows, int* x0, int* cols) {
+__host__ __device__ inline void conv_tile_shape(int P0, int pix, int H, int W, int* r0, int* rows, int* x0, int* cols) {
     const int HW = H * W;
-    const int plast = (P0 + CONV_PIX - 1 < HW ? P0 + CONV_PIX - 1 : HW - 1);
+    const int plast = (P0 + pix - 1 < HW ? P0 + pix - 1 : HW - 1);
     *r0 = P0 / W;
     const int r1 = plast / W;
     *rows = r1 - *r0 + 3;
@@ -144,7 +145,7 @@ __host__ __device__ inline void conv_tile_shape(int P0, int H, int W, int* r0, i
     }
 }
 
-template <int NC, bool RELU, bool OUTF32, bool MASK>
+template <int NC, int NF, bool RELU, bool OUTF32, bool MASK>
 __global__ __launch_bounds__(256) void k_conv3l(const uint16_t* __restrict__ X, int Cin, const uint16_t* __restrict__ Wt,
                                                 const float* __restrict__ bias, void* __restrict__ Yv, int Cout,
                                                 const uint16_t* __restrict__ mask, int H, int W) {
@@ -155,26 +156,27 @@ __global__ __launch_bounds__(256) void k_conv3l(const uint16_t* __restrict__ X, 
     const int HW = H * W;
     const long long img = blockIdx.z;
     const int co0 = blockIdx.y * (16 * NC);
-    const int P0 = blockIdx.x * CONV_PIX;
-    const int pbase = P0 + wv * 16 * CONV_NF;
+    constexpr int PIX = 64 * NF;
+    const int P0 = blockIdx.x * PIX;
+    const int pbase = P0 + wv * 16 * NF;
     const uint16_t* __restrict__ Xi = X + img * HW * Cin;
     int r0, rows, x0, cols;
-    conv_tile_shape(P0, H, W, &r0, &rows, &x0, &cols);
+    conv_tile_shape(P0, PIX, H, W, &r0, &rows, &x0, &cols);
     const int npix = rows * cols;   // <= CONV_TILE_PIX (checked by the launcher)
-    int lp[CONV_NF];
-    bool pv[CONV_NF];
+    int lp[NF];
+    bool pv[NF];
 #pragma unroll
-    for (int f = 0; f < CONV_NF; ++f) {
+    for (int f = 0; f < NF; ++f) {
         const int p = pbase + f * 16 + l16;
         pv[f] = p < HW;
         const int py = pv[f] ? p / W : r0, px = pv[f] ? p - (p / W) * W : x0 + 1;
         lp[f] = (py - r0 + 1) * cols + (px - x0);   // tile index of the pixel itself
     }
-    f4 acc[NC][CONV_NF];
+    f4 acc[NC][NF];
 #pragma unroll
     for (int i = 0; i < NC; ++i)
 #pragma unroll
-        for (int f = 0; f < CONV_NF; ++f) acc[i][f] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int f = 0; f < NF; ++f) acc[i][f] = f4{0.f, 0.f, 0.f, 0.f};
     for (int c0 = 0; c0 < Cin; c0 += 32) {
         __syncthreads();   // the previous chunk's reads are done
         for (int e = threadIdx.x; e < npix * 4; e += 256) {
@@ -190,9 +192,9 @@ __global__ __launch_bounds__(256) void k_conv3l(const uint16_t* __restrict__ X, 
 #pragma unroll
         for (int t = 0; t < KK; ++t) {
             const int dy = t / 3 - 1, dx = t % 3 - 1;
-            bf8 bv[CONV_NF], av[NC];
+            bf8 bv[NF], av[NC];
 #pragma unroll
-            for (int f = 0; f < CONV_NF; ++f)
+            for (int f = 0; f < NF; ++f)
                 bv[f] = pv[f] ? __builtin_bit_cast(bf8, tile[(lp[f] + dy * cols + dx) * 4 + lq]) : zero8();
             const uint16_t* wsrc = Wt + ((long long)(co0 + l16) * KK + t) * Cin + c0 + lq * 8;
 #pragma unroll
@@ -200,13 +202,13 @@ __global__ __launch_bounds__(256) void k_conv3l(const uint16_t* __restrict__ X, 
 #pragma unroll
             for (int i = 0; i < NC; ++i)
 #pragma unroll
-                for (int f = 0; f < CONV_NF; ++f)
+                for (int f = 0; f < NF; ++f)
                     acc[i][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[f], acc[i][f], 0, 0, 0);
         }
     }
     // lane (lq, l16) holds D[co = co0 + 16i + 4lq + v][pixel = pbase + 16f + l16]
 #pragma unroll
-    for (int f = 0; f < CONV_NF; ++f) {
+    for (int f = 0; f < NF; ++f) {
         const int p = pbase + f * 16 + l16;
         if (p >= HW) continue;
         const long long o = (img * HW + p) * Cout;
@@ -326,33 +328,57 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     }
 }
 
-// Bias gradient: partial[block][co] = Σ over the block's pixels of dZ[pixel][co].
+// Bias gradient: partial[block][co] = Σ over the block's pixels of dZ[pixel][co].  Thread t
+// sums channels 8·(t mod G) .. +7 (one 16-byte load, G = C/8 groups per pixel) over the
+// pixels t/G, t/G + 256/G, ... of the block; the 256/G row sums of a channel are then added
+// in a fixed order (deterministic).
+constexpr int COLSUM_PER = 256;   // pixels per block
 __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ dZ, long long npix, int C, int per_block,
                                                 float* __restrict__ partial) {
-    __shared__ float red[256];
-    const int c = threadIdx.x % C, lanes = 256 / C * C;
-    float s = 0.f;
-    if (threadIdx.x < lanes) {
+    __shared__ float red[256 * 8];
+    const int G = C / 8, rows = 256 / G, lanes = rows * G;
+    const int t = threadIdx.x, g = t % G;
+    float s[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = 0.f;
+    if (t < lanes) {
         const long long p0 = (long long)blockIdx.x * per_block;
         const long long p1 = min(npix, p0 + per_block);
-        for (long long p = p0 + threadIdx.x / C; p < p1; p += 256 / C) s += bf2f(dZ[p * C + c]);
+        for (long long p = p0 + t / G; p < p1; p += rows) {
+            const uint4 v = *reinterpret_cast<const uint4*>(dZ + p * C + 8 * g);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s[2 * k] += bf2f((uint16_t)(w[k] & 0xffffu));
+                s[2 * k + 1] += bf2f((uint16_t)(w[k] >> 16));
+            }
+        }
     }
-    red[threadIdx.x] = s;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[t * 8 + k] = s[k];
     __syncthreads();
-    if (threadIdx.x < C) {
-        float t = 0.f;
-        for (int k = threadIdx.x; k < lanes; k += C) t += red[k];
-        partial[(long long)blockIdx.x * C + threadIdx.x] = t;
+    for (int c = t; c < C; c += 256) {
+        float u = 0.f;
+        for (int r = 0; r < rows; ++r) u += red[(r * G + c / 8) * 8 + c % 8];
+        partial[(long long)blockIdx.x * C + c] = u;
     }
 }
 
+// g[c] = Σ_b partial[b][c]: one block per channel, strided partial sums per thread, then a
+// fixed-order tree in LDS (deterministic).
 __global__ __launch_bounds__(256) void k_colsum_reduce(const float* __restrict__ partial, int nb, int C, int c_real,
                                                        float* __restrict__ g) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= c_real) return;
+    __shared__ float red[256];
+    const int c = blockIdx.x;
     float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += partial[(long long)b * C + c];
-    g[c] = s;
+    for (int b = threadIdx.x; b < nb; b += 256) s += partial[(long long)b * C + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && c < c_real) g[c] = red[0];
 }
 
 // 2×2 average pooling: out[b][y][x][c] = mean of in[b][2y+i][2x+j][c].
@@ -589,6 +615,17 @@ int net_conv(const uint16_t* X, int Cin, const uint16_t* W, const float* bias, v
     int nc = Cout % 64 == 0 ? 4 : (Cout % 96 == 0 ? 6 : 2);
     if (Cout == 32) nc = 2;
     const dim3 grid((unsigned)((H * Wd + 127) / 128), (unsigned)(Cout / (16 * nc)), (unsigned)batch), blk(256);
+    // 3×3 LDS kernel: 128 pixels and 16·nc channels per block, or 64 pixels and 32 channels
+    // where that grid would have fewer than four blocks per CU
+    auto nblk3 = [&](int c, int f) {
+        return (long long)((H * Wd + 64 * f - 1) / (64 * f)) * (Cout / (16 * c)) * batch;
+    };
+    int nf = 2, nc3 = nc;
+    if (nblk3(nc3, nf) < 1024) {
+        nf = 1;
+        nc3 = 2;
+    }
+    const int pix = 64 * nf;
     KScope ks_(SG_K_NET, 2.0 * H * Wd * (double)batch * Cout * Cin * ks * ks, st);
 #define SG_CONV(NC_, KS_, R_, F_, M_) \
     hipLaunchKernelGGL((k_conv<NC_, KS_, R_, F_, M_>), grid, blk, 0, st, X, Cin, W, bias, Y, Cout, mask, H, Wd)
@@ -599,19 +636,20 @@ int net_conv(const uint16_t* X, int Cin, const uint16_t* W, const float* bias, v
         else SG_CONV(6, KS_, R_, F_, M_);            \
     } while (0)
     // the LDS-tiled 3×3 kernel when every block's halo tile fits (the tile is largest for
-    // the blocks whose pixels span the most rows, at most ceil((CONV_PIX-1)/W)+1 of them;
-    // with W a multiple of CONV_PIX every block lies in one row)
-    const int max_rows = (CONV_PIX - 1 + Wd - 1) / Wd + 1 + 2;
+    // the blocks whose pixels span the most rows, at most ceil((pix-1)/W)+1 of them; with W
+    // a multiple of pix every block lies in one row)
+    const int max_rows = (pix - 1 + Wd - 1) / Wd + 1 + 2;
     const bool lds_fits = (long long)max_rows * (Wd + 2) <= CONV_TILE_PIX ||
-                          (Wd % CONV_PIX == 0 && 3 * (CONV_PIX + 2) <= CONV_TILE_PIX);
-    const dim3 gridl((unsigned)((H * Wd + CONV_PIX - 1) / CONV_PIX), grid.y, grid.z);
-#define SG_CONVL(NC_, R_, F_, M_) \
-    hipLaunchKernelGGL((k_conv3l<NC_, R_, F_, M_>), gridl, blk, 0, st, X, Cin, W, bias, Y, Cout, mask, H, Wd)
-#define SG_CONVL_NC(R_, F_, M_)                    \
-    do {                                           \
-        if (nc == 2) SG_CONVL(2, R_, F_, M_);      \
-        else if (nc == 4) SG_CONVL(4, R_, F_, M_); \
-        else SG_CONVL(6, R_, F_, M_);              \
+                          (Wd % pix == 0 && 3 * (pix + 2) <= CONV_TILE_PIX);
+    const dim3 gridl((unsigned)((H * Wd + pix - 1) / pix), (unsigned)(Cout / (16 * nc3)), grid.z);
+#define SG_CONVL(NC_, NF_, R_, F_, M_) \
+    hipLaunchKernelGGL((k_conv3l<NC_, NF_, R_, F_, M_>), gridl, blk, 0, st, X, Cin, W, bias, Y, Cout, mask, H, Wd)
+#define SG_CONVL_NC(R_, F_, M_)                        \
+    do {                                               \
+        if (nf == 1) SG_CONVL(2, 1, R_, F_, M_);       \
+        else if (nc3 == 2) SG_CONVL(2, 2, R_, F_, M_); \
+        else if (nc3 == 4) SG_CONVL(4, 2, R_, F_, M_); \
+        else SG_CONVL(6, 2, R_, F_, M_);               \
     } while (0)
     if (ks == 3 && lds_fits) {
         if (out_f32) SG_CONVL_NC(false, true, false);
@@ -659,17 +697,17 @@ int net_wgrad(const uint16_t* dZ, int Cout, const uint16_t* X, int Cin, int H, i
                        batch * nchunk, Cout, KK, Cin, co_real, ci_real, gW);
     SG_HIP(hipGetLastError());
     const long long npix = (long long)batch * H * Wd;
-    const int per = 2048;
+    const int per = COLSUM_PER;
     const int nb = (int)((npix + per - 1) / per);
-    if (Cout > 256) return fail(SG_EINVAL, "net: too many channels for the bias reduction");
+    if (Cout > 256 || Cout % 8) return fail(SG_EINVAL, "net: channel count unsuitable for the bias reduction");
     hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(256), 0, st, dZ, npix, Cout, per, scratch_b);
-    hipLaunchKernelGGL(k_colsum_reduce, dim3((co_real + 255) / 256), dim3(256), 0, st, scratch_b, nb, Cout, co_real, gb);
+    hipLaunchKernelGGL(k_colsum_reduce, dim3(co_real), dim3(256), 0, st, scratch_b, nb, Cout, co_real, gb);
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
 
 long long net_colsum_scratch(int Cout, int H, int Wd, int batch) {
-    return ((long long)batch * H * Wd + 2047) / 2048 * Cout;
+    return ((long long)batch * H * Wd + COLSUM_PER - 1) / COLSUM_PER * Cout;
 }
 
 int net_pool(const uint16_t* in, uint16_t* out, int Hl, int Wl, int C, int batch, hipStream_t st) {
