@@ -262,11 +262,13 @@ def batched_pipelined(insts, chunk, threads, log):
     with cf.ThreadPoolExecutor(max_workers=max(1, threads - 1)) as ex:
         futs = [ex.submit(timed_setup, inst) for inst in insts]
         t_wait = t_solve = 0.0
+        waits = []
         with torch.cuda.stream(stream):
             for c0 in range(0, len(insts), chunk):
                 ta = time.perf_counter()
                 part = [f.result() for f in futs[c0:c0 + chunk]]
                 tb = time.perf_counter()
+                waits.append(tb - ta)
                 ops += part
                 bs = [op.rhs(i.f) for op, i in zip(part, insts[c0:c0 + chunk])]
                 _, rc, infos = sg.gmres_batched(part, bs, None, restart=30, maxit=1000, pc="mean",
@@ -284,7 +286,8 @@ def batched_pipelined(insts, chunk, threads, log):
         "waiting for setups %.3f s, in the solves %.3f s; one setup %.1f ms median, %.1f ms max"
         % (threads - 1, chunk, t, len(insts) / t, rc_all, t_wait, t_solve, np.median(setup_ms), np.max(setup_ms)))
     return {"s": t, "solves_per_s": len(insts) / t, "chunk": chunk, "host_threads": threads - 1,
-            "wait_setup_s": t_wait, "solve_s": t_solve, "setup_ms_median": float(np.median(setup_ms)),
+            "wait_setup_s": t_wait, "wait_per_chunk_s": waits, "solve_s": t_solve,
+            "setup_ms_median": float(np.median(setup_ms)),
             "setup_ms_max": float(np.max(setup_ms)),
             "all_converged": bool(rc_all == 0), "iters_mean": float(np.mean(iters))}
 
