@@ -551,12 +551,14 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
             d.cu = s.cu;
             d.j = j;
             d.full = s.full ? 1 : 0;
-            d.nblocks = s.nblk;
+            // from three basis vectors per wave on, half the blocks (the passes then take two
+            // grid-stride chunks per iteration, as in the single solver)
+            d.nblocks = (j + 3) / 4 >= 3 ? std::max(1, s.nblk / 2) : s.nblk;
             maxj = std::max(maxj, j);
-            g_dred.add(d, s.nblk, 16.0 * (j + (s.full ? 2 : 1)) * n);
+            g_dred.add(d, d.nblocks, 16.0 * (j + (s.full ? 2 : 1)) * n);
             g_dsum.add(d, s.full ? 2 * j + 3 : j + 1);
             g_dfin.add(d, 1);
-            if (s.full) g_dupd.add(d, s.nblk, 16.0 * (j + 4) * n);
+            if (s.full) g_dupd.add(d, d.nblocks, 16.0 * (j + 4) * n);
         }
 
         for (auto* gp : {&g_copy, &g_lin, &g_pcopy, &g_xupd, &g_res, &g_norm, &g_nred}) stg.put_group(*gp);
