@@ -206,9 +206,9 @@ int  sg_gmres(sg_handle h, const sg_c64* b, sg_c64* x, const sg_solve_opts* opts
  * always use SG_ORTH_CGS2.  Beyond 64 basis vectors the delayed form reduces over chunks of
  * 64 vectors in one launch and updates chunk by chunk (u and w read and written once more
  * per further chunk).  The delayed form stores each candidate scaled to about unit norm; the
- * two-pass form keeps its candidates unnormalised (lazy scales), so on a poorly scaled
- * operator (||A P^{-1}|| >> 1, e.g. no preconditioner) a long cycle can overflow there:
- * it then stops with SG_ENONFINITE. */
+ * two-pass form keeps its basis vectors unnormalised (lazy scales) and stores a vector
+ * normalised when its norm leaves [1e-50, 1e50], so that long cycles on a poorly scaled
+ * operator (||A P^{-1}|| >> 1, e.g. no preconditioner) do not overflow in either form. */
 enum { SG_ORTH_DCGS2 = 0, SG_ORTH_CGS2 = 1 };
 int  sg_set_orthogonalisation(sg_handle h, int kind);
 /* The orthonormal Arnoldi basis v_0..v_{nvec-1} of the last cycle of the handle's last

@@ -333,6 +333,25 @@ int run_gmres(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o, sg_p
             if (o->hist && s.iters - 1 < o->hist_cap) o->hist[s.iters - 1] = s.relres_est;
             if (!(nrm > 1e-14 * colnorm / (sj > 0 ? sj : 1.0)) || hnext <= 1e-14 * colnorm) { breakdown = true; break; }
             hscale[j + 1] = 1.0 / nrm;   // the same value cgs2_step left in W.scale[j + 1]
+            if (nrm > 1e50 || nrm < 1e-50) {
+                // The stored vectors are unnormalised (lazy scales), so each step multiplies their
+                // size by about ||A P^{-1}||; store V_{j+1} normalised before that overflows
+                // (or underflows) the squared sums, together with what was already formed from
+                // it by the look-ahead (w_{j+2} and, flexible, Z_{j+1}), and make its scale 1.
+                const double inv = hscale[j + 1];
+                if ((rc = launch_scale_copy(n, inv, wv, wv, stream))) return rc;
+                if (queued) {
+                    double2* wn = Vb + (long long)(j + 2) * ldv;
+                    if ((rc = launch_scale_copy(n, inv, wn, wn, stream))) return rc;
+                    if (flexible) {
+                        double2* zn = W.Z + (long long)(j + 1) * ldv;
+                        if ((rc = launch_scale_copy(n, inv, zn, zn, stream))) return rc;
+                    }
+                }
+                static const double one = 1.0;
+                SG_HIP(hipMemcpyAsync(W.scale + j + 1, &one, sizeof(double), hipMemcpyHostToDevice, stream));
+                hscale[j + 1] = 1.0;
+            }
             if (s.relres_est <= o->tol || s.iters >= o->maxit) break;
         }
         // y = R^{-1} g (upper triangular k×k)

@@ -654,8 +654,7 @@ def test_delayed_cgs2_beyond_64_vectors(key, restart):
     oracle's modified Gram-Schmidt GMRES.  The first cycle runs past 64 vectors, the last
     cycle's basis is orthonormal to 1e-12, the iteration counts agree within 2 + 1 % (the restarted
     runs are long: 560 and about 2000 iterations), the solution reaches the 1e-8 true
-    residual (oracle's matrix) and matches the direct solution.  (The two-pass CGS2 driver
-    keeps its candidates unnormalised and stops with SG_ENONFINITE on these runs.)"""
+    residual (oracle's matrix) and matches the direct solution."""
     inst = SMALL[key]()
     S = oracle_sys(key, inst)
     op = sg.SG.from_instance(inst)
@@ -675,6 +674,29 @@ def test_delayed_cgs2_beyond_64_vectors(key, restart):
         assert abs(id_["iters"] - io.iters) <= 2 + 0.01 * io.iters
         xd = reference_solution(key, S)
         _check_solution(S, to_host(xd_), 1e-8, xd)
+    finally:
+        op.close()
+
+
+@pytest.mark.parametrize("key,restart", [("2d_n37_s2_r4", 200), ("c1_1d", 150)])
+def test_two_pass_cgs2_long_unpreconditioned_cycles(key, restart):
+    """The same long unpreconditioned cycles with the two-pass CGS2, whose basis vectors are
+    stored unnormalised with lazy scales: a vector whose norm leaves [1e-50, 1e50] is stored
+    normalised (with what the look-ahead already formed from it), so the cycle does not
+    overflow.  Iteration counts within 2 + 1 % of the oracle's modified Gram-Schmidt GMRES,
+    the solution at the 1e-8 true residual and against the direct solution."""
+    inst = SMALL[key]()
+    S = oracle_sys(key, inst)
+    op = sg.SG.from_instance(inst)
+    try:
+        op.set_orthogonalisation("cgs2")
+        b = op.rhs(inst.f)
+        x, info = op.gmres(b, restart=restart, maxit=20000, pc="none", tol=1e-8)
+        _, io = krylov.gmres(lambda v: S.A @ v, S.b, None, restart=restart, tol=1e-8, maxit=20000)
+        print("%s m=%d: two-pass cgs2 %d its, oracle %d" % (key, restart, info["iters"], io.iters), flush=True)
+        assert info["converged"] == 1
+        assert abs(info["iters"] - io.iters) <= 2 + 0.01 * io.iters
+        _check_solution(S, to_host(x), 1e-8, reference_solution(key, S))
     finally:
         op.close()
 
