@@ -177,8 +177,20 @@ __global__ __launch_bounds__(256) void k_conv3l(const uint16_t* __restrict__ X, 
     for (int i = 0; i < NC; ++i)
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[i][f] = f4{0.f, 0.f, 0.f, 0.f};
+    // with 32 output channels per block the chunk's weight fragments of all nine taps fit in
+    // registers: they are loaded before the input tile is staged, so that their latency
+    // overlaps the staging instead of stalling every tap
+    constexpr bool PRE = NC <= 2;
     for (int c0 = 0; c0 < Cin; c0 += 32) {
         __syncthreads();   // the previous chunk's reads are done
+        bf8 wr[PRE ? KK : 1][NC];
+        if constexpr (PRE) {
+            const uint16_t* wsrc0 = Wt + (long long)(co0 + l16) * KK * Cin + c0 + lq * 8;
+#pragma unroll
+            for (int t = 0; t < KK; ++t)
+#pragma unroll
+                for (int i = 0; i < NC; ++i) wr[t][i] = load8(wsrc0 + (long long)t * Cin + (long long)i * 16 * KK * Cin);
+        }
         for (int e = threadIdx.x; e < npix * 4; e += 256) {
             const int q = e >> 2, part = e & 3;
             const int rr = q / cols, cc = q - rr * cols;
@@ -196,9 +208,14 @@ __global__ __launch_bounds__(256) void k_conv3l(const uint16_t* __restrict__ X, 
 #pragma unroll
             for (int f = 0; f < NF; ++f)
                 bv[f] = pv[f] ? __builtin_bit_cast(bf8, tile[(lp[f] + dy * cols + dx) * 4 + lq]) : zero8();
-            const uint16_t* wsrc = Wt + ((long long)(co0 + l16) * KK + t) * Cin + c0 + lq * 8;
+            if constexpr (PRE) {
 #pragma unroll
-            for (int i = 0; i < NC; ++i) av[i] = load8(wsrc + (long long)i * 16 * KK * Cin);
+                for (int i = 0; i < NC; ++i) av[i] = wr[t][i];
+            } else {
+                const uint16_t* wsrc = Wt + ((long long)(co0 + l16) * KK + t) * Cin + c0 + lq * 8;
+#pragma unroll
+                for (int i = 0; i < NC; ++i) av[i] = load8(wsrc + (long long)i * 16 * KK * Cin);
+            }
 #pragma unroll
             for (int i = 0; i < NC; ++i)
 #pragma unroll
