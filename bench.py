@@ -281,16 +281,19 @@ def batched_pipelined(insts, chunk, threads, log):
                 setup_c_ms += [i["t_setup"] for i in infos]
         stream.synchronize()
     t = time.perf_counter() - t0
+    slow = max(ops, key=lambda o: o.setup_times()["total"]).setup_times()
     for op in ops:
         op.close()
     log("batched with setup overlapped (%d host threads, chunks of %d): %.3f s (%.1f solves/s), rc %d; "
         "waiting for setups %.3f s, in the solves %.3f s; one setup %.1f ms median, %.1f ms max (%.1f ms max "
-        "inside sg_setup)" % (threads - 1, chunk, t, len(insts) / t, rc_all, t_wait, t_solve, np.median(setup_ms),
-                              np.max(setup_ms), np.max(setup_c_ms)))
+        "inside sg_setup: %.1f ms allocating, %.1f ms uploading, %.1f ms creating its stream)"
+        % (threads - 1, chunk, t, len(insts) / t, rc_all, t_wait, t_solve, np.median(setup_ms), np.max(setup_ms),
+           slow["total"], slow["alloc"], slow["upload"], slow["stream"]))
     return {"s": t, "solves_per_s": len(insts) / t, "chunk": chunk, "host_threads": threads - 1,
             "wait_setup_s": t_wait, "wait_per_chunk_s": waits, "solve_s": t_solve,
             "setup_ms_median": float(np.median(setup_ms)),
             "setup_ms_max": float(np.max(setup_ms)), "setup_ms_max_inside_sg_setup": float(np.max(setup_c_ms)),
+            "slowest_setup_parts_ms": slow,
             "all_converged": bool(rc_all == 0), "iters_mean": float(np.mean(iters))}
 
 

@@ -154,6 +154,10 @@ int  sg_apply(sg_handle h, const sg_c64* x, sg_c64* y, hipStream_t stream);
  * learned correction. */
 enum { SG_MEAN_FD = 0, SG_MEAN_LINE = 1, SG_MEAN_LINE_FALLBACK = 2 };
 int  sg_mean_solver(sg_handle h, int* kind, double* cond_v);
+/* Where this handle's sg_setup spent its time, in milliseconds (host array of 4): the whole
+ * call, its device allocations, its uploads (copy and wait) and the creation of its upload
+ * stream; the rest is host computation. */
+int  sg_setup_times(sg_handle h, double* ms);
 /* Process-wide limit on that cond₂ figure for later sg_setup calls (default 1e4, >= 1,
  * else SG_EINVAL); a limit of 1 sends every 2D constant-k̄ problem with n <= 257 to the line
  * factorisation. */

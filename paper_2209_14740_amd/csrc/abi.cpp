@@ -154,6 +154,18 @@ int sg_mean_solver(sg_handle h, int* kind, double* cond_v) {
     })
 }
 
+int sg_setup_times(sg_handle h, double* ms) {
+    SG_TRY({
+        if (!h || !ms) return fail(SG_EINVAL, "null argument");
+        const Ctx* c = ctx(h);
+        ms[0] = c->t_setup_ms;
+        ms[1] = c->t_setup_alloc_ms;
+        ms[2] = c->t_setup_upload_ms;
+        ms[3] = c->t_setup_stream_ms;
+        return SG_OK;
+    })
+}
+
 int sg_set_operator_shift(sg_handle h, double beta) {
     SG_TRY({
         if (!h) return fail(SG_EINVAL, "null handle");

@@ -430,12 +430,12 @@ int build_line_factors(Ctx* c, const double* k0_host) {
         // 4·KCM - L rows past the end of a factor
         const int kcm = pipe_kcm(L);
         const size_t pad = kcm ? (size_t)std::max(0, 4 * kcm - L) * L : 0;
-        SG_HIP(hipMalloc(&c->d_lineE[t], (dev.size() + pad) * sizeof(double2)));
+        SG_HIP(setup_alloc(&c->d_lineE[t], (dev.size() + pad) * sizeof(double2)));
         if (int rc_ = upload(c->d_lineE[t], dev.data(), dev.size() * sizeof(double2))) return rc_;
         if (pad)
             if (int rc_ = upload_zero(c->d_lineE[t] + dev.size(), pad * sizeof(double2))) return rc_;
     }
-    SG_HIP(hipMalloc(&c->d_lineb, (size_t)L * sizeof(double)));
+    SG_HIP(setup_alloc(&c->d_lineb, (size_t)L * sizeof(double)));
     if (int rc_ = upload(c->d_lineb, bl.data(), (size_t)L * sizeof(double))) return rc_;
     return SG_OK;
 }

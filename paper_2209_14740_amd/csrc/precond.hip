@@ -937,9 +937,9 @@ static int upload_planes(DenseB& d, int N, const std::vector<cplx>& B, int ld) {
         }
     std::vector<float> hf(h.size());
     for (size_t i = 0; i < h.size(); ++i) hf[i] = (float)h[i];
-    SG_HIP(hipMalloc(&d.p3, h.size() * sizeof(double)));
+    SG_HIP(setup_alloc(&d.p3, h.size() * sizeof(double)));
     if (int rc_ = upload(d.p3, h.data(), h.size() * sizeof(double))) return rc_;
-    SG_HIP(hipMalloc(&d.p3f, hf.size() * sizeof(float)));
+    SG_HIP(setup_alloc(&d.p3f, hf.size() * sizeof(float)));
     if (int rc_ = upload(d.p3f, hf.data(), hf.size() * sizeof(float))) return rc_;
     return SG_OK;
 }
@@ -953,10 +953,10 @@ static int upload_one(DenseB& d, const std::vector<double>& e) {
         hi[i] = host_bf16((float)e[i]);
         lo[i] = host_bf16((float)(e[i] - (double)host_bf16_f(hi[i])));
     }
-    SG_HIP(hipMalloc(&d.f64, cnt * sizeof(double)));
-    SG_HIP(hipMalloc(&d.f32, cnt * sizeof(float)));
-    SG_HIP(hipMalloc(&d.bf_hi, cnt * sizeof(uint16_t)));
-    SG_HIP(hipMalloc(&d.bf_lo, cnt * sizeof(uint16_t)));
+    SG_HIP(setup_alloc(&d.f64, cnt * sizeof(double)));
+    SG_HIP(setup_alloc(&d.f32, cnt * sizeof(float)));
+    SG_HIP(setup_alloc(&d.bf_hi, cnt * sizeof(uint16_t)));
+    SG_HIP(setup_alloc(&d.bf_lo, cnt * sizeof(uint16_t)));
     if (int rc_ = upload(d.f64, e.data(), cnt * sizeof(double))) return rc_;
     if (int rc_ = upload(d.f32, f32.data(), cnt * sizeof(float))) return rc_;
     if (int rc_ = upload(d.bf_hi, hi.data(), cnt * sizeof(uint16_t))) return rc_;

@@ -429,21 +429,21 @@ static int build_tri(int n, double h, double kbar, const std::vector<cplx>& sig,
             hpsi[o + 3] = make_double2(m11.real(), m11.imag());
         }
     }
-    SG_HIP(hipMalloc(&tf.u1p, hu1p.size() * sizeof(double2)));
-    SG_HIP(hipMalloc(&tf.u2p, hu2p.size() * sizeof(double2)));
-    SG_HIP(hipMalloc(&tf.phi, hphi.size() * sizeof(double2)));
-    SG_HIP(hipMalloc(&tf.psi, hpsi.size() * sizeof(double2)));
+    SG_HIP(setup_alloc(&tf.u1p, hu1p.size() * sizeof(double2)));
+    SG_HIP(setup_alloc(&tf.u2p, hu2p.size() * sizeof(double2)));
+    SG_HIP(setup_alloc(&tf.phi, hphi.size() * sizeof(double2)));
+    SG_HIP(setup_alloc(&tf.psi, hpsi.size() * sizeof(double2)));
     if (int rc_ = upload(tf.u1p, hu1p.data(), hu1p.size() * sizeof(double2))) return rc_;
     if (int rc_ = upload(tf.u2p, hu2p.data(), hu2p.size() * sizeof(double2))) return rc_;
     if (int rc_ = upload(tf.phi, hphi.data(), hphi.size() * sizeof(double2))) return rc_;
     if (int rc_ = upload(tf.psi, hpsi.data(), hpsi.size() * sizeof(double2))) return rc_;
-    SG_HIP(hipMalloc(&tf.pivm, hpm.size() * sizeof(uint32_t)));
+    SG_HIP(setup_alloc(&tf.pivm, hpm.size() * sizeof(uint32_t)));
     if (int rc_ = upload(tf.pivm, hpm.data(), hpm.size() * sizeof(uint32_t))) return rc_;
-    SG_HIP(hipMalloc(&tf.dl, hdl.size() * sizeof(double2)));
-    SG_HIP(hipMalloc(&tf.dinv, hdi.size() * sizeof(double2)));
-    SG_HIP(hipMalloc(&tf.du1, hu1.size() * sizeof(double2)));
-    SG_HIP(hipMalloc(&tf.du2, hu2.size() * sizeof(double2)));
-    SG_HIP(hipMalloc(&tf.piv, hp.size()));
+    SG_HIP(setup_alloc(&tf.dl, hdl.size() * sizeof(double2)));
+    SG_HIP(setup_alloc(&tf.dinv, hdi.size() * sizeof(double2)));
+    SG_HIP(setup_alloc(&tf.du1, hu1.size() * sizeof(double2)));
+    SG_HIP(setup_alloc(&tf.du2, hu2.size() * sizeof(double2)));
+    SG_HIP(setup_alloc(&tf.piv, hp.size()));
     if (int rc_ = upload(tf.dl, hdl.data(), hdl.size() * sizeof(double2))) return rc_;
     if (int rc_ = upload(tf.dinv, hdi.data(), hdi.size() * sizeof(double2))) return rc_;
     if (int rc_ = upload(tf.du1, hu1.data(), hu1.size() * sizeof(double2))) return rc_;
@@ -511,13 +511,37 @@ double eigen_cond_limit() { return g_eigen_cond_limit.load(); }
 void set_eigen_cond_limit(double v) { g_eigen_cond_limit.store(v); }
 
 static thread_local hipStream_t t_setup_stream = nullptr;
+static thread_local SetupClock t_setup_clock;
+
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+SetupClock& setup_clock() { return t_setup_clock; }
+
+static void stamp_setup(Ctx* c, std::chrono::steady_clock::time_point t0) {
+    c->t_setup_ms = ms_since(t0);
+    c->t_setup_alloc_ms = t_setup_clock.alloc;
+    c->t_setup_upload_ms = t_setup_clock.upload;
+    c->t_setup_stream_ms = t_setup_clock.stream;
+}
+
+hipError_t setup_alloc_raw(void** p, size_t bytes) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const hipError_t e = hipMalloc(p, bytes);
+    t_setup_clock.alloc += ms_since(t0);
+    return e;
+}
 
 SetupStream::SetupStream() {
     rc = SG_OK;
+    t_setup_clock = SetupClock{};
+    const auto t0 = std::chrono::steady_clock::now();
     if (hipStreamCreateWithFlags(&t_setup_stream, hipStreamNonBlocking) != hipSuccess) {
         t_setup_stream = nullptr;
         rc = fail(SG_EHIP, "could not create the setup stream");
     }
+    t_setup_clock.stream += ms_since(t0);
 }
 SetupStream::~SetupStream() {
     if (t_setup_stream) (void)hipStreamDestroy(t_setup_stream);
@@ -526,8 +550,10 @@ SetupStream::~SetupStream() {
 
 int upload(void* dst, const void* src, size_t bytes) {
     if (bytes == 0) return SG_OK;
+    const auto t0 = std::chrono::steady_clock::now();
     SG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, t_setup_stream));
     SG_HIP(hipStreamSynchronize(t_setup_stream));   // src may be freed when this returns
+    t_setup_clock.upload += ms_since(t0);
     return SG_OK;
 }
 
@@ -659,11 +685,11 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     c->bvals_off = (int)vals.size();
     vals.insert(vals.end(), c->B.term_val.begin(), c->B.term_val.end());
 
-    SG_HIP(hipMalloc(&c->d_D2, D2.size() * sizeof(double)));
-    SG_HIP(hipMalloc(&c->d_D1, D1.size() * sizeof(double)));
-    SG_HIP(hipMalloc(&c->d_prog, prog.size() * sizeof(int)));
-    SG_HIP(hipMalloc(&c->d_vals, std::max<size_t>(vals.size(), 1) * sizeof(double)));
-    SG_HIP(hipMalloc(&c->d_w, w.size() * sizeof(double)));
+    SG_HIP(setup_alloc(&c->d_D2, D2.size() * sizeof(double)));
+    SG_HIP(setup_alloc(&c->d_D1, D1.size() * sizeof(double)));
+    SG_HIP(setup_alloc(&c->d_prog, prog.size() * sizeof(int)));
+    SG_HIP(setup_alloc(&c->d_vals, std::max<size_t>(vals.size(), 1) * sizeof(double)));
+    SG_HIP(setup_alloc(&c->d_w, w.size() * sizeof(double)));
     if (int rc_ = upload(c->d_D2, D2.data(), D2.size() * sizeof(double))) return rc_;
     if (int rc_ = upload(c->d_D1, D1.data(), D1.size() * sizeof(double))) return rc_;
     if (int rc_ = upload(c->d_prog, prog.data(), prog.size() * sizeof(int))) return rc_;
@@ -671,15 +697,15 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
         if (int rc_ = upload(c->d_vals, vals.data(), vals.size() * sizeof(double))) return rc_;
     if (int rc_ = upload(c->d_w, w.data(), w.size() * sizeof(double))) return rc_;
     c->w_host = w;
-    SG_HIP(hipMalloc(&c->d_kf, (size_t)s * P * sizeof(double)));
+    SG_HIP(setup_alloc(&c->d_kf, (size_t)s * P * sizeof(double)));
     if (int rc_ = upload(c->d_kf, p->k_fields + P, (size_t)s * P * sizeof(double))) return rc_;
 
     if (c->vmean) {
-        SG_HIP(hipMalloc(&c->d_k0, (size_t)P * sizeof(double)));
+        SG_HIP(setup_alloc(&c->d_k0, (size_t)P * sizeof(double)));
         if (int rc_ = upload(c->d_k0, p->k_fields, (size_t)P * sizeof(double))) return rc_;
         int rc = build_line_factors(c.get(), p->k_fields);
         if (rc) return rc;
-        c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        stamp_setup(c.get(), t0);
         *out = c.release();
         return SG_OK;
     }
@@ -705,7 +731,7 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
             std::vector<double> k0(P, kb);
             rc = build_line_factors(c.get(), k0.data());
             if (rc) return rc;
-            c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            stamp_setup(c.get(), t0);
             *out = c.release();
             return SG_OK;
         }
@@ -722,8 +748,8 @@ int build_ctx(const sg_problem* p, hipStream_t stream, Ctx** out) {
     // rows of the intermediate start on 128-byte boundaries, so that the sweep's and the
     // transforms' row pieces are whole cache lines
     c->tld = c->dim == 2 ? (n + 7) / 8 * 8 : n;
-    SG_HIP(hipMalloc(&c->d_tmp_pc, (c->dim == 2 ? (size_t)c->Q * n * c->tld : (size_t)c->nvec) * sizeof(double2)));
-    c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    SG_HIP(setup_alloc(&c->d_tmp_pc, (c->dim == 2 ? (size_t)c->Q * n * c->tld : (size_t)c->nvec) * sizeof(double2)));
+    stamp_setup(c.get(), t0);
     *out = c.release();
     return SG_OK;
 }

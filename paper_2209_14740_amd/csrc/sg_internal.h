@@ -37,6 +37,17 @@ struct SetupStream {
 };
 int upload(void* dst, const void* src, size_t bytes);
 int upload_zero(void* dst, size_t bytes);
+// Time a setup spends in device allocations, uploads and its stream (milliseconds, the calling
+// thread's current setup; reported by sg_setup_times).
+struct SetupClock {
+    double alloc = 0, upload = 0, stream = 0;
+};
+SetupClock& setup_clock();
+hipError_t setup_alloc_raw(void** p, size_t bytes);
+template <class T>
+hipError_t setup_alloc(T** p, size_t bytes) {
+    return setup_alloc_raw(reinterpret_cast<void**>(p), bytes);
+}
 
 // Coupling program of the matrix-free operator.  For output block i the pairs
 // [pair_ptr[i], pair_ptr[i+1]) list the input blocks j with a nonzero coupling; pair p
@@ -259,6 +270,7 @@ struct Ctx {
     bool classic_cgs2 = false;         // sg_set_orthogonalisation(SG_ORTH_CGS2): the two-pass driver
     int last_k = 0;                    // orthonormal basis vectors of the last delayed-CGS2 cycle
     double t_setup_ms = 0;
+    double t_setup_alloc_ms = 0, t_setup_upload_ms = 0, t_setup_stream_ms = 0;   // parts of t_setup_ms
 
     ~Ctx();
 };

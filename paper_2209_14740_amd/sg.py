@@ -85,6 +85,7 @@ def lib():
     L.sg_set_operator_shift.argtypes = [vp, d]
     L.sg_moments.argtypes = [vp, vp, vp, vp, vp]
     L.sg_mean_solver.argtypes = [vp, C.POINTER(i), C.POINTER(d)]
+    L.sg_setup_times.argtypes = [vp, C.POINTER(d)]
     L.sg_set_eigen_cond_limit.argtypes = [d]
     L.sg_set_orthogonalisation.argtypes = [vp, i]
     L.sg_last_basis.argtypes = [vp, C.POINTER(i), C.POINTER(vp)]
@@ -122,7 +123,7 @@ def lib():
     L.sg_last_error.argtypes = []
     L.sg_last_error.restype = C.c_char_p
     for name in ("sg_setup", "sg_basis", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres", "sg_fgmres",
-                 "sg_stationary", "sg_set_operator_shift", "sg_moments", "sg_degree_magnitudes", "sg_mean_solver", "sg_set_eigen_cond_limit", "sg_set_orthogonalisation", "sg_last_basis", "sg_cgs2",
+                 "sg_stationary", "sg_set_operator_shift", "sg_moments", "sg_degree_magnitudes", "sg_mean_solver", "sg_setup_times", "sg_set_eigen_cond_limit", "sg_set_orthogonalisation", "sg_last_basis", "sg_cgs2",
                  "sg_cgs2_noalloc", "sg_norm", "sg_axpby", "sg_set_profiling",
                  "sg_kernel_times", "sg_gmres_batched", "sg_batched_release", "sg_autotune", "sg_tune_get", "sg_tune_set", "sg_net_create", "sg_net_get_params", "sg_net_set_params",
                  "sg_net_forward_nhwc", "sg_net_grad_nhwc", "sg_net_adam_step", "sg_net_train_pairs", "sg_net_save",
@@ -240,6 +241,12 @@ class SG:
         k, cv = C.c_int(), C.c_double()
         check(lib().sg_mean_solver(self._h, C.byref(k), C.byref(cv)), "sg_mean_solver")
         return ("fd", "line", "line_fallback")[k.value], cv.value
+
+    def setup_times(self):
+        """Milliseconds of this handle's setup: total, device allocations, uploads, stream creation."""
+        ms = (C.c_double * 4)()
+        check(lib().sg_setup_times(self._h, ms), "sg_setup_times")
+        return {"total": ms[0], "alloc": ms[1], "upload": ms[2], "stream": ms[3]}
 
     def moments(self, x, stream=None):
         """(E[u], Var[Re u], Var[Im u]) of the SG solution x, as torch tensors on the device."""
@@ -508,6 +515,7 @@ def norm(x, stream=None) -> float:
 
 EXPORTED = ["sg_setup", "sg_destroy", "sg_basis", "sg_size", "sg_rhs", "sg_apply", "sg_precond", "sg_gmres",
             "sg_fgmres", "sg_stationary", "sg_set_operator_shift", "sg_moments", "sg_degree_magnitudes", "sg_mean_solver",
+            "sg_setup_times",
             "sg_set_eigen_cond_limit", "sg_set_orthogonalisation", "sg_last_basis", "sg_gmres_batched",
             "sg_batched_release", "sg_autotune", "sg_tune_get",
             "sg_tune_set", "sg_cgs2", "sg_cgs2_noalloc", "sg_norm", "sg_axpby",
