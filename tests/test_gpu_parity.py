@@ -511,6 +511,20 @@ def test_nonfinite_inputs_are_reported():
 
 # --------------------------------------------------------------- edge cases
 
+def test_setup_times_are_consistent():
+    """sg_setup_times: the parts (allocation, uploads, stream creation) are non-negative and
+    add up to no more than the whole setup."""
+    inst = SMALL["2d_n37_s2_r4"]()
+    op = sg.SG.from_instance(inst)
+    try:
+        t = op.setup_times()
+        print("setup times", t, flush=True)
+        assert t["total"] > 0 and min(t["alloc"], t["upload"], t["stream"]) >= 0
+        assert t["alloc"] + t["upload"] + t["stream"] <= t["total"] * 1.0001
+    finally:
+        op.close()
+
+
 def test_sigma_zero_one_step():
     """σ = 0: A = A_0, so A_0-preconditioned GMRES converges in one iteration (breakdown of
     the Krylov space is the exact solution, Remark 6.1)."""
