@@ -743,9 +743,11 @@ int launch_dcgs_reduce(long long n, int nv, const double2* V, long long ldv, con
     const int nout = w ? 2 * nv + 3 : nv + 1;
     const int nchunk = std::max(1, (nv + 63) / 64);   // chunks of 64 basis vectors (grid y)
     const int nvw = (std::min(nv, 64) + 3) / 4;
-    // from four basis vectors per wave on: half the blocks, two chunks per iteration each
-    // (measured 5-11 % faster on 36 MB and 351 MB vectors; no gain with one or two)
-    const int nb = nvw >= 3 ? std::max(1, nblocks / 2) : nblocks;
+    // Grid: fewer, longer-running blocks than the other reductions. A sweep over 256 to
+    // 2048 blocks on 36 MB and 351 MB vectors, one to sixteen basis vectors per wave, was
+    // fastest at 1024 blocks with one vector per wave and at 512 from two on, with two
+    // grid-stride chunks per iteration only at two vectors per wave (2-25 % over 2048).
+    const int nb = std::min(nblocks, nvw <= 1 ? 1024 : 512);
     {
         KScope ks(SG_K_DOT, 16.0 * (nv + (w ? 2 : 1) * nchunk) * (double)n, st);
         const dim3 grid(nb, nchunk);
@@ -753,7 +755,7 @@ int launch_dcgs_reduce(long long n, int nv, const double2* V, long long ldv, con
     if (nvw <= NVW_) {                                                                                            \
         hipLaunchKernelGGL((k_dcgs_reduce<NVW_, UNR_>), grid, dim3(RB), 0, st, n, nv, V, ldv, u, w, partial);     \
     } else
-        SG_DR(1, 1) SG_DR(2, 1) SG_DR(4, 2) SG_DR(8, 2) SG_DR(16, 2) {
+        SG_DR(1, 1) SG_DR(2, 2) SG_DR(4, 1) SG_DR(8, 1) SG_DR(16, 1) {
             return fail(SG_EINVAL, "delayed CGS2: more than 64 basis vectors per chunk");
         }
 #undef SG_DR
