@@ -789,13 +789,15 @@ int launch_dcgs_update(long long n, int nv, const double2* V, long long ldv, dou
         const double2* cuc = last ? cu : cu + 3;
         const double2* Vc = V + (long long)koff * ldv;
         const int nvw = (nvc + 3) / 4;
-        const int nb = nvw >= 3 ? std::max(1, nblocks / 2) : nblocks;   // as in the reduction
+        // 512 blocks from two vectors per wave on (the same sweep as the reduction: 3-7 %
+        // over 1024-2048 blocks); with one vector per wave the full grid stays fastest
+        const int nb = nvw >= 2 ? std::min(nblocks, 512) : nblocks;
 #define SG_DU(NVW_, UNR_)                                                                                        \
     if (nvw <= NVW_) {                                                                                           \
         hipLaunchKernelGGL((k_dcgs_update<NVW_, UNR_>), dim3(nb), dim3(RB), 0, st, n, nvc, Vc, ldv, u, w, cv + koff, \
                            cw + koff, cuc);                                                                      \
     } else
-        SG_DU(1, 1) SG_DU(2, 1) SG_DU(4, 2) SG_DU(8, 2) SG_DU(16, 2) {
+        SG_DU(1, 1) SG_DU(2, 2) SG_DU(4, 1) SG_DU(8, 1) SG_DU(16, 1) {
             return fail(SG_EINVAL, "delayed CGS2: more than 64 basis vectors per chunk");
         }
 #undef SG_DU
