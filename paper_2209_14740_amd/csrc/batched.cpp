@@ -551,9 +551,11 @@ static int run_gmres_batched_dcgs(int count, Ctx* const* ctx, const double2* con
             d.cu = s.cu;
             d.j = j;
             d.full = s.full ? 1 : 0;
-            // from three basis vectors per wave on, half the blocks (the passes then take two
-            // grid-stride chunks per iteration, as in the single solver)
-            d.nblocks = (j + 3) / 4 >= 3 ? std::max(1, s.nblk / 2) : s.nblk;
+            // about 32 grid-stride chunks of 64 elements per block (the launch holds every
+            // instance's blocks, so the grid is full without short blocks), and from two basis
+            // vectors per wave on at most 512 blocks per instance, as in the single solver
+            d.nblocks = (int)std::min<long long>((j + 3) / 4 >= 2 ? 512 : s.nblk,
+                                                 std::max<long long>(1, (n + 2047) / 2048));
             maxj = std::max(maxj, j);
             g_dred.add(d, d.nblocks, 16.0 * (j + (s.full ? 2 : 1)) * n);
             g_dsum.add(d, s.full ? 2 * j + 3 : j + 1);

@@ -986,7 +986,7 @@ int launch_dcgs_reduce_grouped(const DcgsTask* d_tasks, const int* d_start, int 
     const int nvw = (maxj + 3) / 4;
 #define SG_DRG(NVW_)                                                                                             \
     if (nvw <= NVW_) {                                                                                           \
-        hipLaunchKernelGGL((k_dcgs_reduce_g<NVW_, (NVW_ >= 4 ? 2 : 1)>), dim3(total), dim3(RB), 0, st, d_tasks,   \
+        hipLaunchKernelGGL((k_dcgs_reduce_g<NVW_, (NVW_ == 2 ? 2 : 1)>), dim3(total), dim3(RB), 0, st, d_tasks,   \
                            d_start, ntask);                                                                      \
         SG_HIP(hipGetLastError());                                                                               \
         return SG_OK;                                                                                            \
@@ -1019,7 +1019,7 @@ int launch_dcgs_update_grouped(const DcgsTask* d_tasks, const int* d_start, int 
     const int nvw = (maxj + 3) / 4;
 #define SG_DUG(NVW_)                                                                                             \
     if (nvw <= NVW_) {                                                                                           \
-        hipLaunchKernelGGL((k_dcgs_update_g<NVW_, (NVW_ >= 4 ? 2 : 1)>), dim3(total), dim3(RB), 0, st, d_tasks,   \
+        hipLaunchKernelGGL((k_dcgs_update_g<NVW_, (NVW_ == 2 ? 2 : 1)>), dim3(total), dim3(RB), 0, st, d_tasks,   \
                            d_start, ntask);                                                                      \
         SG_HIP(hipGetLastError());                                                                               \
         return SG_OK;                                                                                            \
