@@ -35,7 +35,7 @@ KIND = {0: "sg_apply", 1: "fd_gemm", 2: "tri_sweep", 3: "cgs2_multidot", 4: "cgs
 # scaled by the same counters on a copy kernel of known size.  Valid only for the kernel
 # source it was measured on (sha256 of the file below) and the tile shape the autotuner
 # chose then; otherwise reported as null.
-TRAFFIC = {"fd_gemm": {"bytes": 82.81e6, "file": "precond.hip", "src": "97723ed64cf9b425", "tile": 5}}
+TRAFFIC = {"fd_gemm": {"bytes": 82.81e6, "file": "precond.hip", "src": "153022b744d212ea", "tile": 5}}
 
 
 def _src_hash(name):
