@@ -110,12 +110,15 @@ static int ensure_dcgs(Ctx* c, int m) {
     (void)hipFree(w.dpart);
     (void)hipFree(w.dsmall);
     if (w.hrec) (void)hipHostFree(w.hrec);
-    w.dpart = w.dsmall = w.hrec = nullptr;
+    w.dpart = w.dsmall = w.hrec = w.hrec_dev = nullptr;
     w.dm = 0;
     if (device_alloc((void**)&w.dpart, (size_t)w.npartial_blocks * (2 * m + 3) * sizeof(double2)) != hipSuccess ||
         device_alloc((void**)&w.dsmall, (size_t)(10 * m + 16) * sizeof(double2)) != hipSuccess)
         return fail(SG_ENOMEM, "delayed CGS2 buffer allocation failed");
-    SG_HIP(hipHostMalloc(&w.hrec, (size_t)2 * (2 * m + 3) * sizeof(double2), hipHostMallocDefault));
+    // coherent: the coefficient kernel's stores to the records reach host memory directly
+    // (no copy launch per Arnoldi step); the host reads a record after the step's event
+    SG_HIP(hipHostMalloc(&w.hrec, (size_t)2 * (2 * m + 3) * sizeof(double2), hipHostMallocCoherent));
+    SG_HIP(hipHostGetDevicePointer((void**)&w.hrec_dev, w.hrec, 0));
     w.dm = m;
     return SG_OK;
 }
@@ -143,8 +146,7 @@ int run_gmres_dcgs2(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o
     double2* ut = W.tmp + n;
     double2* red = W.dsmall;                 // 2m+3
     double2* h1 = red + (2 * m + 3);         // m+1
-    double2* rec = h1 + (m + 1);             // 2m+3
-    double2* cv = rec + (2 * m + 3);         // m
+    double2* cv = h1 + (m + 1);              // m (the step records go to the pinned W.hrec)
     double2* cw = cv + m;                    // m
     double2* cu = cw + m;                    // 7: update coefficients and the scale of the candidate
     sg_solve_stats s{};
@@ -228,9 +230,9 @@ int run_gmres_dcgs2(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o
             if ((r = launch_dcgs_reduce(n, j, Vb, ldv, Vb + (long long)j * ldv,
                                         full ? Vb + (long long)(j + 1) * ldv : nullptr, W.dpart, nb, red, stream)))
                 return r;
-            if ((r = launch_dcgs_finalize(j, full, red, h1, rec, cv, cw, cu, stream))) return r;
-            SG_HIP(hipMemcpyAsync(W.hrec + (size_t)(j & 1) * (2 * m + 3), rec, (size_t)(2 * j + 3) * sizeof(double2),
-                                  hipMemcpyDeviceToHost, stream));
+            if ((r = launch_dcgs_finalize(j, full, red, h1, W.hrec_dev + (size_t)(j & 1) * (2 * m + 3), cv, cw, cu,
+                                          stream)))
+                return r;
             if (full && (r = launch_dcgs_update(n, j, Vb, ldv, Vb + (long long)j * ldv, Vb + (long long)(j + 1) * ldv,
                                                 cv, cw, cu, nb, stream)))
                 return r;
@@ -268,7 +270,7 @@ int run_gmres_dcgs2(Ctx* c, const double2* b, double2* x, const sg_solve_opts* o
             if (!std::isfinite(nu)) return fail(SG_ENONFINITE, "non-finite Arnoldi norm");
             bool finish_next = false;
             if (j >= 1 && k < j) {   // (a full step redone after a finishing one finds it committed)
-                // column j-1 is complete: rows 0..j-1 from rec, row j = ν_j
+                // column j-1 is complete: rows 0..j-1 from the record, row j = ν_j
                 std::vector<cd> col(j + 1);
                 double colnorm = 0.0;
                 for (int i = 0; i < j; ++i) {

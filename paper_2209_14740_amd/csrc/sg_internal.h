@@ -183,6 +183,7 @@ struct Workspace {
     double2* dpart = nullptr;
     double2* dsmall = nullptr;
     double2* hrec = nullptr;
+    double2* hrec_dev = nullptr;   // hrec's device address: the coefficient kernel writes the records there
 };
 
 // Optional per-kernel-class event timing (sg_set_profiling / sg_kernel_times).
