@@ -185,7 +185,6 @@ def batched_config4(count, log, one_at_a_time=True):
     torch.cuda.synchronize()
     t_solve64 = time.perf_counter() - t0
     log("batched FP64 preconditioner: %.3f s (%.1f solves/s), rc %d" % (t_solve64, count / t_solve64, rc64))
-    pipe = batched_pipelined(insts, 128, threads, log)
     # the same instances one at a time through sg_gmres (same algorithm and precision), in
     # windows of 64 handles: a first pass over the window with each handle's Krylov-workspace
     # allocation, a second pass in the steady state (63 other solves between a handle's two
@@ -210,6 +209,15 @@ def batched_config4(count, log, one_at_a_time=True):
             % (t_seq[0], t_seq[1], count / t_seq[1]))
     else:   # kernel-trace runs: the batch legs only
         t_seq = [float("nan")] * 2
+    # setup overlapped with the solves, from a cold start: this leg's 512 new handles would not
+    # fit beside the first 512 and the cached arena (a setup that finds the device full hands
+    # the arena back, a device-wide wait of seconds), so both are freed first
+    for op in ops:
+        op.close()
+    del bs, xs
+    sg.batched_release()
+    torch.cuda.empty_cache()
+    pipe = batched_pipelined(insts, 128, threads, log)
     its = np.array([i["iters"] for i in infos])
     rel = np.array([i["relres_true"] for i in infos])
     out = {"workload": "%d seeded instances, N in {63,127,255}, kbar~U[5,30], sigma=0.1 kbar, s in 1..4, "
@@ -226,9 +234,6 @@ def batched_config4(count, log, one_at_a_time=True):
            "autotune_gpu_ms": tune_ms, "tiles": tiles, "all_converged": bool(rc == 0),
            "iters_mean": float(its.mean()), "iters_max": int(its.max()), "relres_true_max": float(rel.max()),
            "kernels": kern}
-    for op in ops:
-        op.close()
-    del bs, xs
     torch.cuda.empty_cache()
     return out
 
@@ -249,6 +254,7 @@ def batched_pipelined(insts, chunk, threads, log):
     from paper_2209_14740_amd import sg
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
+    free_start = torch.cuda.mem_get_info()[0]
     t0 = time.perf_counter()
     ops, iters, rc_all = [], [], 0
     setup_ms = []
@@ -281,7 +287,9 @@ def batched_pipelined(insts, chunk, threads, log):
                 setup_c_ms += [i["t_setup"] for i in infos]
         stream.synchronize()
     t = time.perf_counter() - t0
-    slow = max(ops, key=lambda o: o.setup_times()["total"]).setup_times()
+    parts = [o.setup_times() for o in ops]
+    slow = max(parts, key=lambda d: d["total"])
+    parts_sum = {k: float(sum(d[k] for d in parts)) for k in parts[0]}
     for op in ops:
         op.close()
     log("batched with setup overlapped (%d host threads, chunks of %d): %.3f s (%.1f solves/s), rc %d; "
@@ -293,7 +301,8 @@ def batched_pipelined(insts, chunk, threads, log):
             "wait_setup_s": t_wait, "wait_per_chunk_s": waits, "solve_s": t_solve,
             "setup_ms_median": float(np.median(setup_ms)),
             "setup_ms_max": float(np.max(setup_ms)), "setup_ms_max_inside_sg_setup": float(np.max(setup_c_ms)),
-            "slowest_setup_parts_ms": slow,
+            "slowest_setup_parts_ms": slow, "setup_parts_sum_ms": parts_sum,
+            "device_free_gb_at_start": free_start / 1e9,
             "all_converged": bool(rc_all == 0), "iters_mean": float(np.mean(iters))}
 
 
