@@ -185,6 +185,15 @@ def batched_config4(count, log, one_at_a_time=True):
     torch.cuda.synchronize()
     t_solve64 = time.perf_counter() - t0
     log("batched FP64 preconditioner: %.3f s (%.1f solves/s), rc %d" % (t_solve64, count / t_solve64, rc64))
+    # setup overlapped with the solves, with handles of its own: the first 512 handles are
+    # freed first (two sets beside the solver's cached arena would fill the device, and a
+    # setup that finds it full hands the arena back, a device-wide wait of seconds); the
+    # arena stays, as in a process that keeps serving batches
+    for op in ops:
+        op.close()
+    del bs, xs
+    torch.cuda.empty_cache()
+    pipe = batched_pipelined(insts, 128, threads, log)
     # the same instances one at a time through sg_gmres (same algorithm and precision), in
     # windows of 64 handles: a first pass over the window with each handle's Krylov-workspace
     # allocation, a second pass in the steady state (63 other solves between a handle's two
@@ -193,6 +202,11 @@ def batched_config4(count, log, one_at_a_time=True):
     # memory together).  The batched solver's cached arena is handed back first.
     sg.batched_release()
     t_seq = [0.0, 0.0]
+    if one_at_a_time:   # fresh handles, set up as before (untimed)
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            ops = list(ex.map(sg.SG.from_instance, insts))
+        bs = [op.rhs(i.f) for op, i in zip(ops, insts)]
+        xs = [op.empty() for op in ops]
     for w0 in range(0, count if one_at_a_time else 0, 64):
         win = list(zip(ops, bs, xs))[w0:w0 + 64]
         for k in range(2):
@@ -209,15 +223,6 @@ def batched_config4(count, log, one_at_a_time=True):
             % (t_seq[0], t_seq[1], count / t_seq[1]))
     else:   # kernel-trace runs: the batch legs only
         t_seq = [float("nan")] * 2
-    # setup overlapped with the solves, from a cold start: this leg's 512 new handles would not
-    # fit beside the first 512 and the cached arena (a setup that finds the device full hands
-    # the arena back, a device-wide wait of seconds), so both are freed first
-    for op in ops:
-        op.close()
-    del bs, xs
-    sg.batched_release()
-    torch.cuda.empty_cache()
-    pipe = batched_pipelined(insts, 128, threads, log)
     its = np.array([i["iters"] for i in infos])
     rel = np.array([i["relres_true"] for i in infos])
     out = {"workload": "%d seeded instances, N in {63,127,255}, kbar~U[5,30], sigma=0.1 kbar, s in 1..4, "
